@@ -1,0 +1,203 @@
+/*
+ * ras_pml.h -- C ABI of the MI355X RAS-PML GMRES hot path.
+ *
+ * What it computes (Xie, Gong, Graham, Spence, Zhang, "Massively parallel
+ * Schwarz methods for the high frequency Helmholtz equation"):
+ *
+ *   * the P1 finite-element discretisation of  Delta u + k^2 u = -f  on the
+ *     unit square surrounded by a Cartesian PML (Section 1, eq. (pml),
+ *     (weak)), written in its complex-symmetric form;
+ *   * the restricted additive Schwarz preconditioner with PML transmission
+ *     conditions  B^{-1} = sum_j R~_j^T A_j^{-1} R_j  (Section 2, discrete
+ *     RAS, eq. (local-ras-discrete) and (update1)), with impedance
+ *     (Section 3 (ii), eq. (impedance)) or Dirichlet local conditions;
+ *   * GMRES accelerated by that preconditioner (Section 4.1).
+ *
+ * Conventions shared by every entry point:
+ *
+ *   * Vectors are DEVICE pointers to interleaved complex128 values
+ *     (re, im, re, im, ...), one value per unknown.  Unknowns are the
+ *     interior mesh nodes (i, j), 1 <= i, j <= Nc-1, numbered
+ *     (j-1)(Nc-1) + (i-1) (x fastest), Nc = grid + 2 * global_pml.
+ *     A handle built by ras_pml_setup_batch concatenates the unknowns of
+ *     its problems in problem order.
+ *   * The caller owns every vector; the handle owns everything else
+ *     (operators, factors, workspaces).  Nothing is freed behind the
+ *     caller's back except by ras_pml_destroy.
+ *   * `stream` is a hipStream_t (NULL = the default stream).  Every entry
+ *     point enqueues its work on that stream and, unless stated otherwise,
+ *     returns without waiting for it.
+ *   * Every function returns RAS_OK (0) or a status below; no C++
+ *     exception crosses the ABI.  Parameter checks run on the host before
+ *     any device work.  ras_pml_last_error gives the message of the last
+ *     failure on a handle.
+ *   * A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef RAS_PML_H
+#define RAS_PML_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ras_status {
+    RAS_OK = 0,
+    RAS_EINVAL = 1,      /* invalid argument (message says which)              */
+    RAS_ENOMEM = 2,      /* device allocation failed                           */
+    RAS_EHIP = 3,        /* a HIP runtime call failed                          */
+    RAS_EZEROPIVOT = 4,  /* a local factorisation met a (near) zero pivot      */
+    RAS_ENONFINITE = 5,  /* a right-hand side or an iterate is not finite      */
+    RAS_ENOTCONV = 6,    /* GMRES stopped at maxit; x holds the last iterate   */
+    RAS_EBREAKDOWN = 7,  /* Arnoldi broke down without reaching the tolerance  */
+    RAS_ENOTSUP = 8      /* a size beyond what the kernels are built for       */
+};
+
+enum { RAS_BC_IMP = 0, RAS_BC_DRCH = 1 };          /* local boundary condition */
+enum { RAS_POU_LINEAR = 0, RAS_POU_BOOLEAN = 1 };  /* partition of unity       */
+enum { RAS_MIXED = 0, RAS_FP64 = 1 };              /* local factor precision   */
+enum { RAS_FLAG_TIMING = 1 };                      /* record HIP events        */
+
+typedef struct ras_pml_handle *ras_pml_t;
+
+typedef struct {
+    double sigma;      /* PML profile g(x) = sigma x^3 (Section 4 uses 10 k);
+                          <= 0 selects 10 k                                  */
+    int global_pml;    /* global PML thickness in cells; < 0 selects pml_width */
+    int bc;            /* RAS_BC_IMP (Section 3 (ii)) or RAS_BC_DRCH          */
+    int pou;           /* RAS_POU_LINEAR (Section 4) or RAS_POU_BOOLEAN       */
+    int precision;     /* RAS_MIXED: complex64 local factors and solves, all
+                          global vectors, SpMV and Krylov work complex128;
+                          RAS_FP64: complex128 everywhere                     */
+    int flags;         /* bitwise OR of RAS_FLAG_*                            */
+} ras_pml_opts;
+
+/* Number of int32 fields in one subdomain descriptor (ras_pml_plan). */
+#define RAS_DESC_INTS 24
+
+/* Fill *o with the defaults (sigma = 10 k, global PML = pml_width,
+ * impedance, linear PoU, mixed precision, no flags). */
+void ras_pml_default_opts(ras_pml_opts *o);
+
+/* Host-only planning: validates the parameters exactly as ras_pml_setup
+ * does and writes the subdomain table without touching any GPU.
+ *   k          wavenumber (> 0)
+ *   h          mesh width; grid[0] * h == 1 and grid[1] == grid[0] required
+ *   grid       cells of the interior box (0,1)^2 per side
+ *   subdomains number of subdomains per side (Section 2 Cartesian covering)
+ *   overlap    delta in cells (>= 0), pml_width kappa in cells (>= 0)
+ *   nsub       out: number of subdomains
+ *   desc       nullable; if given, nsub * RAS_DESC_INTS int32 (host memory):
+ *              [0] n_local  [1] n_fast  [2] W = n_fast + 2 (factor column
+ *              length)  [3] x_fast  [4] first unknown node i  [5] n_x
+ *              [6] first unknown node j  [7] n_y  [8] chunk p  [9] chunk q
+ *              [10..13] Omega_int x lo, x hi, y lo, y hi (node indices)
+ *              [14..17] Omega_j box x lo, x hi, y lo, y hi (node indices)
+ *              [18] flags: bit0/1 PML added below/above in x, bit2/3 in y,
+ *              bit4..7 impedance on the x-lo, x-hi, y-lo, y-hi side
+ *              [19] problem index  [20..23] reserved (0)
+ *   desc_cap   capacity of desc in subdomains (ignored when desc is NULL)
+ * Returns RAS_EINVAL (message via ras_pml_strerror) or RAS_ENOTSUP.        */
+int ras_pml_plan(double k, double h, const int grid[2], const int subdomains[2],
+                 int overlap, int pml_width, const ras_pml_opts *opts,
+                 int *nsub, int *desc, int desc_cap);
+
+/* Message of the last failed ras_pml_plan / setup call on this thread. */
+const char *ras_pml_plan_error(void);
+
+/* Build the operator A (Section 1), every local operator A_j with its PML
+ * (Section 2, local scaling function) and impedance or Dirichlet
+ * condition, and factorise every A_j once (A_j = L_j D_j L_j^T, no
+ * pivoting).  Arguments as for ras_pml_plan; the handle is written to *out.
+ * Synchronises `stream` before returning (the pivot check needs it).
+ * Errors: RAS_EINVAL, RAS_ENOTSUP, RAS_ENOMEM, RAS_EHIP, RAS_EZEROPIVOT
+ * (no handle is returned on error).                                         */
+int ras_pml_setup(double k, double h, const int grid[2], const int subdomains[2],
+                  int overlap, int pml_width, const ras_pml_opts *opts,
+                  void *stream, ras_pml_t *out);
+
+/* One handle for `nprob` independent problems (multi-problem batching).
+ * Arrays of length nprob; every problem shares `opts`.  The unknowns of
+ * problem p start at offset ras_pml_problem_offset(H, p).                 */
+int ras_pml_setup_batch(int nprob, const double *k, const double *h, const int *grid,
+                        const int *subdomains, const int *overlap, const int *pml_width,
+                        const ras_pml_opts *opts, void *stream, ras_pml_t *out);
+
+void ras_pml_destroy(ras_pml_t H);
+
+/* Sizes. */
+int ras_pml_num_dofs(ras_pml_t H, long long *n);        /* all problems */
+int ras_pml_num_problems(ras_pml_t H, int *nprob);
+int ras_pml_problem_offset(ras_pml_t H, int p, long long *off, long long *n);
+int ras_pml_num_subdomains(ras_pml_t H, int *nsub);
+int ras_pml_num_local(ras_pml_t H, long long *nloc);    /* sum of n_local */
+int ras_pml_subdomain_desc(ras_pml_t H, int *desc, int desc_cap);  /* host */
+
+/* b = M f : the P1 mass matrix (unweighted) applied to nodal source values
+ * f at the unknowns (the source is taken as zero on the boundary of Omega).
+ * Right-hand side of the weak form (Section 1, eq. (weak)).               */
+int ras_pml_rhs(ras_pml_t H, const void *f, void *b, void *stream);
+
+/* y = A x, the complex-symmetric 7-point P1 operator (Section 1). */
+int ras_pml_spmv(ras_pml_t H, const void *x, void *y, void *stream);
+
+/* z = B^{-1} v = sum_j R~_j^T A_j^{-1} R_j v (Section 2).  v and z must not
+ * alias.  Deterministic: the same input gives bitwise the same output.     */
+int ras_pml_apply(ras_pml_t H, const void *v, void *z, void *stream);
+
+/* Local solutions x_j = A_j^{-1} R_j v of every subdomain, back to back in
+ * subdomain order (n_local each), complex128, before the PoU-weighted sum. */
+int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream);
+
+/* Flexible GMRES(restart), right preconditioned by B^{-1} (Section 4.1),
+ * modified Gram-Schmidt, complex Givens rotations, all Krylov arithmetic in
+ * complex128.  x holds x0 on entry and the iterate on return.  Stops when
+ * the true residual ||b - A x|| <= rtol ||b|| (checked at every restart and
+ * at the end) or after maxit Arnoldi steps.  iters/relres (nullable) get
+ * the step count and the final true relative residual; hist (nullable,
+ * maxit+1 doubles, host) gets the residual estimate after every step.
+ * For a batch handle every problem is solved independently with its own
+ * stopping test; iters/relres then describe the slowest problem and
+ * ras_pml_batch_result gives each one.  Synchronises `stream`.
+ * Errors: RAS_EINVAL, RAS_ENONFINITE, RAS_ENOTCONV, RAS_EBREAKDOWN,
+ * RAS_ENOMEM, RAS_EHIP.                                                    */
+int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, int maxit,
+                int *iters, double *relres, double *hist, void *stream);
+
+/* Per-problem outcome of the last gmres_solve on a batch handle. */
+int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged);
+
+/* Inspection (tests).  All outputs are HOST memory, complex128.
+ *   export_stencil: 4 * n_dofs values: the C, E, N and NE couplings of every
+ *     unknown (E = to (i+1,j), N = to (i,j+1), NE = to (i+1,j+1); zero where
+ *     the neighbour is not an unknown).
+ *   export_local: 4 * n_local values for subdomain j in the local ordering:
+ *     diagonal, fast-axis (+1), slow-axis (+n_fast), diagonal (+n_fast+1).
+ *   export_factor: (n_pad * W) L entries of subdomain j, column c at
+ *     c * W, row r at position r mod W (position c mod W holds 0), then
+ *     n_pad values of D^{-1}; n_pad = n_local rounded up to 64.            */
+int ras_pml_export_stencil(ras_pml_t H, void *host_out);
+int ras_pml_export_local(ras_pml_t H, int j, void *host_out);
+int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_values);
+
+/* Timing statistics recorded with RAS_FLAG_TIMING (milliseconds, summed
+ * over launches since setup or the last reset).  Synchronises.            */
+typedef struct {
+    long long n_solve;     double solve_ms;    /* batched band solves         */
+    long long n_sum;       double sum_ms;      /* PoU-weighted sums           */
+    long long n_spmv;      double spmv_ms;
+    long long n_mgs;       double mgs_ms;      /* projections + norms         */
+    long long n_givens;    double givens_ms;
+    double setup_assemble_ms, setup_factor_ms;
+    double solve_bytes;    /* algorithmic bytes of one band-solve launch      */
+    double factor_bytes;   /* bytes of all stored factors                     */
+} ras_pml_stats;
+int ras_pml_get_stats(ras_pml_t H, ras_pml_stats *out);
+int ras_pml_reset_stats(ras_pml_t H);
+
+const char *ras_pml_strerror(int status);
+const char *ras_pml_last_error(ras_pml_t H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RAS_PML_H */

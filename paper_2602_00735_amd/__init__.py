@@ -1,0 +1,338 @@
+"""RAS-PML GMRES hot path for MI355X: Python binding of libras_pml.so.
+
+Thin ctypes marshalling over the C ABI in include/ras_pml.h: the functions
+here have the ABI's names and pass device pointers of torch tensors
+(complex128 on the GPU) and the current HIP stream.  Every step of the
+method runs in the HIP library; there is no Python or CPU fallback, and
+importing a function that needs the library raises if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libras_pml.so")
+
+RAS_OK, RAS_EINVAL, RAS_ENOMEM, RAS_EHIP, RAS_EZEROPIVOT = 0, 1, 2, 3, 4
+RAS_ENONFINITE, RAS_ENOTCONV, RAS_EBREAKDOWN, RAS_ENOTSUP = 5, 6, 7, 8
+RAS_BC_IMP, RAS_BC_DRCH = 0, 1
+RAS_POU_LINEAR, RAS_POU_BOOLEAN = 0, 1
+RAS_MIXED, RAS_FP64 = 0, 1
+RAS_FLAG_TIMING = 1
+RAS_DESC_INTS = 24
+
+
+class RasPmlError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (status %d): %s" % (_STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+_STATUS = {0: "RAS_OK", 1: "RAS_EINVAL", 2: "RAS_ENOMEM", 3: "RAS_EHIP", 4: "RAS_EZEROPIVOT",
+           5: "RAS_ENONFINITE", 6: "RAS_ENOTCONV", 7: "RAS_EBREAKDOWN", 8: "RAS_ENOTSUP"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("global_pml", ctypes.c_int), ("bc", ctypes.c_int),
+                ("pou", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_solve", ctypes.c_longlong), ("solve_ms", ctypes.c_double),
+                ("n_sum", ctypes.c_longlong), ("sum_ms", ctypes.c_double),
+                ("n_spmv", ctypes.c_longlong), ("spmv_ms", ctypes.c_double),
+                ("n_mgs", ctypes.c_longlong), ("mgs_ms", ctypes.c_double),
+                ("n_givens", ctypes.c_longlong), ("givens_ms", ctypes.c_double),
+                ("setup_assemble_ms", ctypes.c_double), ("setup_factor_ms", ctypes.c_double),
+                ("solve_bytes", ctypes.c_double), ("factor_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# (name, restype, argtypes) of every exported symbol
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_LL = ctypes.c_longlong
+_IP = ctypes.POINTER(ctypes.c_int)
+_DP = ctypes.POINTER(ctypes.c_double)
+_LLP = ctypes.POINTER(ctypes.c_longlong)
+SYMBOLS = [
+    ("ras_pml_default_opts", None, [ctypes.POINTER(Opts)]),
+    ("ras_pml_plan", _I, [_D, _D, _IP, _IP, _I, _I, ctypes.POINTER(Opts), _IP, _IP, _I]),
+    ("ras_pml_plan_error", ctypes.c_char_p, []),
+    ("ras_pml_setup", _I, [_D, _D, _IP, _IP, _I, _I, ctypes.POINTER(Opts), _P,
+                           ctypes.POINTER(_P)]),
+    ("ras_pml_setup_batch", _I, [_I, _DP, _DP, _IP, _IP, _IP, _IP, ctypes.POINTER(Opts), _P,
+                                 ctypes.POINTER(_P)]),
+    ("ras_pml_destroy", None, [_P]),
+    ("ras_pml_num_dofs", _I, [_P, _LLP]),
+    ("ras_pml_num_problems", _I, [_P, _IP]),
+    ("ras_pml_problem_offset", _I, [_P, _I, _LLP, _LLP]),
+    ("ras_pml_num_subdomains", _I, [_P, _IP]),
+    ("ras_pml_num_local", _I, [_P, _LLP]),
+    ("ras_pml_subdomain_desc", _I, [_P, _IP, _I]),
+    ("ras_pml_rhs", _I, [_P, _P, _P, _P]),
+    ("ras_pml_spmv", _I, [_P, _P, _P, _P]),
+    ("ras_pml_apply", _I, [_P, _P, _P, _P]),
+    ("ras_pml_local_solve", _I, [_P, _P, _P, _P]),
+    ("gmres_solve", _I, [_P, _P, _P, _D, _I, _I, _IP, _DP, _DP, _P]),
+    ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
+    ("ras_pml_export_stencil", _I, [_P, _P]),
+    ("ras_pml_export_local", _I, [_P, _I, _P]),
+    ("ras_pml_export_factor", _I, [_P, _I, _P, _LL]),
+    ("ras_pml_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
+    ("ras_pml_reset_stats", _I, [_P]),
+    ("ras_pml_strerror", ctypes.c_char_p, [_I]),
+    ("ras_pml_last_error", ctypes.c_char_p, [_P]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libras_pml.so; raise (never fall back) if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libras_pml.so is not built; run "
+                              "`python -m paper_2602_00735_amd.build` (HIP for gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SYMBOLS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().ras_pml_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _i2(a):
+    return (ctypes.c_int * 2)(int(a[0]), int(a[1]))
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_vec(t, n, name):
+    import torch
+    if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous complex128 CUDA tensor of %d values" % (name, n))
+
+
+def ras_pml_plan(k, h, grid, subdomains, overlap, pml_width, opts=None):
+    """Host-only planning; returns the descriptor table as a list of lists."""
+    L = lib()
+    o = opts if opts is not None else default_opts()
+    ns = ctypes.c_int(0)
+    rc = L.ras_pml_plan(k, h, _i2(grid), _i2(subdomains), overlap, pml_width, ctypes.byref(o),
+                        ctypes.byref(ns), None, 0)
+    if rc != RAS_OK:
+        raise RasPmlError(rc, L.ras_pml_plan_error().decode())
+    buf = (ctypes.c_int * (ns.value * RAS_DESC_INTS))()
+    rc = L.ras_pml_plan(k, h, _i2(grid), _i2(subdomains), overlap, pml_width, ctypes.byref(o),
+                        ctypes.byref(ns), buf, ns.value)
+    if rc != RAS_OK:
+        raise RasPmlError(rc, L.ras_pml_plan_error().decode())
+    return [list(buf[i * RAS_DESC_INTS:(i + 1) * RAS_DESC_INTS]) for i in range(ns.value)]
+
+
+class Handle:
+    """Owns a ras_pml_t; destroyed with the object or by ras_pml_destroy."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+        L = lib()
+        n = ctypes.c_longlong(0)
+        L.ras_pml_num_dofs(self.ptr, ctypes.byref(n))
+        self.ndof = n.value
+        ns = ctypes.c_int(0)
+        L.ras_pml_num_subdomains(self.ptr, ctypes.byref(ns))
+        self.nsub = ns.value
+        nl = ctypes.c_longlong(0)
+        L.ras_pml_num_local(self.ptr, ctypes.byref(nl))
+        self.nloc = nl.value
+        npb = ctypes.c_int(0)
+        L.ras_pml_num_problems(self.ptr, ctypes.byref(npb))
+        self.nprob = npb.value
+
+    def _raise(self, rc):
+        raise RasPmlError(rc, lib().ras_pml_last_error(self.ptr).decode())
+
+    def close(self):
+        if self.ptr:
+            lib().ras_pml_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def problem_offset(self, p):
+        off, n = ctypes.c_longlong(0), ctypes.c_longlong(0)
+        rc = lib().ras_pml_problem_offset(self.ptr, p, ctypes.byref(off), ctypes.byref(n))
+        if rc:
+            self._raise(rc)
+        return off.value, n.value
+
+    def desc(self):
+        buf = (ctypes.c_int * (self.nsub * RAS_DESC_INTS))()
+        rc = lib().ras_pml_subdomain_desc(self.ptr, buf, self.nsub)
+        if rc:
+            self._raise(rc)
+        return [list(buf[i * RAS_DESC_INTS:(i + 1) * RAS_DESC_INTS]) for i in range(self.nsub)]
+
+
+def ras_pml_setup(k, h, grid, subdomains, overlap, pml_width, opts=None, stream=None) -> Handle:
+    L = lib()
+    o = opts if opts is not None else default_opts()
+    out = ctypes.c_void_p()
+    rc = L.ras_pml_setup(k, h, _i2(grid), _i2(subdomains), overlap, pml_width, ctypes.byref(o),
+                         _stream(stream), ctypes.byref(out))
+    if rc != RAS_OK:
+        raise RasPmlError(rc, L.ras_pml_plan_error().decode())
+    return Handle(out)
+
+
+def ras_pml_setup_batch(ks, hs, grids, subdomains, overlaps, pml_widths, opts=None,
+                        stream=None) -> Handle:
+    L = lib()
+    n = len(ks)
+    o = opts if opts is not None else default_opts()
+    D = ctypes.c_double * n
+    I = ctypes.c_int * n
+    I2 = ctypes.c_int * (2 * n)
+    g = [int(x) for gg in grids for x in gg]
+    s = [int(x) for ss in subdomains for x in ss]
+    out = ctypes.c_void_p()
+    rc = L.ras_pml_setup_batch(n, D(*ks), D(*hs), I2(*g), I2(*s), I(*overlaps), I(*pml_widths),
+                               ctypes.byref(o), _stream(stream), ctypes.byref(out))
+    if rc != RAS_OK:
+        raise RasPmlError(rc, L.ras_pml_plan_error().decode())
+    return Handle(out)
+
+
+def ras_pml_destroy(H: Handle):
+    H.close()
+
+
+def ras_pml_rhs(H: Handle, f, b, stream=None):
+    _check_vec(f, H.ndof, "f")
+    _check_vec(b, H.ndof, "b")
+    rc = lib().ras_pml_rhs(H.ptr, _ptr(f), _ptr(b), _stream(stream))
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_spmv(H: Handle, x, y, stream=None):
+    _check_vec(x, H.ndof, "x")
+    _check_vec(y, H.ndof, "y")
+    rc = lib().ras_pml_spmv(H.ptr, _ptr(x), _ptr(y), _stream(stream))
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_apply(H: Handle, v, z, stream=None):
+    _check_vec(v, H.ndof, "v")
+    _check_vec(z, H.ndof, "z")
+    rc = lib().ras_pml_apply(H.ptr, _ptr(v), _ptr(z), _stream(stream))
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_local_solve(H: Handle, v, xloc, stream=None):
+    _check_vec(v, H.ndof, "v")
+    _check_vec(xloc, H.nloc, "xloc")
+    rc = lib().ras_pml_local_solve(H.ptr, _ptr(v), _ptr(xloc), _stream(stream))
+    if rc:
+        H._raise(rc)
+
+
+def gmres_solve(H: Handle, b, x, rtol=1e-6, restart=100, maxit=500, stream=None, check=True):
+    """Returns (status, iters, relres, hist).  Raises on errors other than
+    RAS_ENOTCONV / RAS_EBREAKDOWN unless check=False."""
+    import numpy as np
+    _check_vec(b, H.ndof, "b")
+    _check_vec(x, H.ndof, "x")
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    rc = lib().gmres_solve(H.ptr, _ptr(b), _ptr(x), rtol, restart, maxit, ctypes.byref(it),
+                           ctypes.byref(rr), hist.ctypes.data_as(_DP), _stream(stream))
+    if check and rc not in (RAS_OK, RAS_ENOTCONV, RAS_EBREAKDOWN):
+        H._raise(rc)
+    return rc, it.value, rr.value, hist[:it.value + 1]
+
+
+def ras_pml_batch_result(H: Handle, p):
+    it, rr, cv = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_int(0)
+    rc = lib().ras_pml_batch_result(H.ptr, p, ctypes.byref(it), ctypes.byref(rr), ctypes.byref(cv))
+    if rc:
+        H._raise(rc)
+    return it.value, rr.value, bool(cv.value)
+
+
+def ras_pml_export_stencil(H: Handle):
+    import numpy as np
+    out = np.zeros(4 * H.ndof, dtype=np.complex128)
+    rc = lib().ras_pml_export_stencil(H.ptr, out.ctypes.data_as(_P))
+    if rc:
+        H._raise(rc)
+    return out.reshape(4, H.ndof)
+
+
+def ras_pml_export_local(H: Handle, j, n_local):
+    import numpy as np
+    out = np.zeros(4 * n_local, dtype=np.complex128)
+    rc = lib().ras_pml_export_local(H.ptr, j, out.ctypes.data_as(_P))
+    if rc:
+        H._raise(rc)
+    return out.reshape(n_local, 4)
+
+
+def ras_pml_export_factor(H: Handle, j, npad, W):
+    """Returns (L columns (npad, W), D^{-1} (npad,)) in slot order."""
+    import numpy as np
+    cnt = npad * (W + 1)
+    out = np.zeros(cnt, dtype=np.complex128)
+    rc = lib().ras_pml_export_factor(H.ptr, j, out.ctypes.data_as(_P), cnt)
+    if rc:
+        H._raise(rc)
+    return out[:npad * W].reshape(npad, W), out[npad * W:]
+
+
+def ras_pml_get_stats(H: Handle) -> dict:
+    s = Stats()
+    rc = lib().ras_pml_get_stats(H.ptr, ctypes.byref(s))
+    if rc:
+        H._raise(rc)
+    return s.as_dict()
+
+
+def ras_pml_reset_stats(H: Handle):
+    rc = lib().ras_pml_reset_stats(H.ptr)
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_strerror(status: int) -> str:
+    return lib().ras_pml_strerror(status).decode()

@@ -1,0 +1,870 @@
+// C ABI of the RAS-PML GMRES hot path (declared in include/ras_pml.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "internal.h"
+
+namespace raspml {
+
+// kernels (k_*.hip)
+void launch_global_stencil(const DevProb *, int, long long, double2 *, long long, hipStream_t);
+void launch_local_stencil(const DevProb *, const DevSub *, int, int, double2 *, hipStream_t);
+void launch_rhs(const DevProb *, int, long long, const double2 *, double2 *, hipStream_t);
+void launch_band_ldlt(bool, int, const DevSub *, const int *, int, const double2 *, void *, int *,
+                      hipStream_t);
+void launch_band_solve(bool, int, const DevProb *, const DevSub *, const int *, int, const int *,
+                       const double2 *, const void *, void *, void *, hipStream_t);
+void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
+                    const int *, const int *, const double *, const void *, double2 *, hipStream_t);
+void launch_export_local(bool, const DevSub *, int, int, const void *, double2 *, hipStream_t);
+void launch_spmv(const DevProb *, int, long long, const int *, const double2 *, long long,
+                 const double2 *, const double2 *, double2 *, hipStream_t);
+void launch_mgs(const DevProb *, int, const KState *, double2 *, const double2 *, long long, int,
+                int, int, int, double2 *, double2 *, unsigned int *, hipStream_t);
+void launch_reduce(const DevProb *, int, const int *, const double2 *, const double2 *, int,
+                   double2 *, double2 *, unsigned int *, hipStream_t);
+void launch_normalize(const DevProb *, int, long long, const KState *, double2 *, int, int,
+                      const double2 *, hipStream_t);
+void launch_start_cycle(const DevProb *, int, long long, const KState *, const double2 *,
+                        double2 *, hipStream_t);
+void launch_givens(KState *, int, int, int, double2 *, double *, double2 *, double2 *, double *,
+                   hipStream_t);
+void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, double2 *,
+                    hipStream_t);
+void launch_update_x(const DevProb *, int, long long, const KState *, const int *, int,
+                     const double2 *, long long, const double2 *, double2 *, hipStream_t);
+
+constexpr int kRedBlocksHost = 512;
+
+enum Cat { C_SOLVE = 0, C_SUM, C_SPMV, C_MGS, C_GIVENS, C_NCAT };
+
+struct Status {
+    int code = RAS_OK;
+    std::string msg;
+};
+
+}  // namespace raspml
+
+using namespace raspml;
+
+struct ras_pml_handle {
+    std::vector<PlanProblem> plans;
+    std::vector<DevProb> hprobs;
+    std::vector<DevSub> hsubs;
+    std::vector<int> order;
+    int nprob = 0, nsub = 0, maxW = 0, max_n = 0;
+    long long ntot = 0, nloc = 0, nvec = 0, max_ndof = 0;
+    bool fp64 = false;
+    int flags = 0;
+    size_t csize = 8;          // bytes of one local complex value
+    size_t fac_elems = 0;
+
+    DevProb *d_probs = nullptr;
+    DevSub *d_subs = nullptr;
+    int *d_order = nullptr;
+    int *d_pcnt = nullptr, *d_pchunk = nullptr;
+    double *d_pw = nullptr;
+    double2 *d_coef = nullptr;
+    double2 *d_lst = nullptr;
+    void *d_F = nullptr, *d_ybuf = nullptr, *d_xout = nullptr;
+    int *d_status = nullptr;
+
+    // Krylov workspace
+    int m_alloc = 0;
+    double2 *d_V = nullptr, *d_Z = nullptr, *d_r = nullptr;
+    double2 *d_H = nullptr, *d_g = nullptr, *d_sn = nullptr, *d_y = nullptr;
+    double *d_cs = nullptr, *d_hist = nullptr;
+    KState *d_ks = nullptr;
+    int *d_active = nullptr;
+    double2 *d_partials = nullptr, *d_redout = nullptr;
+    unsigned int *d_counters = nullptr;
+    KState *h_ks = nullptr;        // pinned
+    double2 *h_red = nullptr;      // pinned
+    std::vector<int> res_iters;
+    std::vector<double> res_relres;
+    std::vector<int> res_conv;
+
+    std::string last_error;
+
+    struct EvPair {
+        hipEvent_t a, b;
+    };
+    std::vector<EvPair> ev[C_NCAT];
+    std::vector<EvPair> pool;
+    ras_pml_stats stats{};
+
+    ~ras_pml_handle();
+};
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+#define HCHK(H, call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            (H)->last_error = std::string(#call) + ": " + hipGetErrorString(e_);      \
+            return (e_ == hipErrorOutOfMemory) ? RAS_ENOMEM : RAS_EHIP;               \
+        }                                                                             \
+    } while (0)
+
+template <typename P>
+int dalloc(ras_pml_handle *H, P **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    if (e != hipSuccess) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed: ", bytes);
+        H->last_error = std::string(buf) + hipGetErrorString(e);
+        *p = nullptr;
+        return e == hipErrorOutOfMemory ? RAS_ENOMEM : RAS_EHIP;
+    }
+    return RAS_OK;
+}
+
+#define RCHK(x)                   \
+    do {                          \
+        int r_ = (x);             \
+        if (r_ != RAS_OK) return r_; \
+    } while (0)
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+ras_pml_handle::EvPair take_pair(ras_pml_handle *H) {
+    if (!H->pool.empty()) {
+        auto p = H->pool.back();
+        H->pool.pop_back();
+        return p;
+    }
+    ras_pml_handle::EvPair p{};
+    (void)hipEventCreate(&p.a);
+    (void)hipEventCreate(&p.b);
+    return p;
+}
+
+struct Timer {
+    ras_pml_handle *H;
+    int cat;
+    hipStream_t s;
+    bool on;
+    ras_pml_handle::EvPair p{};
+    Timer(ras_pml_handle *H_, int cat_, hipStream_t s_)
+        : H(H_), cat(cat_), s(s_), on((H_->flags & RAS_FLAG_TIMING) != 0) {
+        if (on) {
+            p = take_pair(H);
+            (void)hipEventRecord(p.a, s);
+        }
+    }
+    ~Timer() {
+        if (on) {
+            (void)hipEventRecord(p.b, s);
+            H->ev[cat].push_back(p);
+        }
+    }
+};
+
+void collect_events(ras_pml_handle *H) {
+    long long *cnt[C_NCAT] = {&H->stats.n_solve, &H->stats.n_sum, &H->stats.n_spmv, &H->stats.n_mgs,
+                              &H->stats.n_givens};
+    double *ms[C_NCAT] = {&H->stats.solve_ms, &H->stats.sum_ms, &H->stats.spmv_ms, &H->stats.mgs_ms,
+                          &H->stats.givens_ms};
+    for (int c = 0; c < C_NCAT; ++c) {
+        for (auto &p : H->ev[c]) {
+            (void)hipEventSynchronize(p.b);
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+                *ms[c] += t;
+                *cnt[c] += 1;
+            }
+            H->pool.push_back(p);
+        }
+        H->ev[c].clear();
+    }
+}
+
+}  // namespace
+
+ras_pml_handle::~ras_pml_handle() {
+    void *ptrs[] = {d_probs, d_subs,  d_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
+                    d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
+                    d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
+                    d_redout, d_counters};
+    for (void *p : ptrs) dfree(p);
+    if (h_ks) (void)hipHostFree(h_ks);
+    if (h_red) (void)hipHostFree(h_red);
+    for (int c = 0; c < C_NCAT; ++c)
+        for (auto &p : ev[c]) pool.push_back(p);
+    for (auto &p : pool) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+}
+
+namespace {
+
+int build(ras_pml_handle *H, hipStream_t st) {
+    // ---- concatenate problems
+    H->nprob = static_cast<int>(H->plans.size());
+    long long dof = 0, vec = 0, loc = 0;
+    size_t fac = 0;
+    int pou_off = 0;
+    H->hprobs.clear();
+    H->hsubs.clear();
+    std::vector<int> pcnt, pchunk;
+    std::vector<double> pw;
+    H->maxW = 0;
+    H->max_n = 0;
+    H->max_ndof = 0;
+    for (int p = 0; p < H->nprob; ++p) {
+        PlanProblem &pl = H->plans[p];
+        DevProb P{};
+        P.k = pl.k;
+        P.h = pl.h;
+        P.sigma = pl.sigma;
+        P.G = pl.G;
+        P.Nc = pl.Nc;
+        P.n1 = pl.Nc - 1;
+        P.Px = pl.Px;
+        P.Py = pl.Py;
+        P.sub_first = static_cast<int>(H->hsubs.size());
+        P.dof_off = dof;
+        P.ndof = pl.ndof;
+        for (int axis = 0; axis < 2; ++axis) {
+            (axis == 0 ? P.pou_x : P.pou_y) = pou_off;
+            pcnt.insert(pcnt.end(), pl.pou_cnt[axis].begin(), pl.pou_cnt[axis].end());
+            pchunk.insert(pchunk.end(), pl.pou_chunk[axis].begin(), pl.pou_chunk[axis].end());
+            pw.insert(pw.end(), pl.pou_w[axis].begin(), pl.pou_w[axis].end());
+            pou_off += pl.Nc + 1;
+        }
+        for (DevSub s : pl.subs) {
+            s.prob = p;
+            s.fac_off = static_cast<long long>(fac);
+            s.vec_off = vec;
+            s.loc_off = loc;
+            fac += static_cast<size_t>(s.npad) * (s.W + 1);
+            vec += s.npad;
+            loc += s.n;
+            H->maxW = std::max(H->maxW, s.W);
+            H->max_n = std::max(H->max_n, s.n);
+            H->hsubs.push_back(s);
+        }
+        dof += pl.ndof;
+        H->max_ndof = std::max(H->max_ndof, pl.ndof);
+        H->hprobs.push_back(P);
+    }
+    if (dof > (1LL << 31) - 1 || vec > (1LL << 31) - 1) {
+        H->last_error = "problem too large for 32-bit unknown indices";
+        return RAS_ENOTSUP;
+    }
+    H->nsub = static_cast<int>(H->hsubs.size());
+    H->ntot = dof;
+    H->nvec = vec;
+    H->nloc = loc;
+    H->fac_elems = fac;
+    H->csize = H->fp64 ? 16 : 8;
+    // largest subdomains first (longest processing time first)
+    H->order.resize(H->nsub);
+    std::iota(H->order.begin(), H->order.end(), 0);
+    std::stable_sort(H->order.begin(), H->order.end(),
+                     [&](int a, int b) { return H->hsubs[a].n > H->hsubs[b].n; });
+
+    // algorithmic bytes of one band-solve launch: L read by both sweeps,
+    // D^{-1}, the gathered right-hand side (complex128), the forward result
+    // written and read back, the local solution written.
+    double sb = 0.0, fb = 0.0;
+    for (const DevSub &s : H->hsubs) {
+        sb += (2.0 * s.npad * s.W + s.npad + 3.0 * s.npad) * H->csize + 16.0 * s.n;
+        fb += static_cast<double>(s.npad) * (s.W + 1) * H->csize;
+    }
+    H->stats.solve_bytes = sb;
+    H->stats.factor_bytes = fb;
+
+    // ---- device memory
+    RCHK(dalloc(H, &H->d_probs, sizeof(DevProb) * H->nprob));
+    RCHK(dalloc(H, &H->d_subs, sizeof(DevSub) * H->nsub));
+    RCHK(dalloc(H, &H->d_order, sizeof(int) * H->nsub));
+    RCHK(dalloc(H, &H->d_pcnt, sizeof(int) * pcnt.size()));
+    RCHK(dalloc(H, &H->d_pchunk, sizeof(int) * pchunk.size()));
+    RCHK(dalloc(H, &H->d_pw, sizeof(double) * pw.size()));
+    RCHK(dalloc(H, &H->d_coef, sizeof(double2) * 4 * H->ntot));
+    RCHK(dalloc(H, &H->d_lst, sizeof(double2) * 4 * H->nloc));
+    RCHK(dalloc(H, &H->d_F, H->csize * fac));
+    RCHK(dalloc(H, &H->d_ybuf, H->csize * H->nvec));
+    RCHK(dalloc(H, &H->d_xout, H->csize * H->nvec));
+    RCHK(dalloc(H, &H->d_status, sizeof(int) * H->nsub));
+    HCHK(H, hipMemcpyAsync(H->d_probs, H->hprobs.data(), sizeof(DevProb) * H->nprob,
+                           hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_subs, H->hsubs.data(), sizeof(DevSub) * H->nsub,
+                           hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_order, H->order.data(), sizeof(int) * H->nsub,
+                           hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_pcnt, pcnt.data(), sizeof(int) * pcnt.size(),
+                           hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_pchunk, pchunk.data(), sizeof(int) * pchunk.size(),
+                           hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_pw, pw.data(), sizeof(double) * pw.size(),
+                           hipMemcpyHostToDevice, st));
+
+    hipEvent_t e0{}, e1{}, e2{};
+    const bool timing = (H->flags & RAS_FLAG_TIMING) != 0;
+    if (timing) {
+        HCHK(H, hipEventCreate(&e0));
+        HCHK(H, hipEventCreate(&e1));
+        HCHK(H, hipEventCreate(&e2));
+        HCHK(H, hipEventRecord(e0, st));
+    }
+    launch_global_stencil(H->d_probs, H->nprob, H->max_ndof, H->d_coef, H->ntot, st);
+    HCHK(H, hipGetLastError());
+    launch_local_stencil(H->d_probs, H->d_subs, H->nsub, H->max_n, H->d_lst, st);
+    HCHK(H, hipGetLastError());
+    if (timing) HCHK(H, hipEventRecord(e1, st));
+    launch_band_ldlt(H->fp64, H->maxW, H->d_subs, H->d_order, H->nsub, H->d_lst, H->d_F,
+                     H->d_status, st);
+    HCHK(H, hipGetLastError());
+    if (timing) HCHK(H, hipEventRecord(e2, st));
+    std::vector<int> status(H->nsub);
+    HCHK(H, hipMemcpyAsync(status.data(), H->d_status, sizeof(int) * H->nsub,
+                           hipMemcpyDeviceToHost, st));
+    HCHK(H, hipStreamSynchronize(st));
+    if (timing) {
+        float a = 0, b = 0;
+        (void)hipEventElapsedTime(&a, e0, e1);
+        (void)hipEventElapsedTime(&b, e1, e2);
+        H->stats.setup_assemble_ms = a;
+        H->stats.setup_factor_ms = b;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipEventDestroy(e2);
+    }
+    for (int s = 0; s < H->nsub; ++s) {
+        if (status[s] >= 0) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "zero pivot in subdomain %d (problem %d) at column %d",
+                          s, H->hsubs[s].prob, status[s]);
+            H->last_error = buf;
+            return RAS_EZEROPIVOT;
+        }
+    }
+    return RAS_OK;
+}
+
+int ensure_krylov(ras_pml_handle *H, int m) {
+    if (H->m_alloc >= m) return RAS_OK;
+    void *ptrs[] = {H->d_V, H->d_Z, H->d_r, H->d_H, H->d_g, H->d_sn, H->d_y, H->d_cs, H->d_hist};
+    for (void *p : ptrs) dfree(p);
+    H->d_V = H->d_Z = H->d_r = H->d_H = H->d_g = H->d_sn = H->d_y = nullptr;
+    H->d_cs = H->d_hist = nullptr;
+    H->m_alloc = 0;
+    const long long n = H->ntot;
+    const int P = H->nprob;
+    RCHK(dalloc(H, &H->d_V, sizeof(double2) * n * (m + 1)));
+    RCHK(dalloc(H, &H->d_Z, sizeof(double2) * n * m));
+    RCHK(dalloc(H, &H->d_r, sizeof(double2) * n));
+    RCHK(dalloc(H, &H->d_H, sizeof(double2) * static_cast<size_t>(P) * (m + 1) * m));
+    RCHK(dalloc(H, &H->d_g, sizeof(double2) * static_cast<size_t>(P) * (m + 1)));
+    RCHK(dalloc(H, &H->d_sn, sizeof(double2) * static_cast<size_t>(P) * m));
+    RCHK(dalloc(H, &H->d_y, sizeof(double2) * static_cast<size_t>(P) * m));
+    RCHK(dalloc(H, &H->d_cs, sizeof(double) * static_cast<size_t>(P) * m));
+    RCHK(dalloc(H, &H->d_hist, sizeof(double) * static_cast<size_t>(P)));
+    if (!H->d_ks) {
+        RCHK(dalloc(H, &H->d_ks, sizeof(KState) * P));
+        RCHK(dalloc(H, &H->d_active, sizeof(int) * P));
+        RCHK(dalloc(H, &H->d_partials, sizeof(double2) * static_cast<size_t>(P) * kRedBlocksHost));
+        RCHK(dalloc(H, &H->d_redout, sizeof(double2) * P));
+        RCHK(dalloc(H, &H->d_counters, sizeof(unsigned int) * P));
+        HCHK(H, hipMemset(H->d_counters, 0, sizeof(unsigned int) * P));
+        HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_ks), sizeof(KState) * P));
+        HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_red), sizeof(double2) * P));
+    }
+    H->m_alloc = m;
+    return RAS_OK;
+}
+
+int check_handle(ras_pml_handle *H) { return H ? RAS_OK : RAS_EINVAL; }
+
+int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st) {
+    {
+        Timer t(H, C_SOLVE, st);
+        launch_band_solve(H->fp64, H->maxW, H->d_probs, H->d_subs, H->d_order, H->nsub, active, v,
+                          H->d_F, H->d_ybuf, H->d_xout, st);
+    }
+    HCHK(H, hipGetLastError());
+    {
+        Timer t(H, C_SUM, st);
+        launch_pou_sum(H->fp64, H->d_probs, H->nprob, H->max_ndof, H->d_subs, active, H->d_pcnt,
+                       H->d_pchunk, H->d_pw, H->d_xout, z, st);
+    }
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+// Deterministic per-problem reduction into H->h_red (synchronises).
+int reduce_sync(ras_pml_handle *H, const double2 *a, const double2 *b, int mode, hipStream_t st) {
+    launch_reduce(H->d_probs, H->nprob, nullptr, a, b, mode, H->d_redout, H->d_partials,
+                  H->d_counters, st);
+    HCHK(H, hipGetLastError());
+    HCHK(H, hipMemcpyAsync(H->h_red, H->d_redout, sizeof(double2) * H->nprob,
+                           hipMemcpyDeviceToHost, st));
+    HCHK(H, hipStreamSynchronize(st));
+    return RAS_OK;
+}
+
+int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int m, int maxit,
+               int *iters, double *relres, double *hist, hipStream_t st) {
+    const int P = H->nprob;
+    RCHK(ensure_krylov(H, m));
+    H->res_iters.assign(P, 0);
+    H->res_relres.assign(P, 0.0);
+    H->res_conv.assign(P, 0);
+    std::vector<double> bnorm(P), beta(P);
+    std::vector<int> need(P, 0);
+    RCHK(reduce_sync(H, b, nullptr, 0, st));
+    for (int p = 0; p < P; ++p) {
+        bnorm[p] = std::sqrt(H->h_red[p].x);
+        if (!std::isfinite(bnorm[p])) {
+            H->last_error = "right-hand side is not finite";
+            return RAS_ENONFINITE;
+        }
+        if (bnorm[p] == 0.0) {
+            const DevProb &D = H->hprobs[p];
+            HCHK(H, hipMemsetAsync(x + D.dof_off, 0, sizeof(double2) * D.ndof, st));
+        }
+    }
+    launch_spmv(H->d_probs, P, H->max_ndof, nullptr, H->d_coef, H->ntot, x, b, H->d_r, st);
+    HCHK(H, hipGetLastError());
+    RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
+    int nneed = 0;
+    for (int p = 0; p < P; ++p) {
+        beta[p] = std::sqrt(H->h_red[p].x);
+        if (!std::isfinite(beta[p])) {
+            H->last_error = "initial residual is not finite";
+            return RAS_ENONFINITE;
+        }
+        need[p] = (bnorm[p] > 0.0 && beta[p] > rtol * bnorm[p]) ? 1 : 0;
+        H->res_relres[p] = bnorm[p] > 0.0 ? beta[p] / bnorm[p] : 0.0;
+        H->res_conv[p] = need[p] ? 0 : 1;
+        nneed += need[p];
+    }
+    int total = 0;
+    int hist_n = 0;
+    if (hist) hist[hist_n++] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    std::vector<double2> g0(static_cast<size_t>(P) * (m + 1));
+    bool broke = false;
+    while (nneed > 0 && total < maxit) {
+        const int mc = std::min(m, maxit - total);
+        for (int p = 0; p < P; ++p) {
+            KState &K = H->h_ks[p];
+            K.bnorm = bnorm[p];
+            K.beta = beta[p];
+            K.est = beta[p];
+            K.rtol = rtol;
+            K.kp = 0;
+            K.in_cycle = need[p];
+            K.breakdown = 0;
+            K.pad_ = 0;
+            for (int i = 0; i <= m; ++i) g0[static_cast<size_t>(p) * (m + 1) + i] = make_double2(0, 0);
+            g0[static_cast<size_t>(p) * (m + 1)] = make_double2(beta[p], 0.0);
+        }
+        HCHK(H, hipMemcpyAsync(H->d_ks, H->h_ks, sizeof(KState) * P, hipMemcpyHostToDevice, st));
+        HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+        HCHK(H, hipMemcpyAsync(H->d_g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice,
+                               st));
+        launch_start_cycle(H->d_probs, P, H->max_ndof, H->d_ks, H->d_r, H->d_V, st);
+        HCHK(H, hipGetLastError());
+        // active-in-cycle flags for the apply/SpMV: mirror of need at start
+        std::vector<int> act(need);
+        for (int j = 0; j < mc; ++j) {
+            const long long n = H->ntot;
+            double2 *Vj = H->d_V + static_cast<long long>(j) * n;
+            double2 *Vj1 = H->d_V + static_cast<long long>(j + 1) * n;
+            double2 *Zj = H->d_Z + static_cast<long long>(j) * n;
+            RCHK(do_apply(H, Vj, Zj, H->d_active, st));
+            {
+                Timer t(H, C_SPMV, st);
+                launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, n, Zj, nullptr, Vj1,
+                            st);
+            }
+            HCHK(H, hipGetLastError());
+            {
+                Timer t(H, C_MGS, st);
+                for (int i = 0; i <= j; ++i)
+                    launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, i, i == 0 ? 0 : 1, m,
+                               H->d_H, H->d_partials, H->d_counters, st);
+                launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, j + 1, 2, m, H->d_H,
+                           H->d_partials, H->d_counters, st);
+                launch_normalize(H->d_probs, P, H->max_ndof, H->d_ks, Vj1, j, m, H->d_H, st);
+            }
+            HCHK(H, hipGetLastError());
+            {
+                Timer t(H, C_GIVENS, st);
+                launch_givens(H->d_ks, P, j, m, H->d_H, H->d_cs, H->d_sn, H->d_g, nullptr, st);
+            }
+            HCHK(H, hipGetLastError());
+            HCHK(H, hipMemcpyAsync(H->h_ks, H->d_ks, sizeof(KState) * P, hipMemcpyDeviceToHost, st));
+            HCHK(H, hipStreamSynchronize(st));
+            ++total;
+            int still = 0;
+            double worst = 0.0;
+            for (int p = 0; p < P; ++p) {
+                if (act[p]) {
+                    worst = std::max(worst, H->h_ks[p].est / bnorm[p]);
+                    H->res_iters[p] += 1;
+                }
+                act[p] = H->h_ks[p].in_cycle;
+                still += act[p];
+            }
+            if (hist) hist[hist_n++] = worst;
+            if (still == 0) break;
+            HCHK(H, hipMemcpyAsync(H->d_active, act.data(), sizeof(int) * P, hipMemcpyHostToDevice,
+                                   st));
+        }
+        // x += Z y for every problem that took steps
+        launch_solve_y(H->d_ks, P, m, H->d_H, H->d_g, H->d_y, st);
+        HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+        launch_update_x(H->d_probs, P, H->max_ndof, H->d_ks, H->d_active, m, H->d_Z, H->ntot,
+                        H->d_y, x, st);
+        HCHK(H, hipGetLastError());
+        launch_spmv(H->d_probs, P, H->max_ndof, nullptr, H->d_coef, H->ntot, x, b, H->d_r, st);
+        HCHK(H, hipGetLastError());
+        RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
+        nneed = 0;
+        for (int p = 0; p < P; ++p) {
+            if (!need[p]) continue;
+            beta[p] = std::sqrt(H->h_red[p].x);
+            if (!std::isfinite(beta[p])) {
+                H->last_error = "iterate is not finite";
+                return RAS_ENONFINITE;
+            }
+            H->res_relres[p] = beta[p] / bnorm[p];
+            if (beta[p] <= rtol * bnorm[p]) {
+                need[p] = 0;
+                H->res_conv[p] = 1;
+            } else if (H->h_ks[p].breakdown) {
+                need[p] = 0;
+                broke = true;
+            }
+            nneed += need[p];
+        }
+    }
+    if (iters) *iters = total;
+    if (relres) *relres = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    for (int p = 0; p < P; ++p)
+        if (!H->res_conv[p]) {
+            if (broke) {
+                H->last_error = "Arnoldi breakdown before the tolerance was reached";
+                return RAS_EBREAKDOWN;
+            }
+            H->last_error = "maximum number of iterations reached";
+            return RAS_ENOTCONV;
+        }
+    return RAS_OK;
+}
+
+int setup_common(int nprob, const double *k, const double *h, const int *grid, const int *subs,
+                 const int *overlap, const int *pml, const ras_pml_opts *opts, void *stream,
+                 ras_pml_t *out) {
+    if (out == nullptr) {
+        g_plan_error = "out is NULL";
+        return RAS_EINVAL;
+    }
+    *out = nullptr;
+    if (nprob < 1 || !k || !h || !grid || !subs || !overlap || !pml) {
+        g_plan_error = "invalid problem arrays";
+        return RAS_EINVAL;
+    }
+    ras_pml_opts o;
+    ras_pml_default_opts(&o);
+    if (opts) o = *opts;
+    std::unique_ptr<ras_pml_handle> H(new (std::nothrow) ras_pml_handle());
+    if (!H) return RAS_ENOMEM;
+    H->plans.resize(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        std::string err;
+        int rc = plan_problem(k[p], h[p], grid + 2 * p, subs + 2 * p, overlap[p], pml[p], o,
+                              H->plans[p], err);
+        if (rc != RAS_OK) {
+            g_plan_error = nprob > 1 ? "problem " + std::to_string(p) + ": " + err : err;
+            return rc;
+        }
+    }
+    H->fp64 = o.precision == RAS_FP64;
+    H->flags = o.flags;
+    int rc = build(H.get(), as_stream(stream));
+    if (rc != RAS_OK) {
+        g_plan_error = H->last_error;
+        return rc;
+    }
+    *out = H.release();
+    return RAS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+void ras_pml_default_opts(ras_pml_opts *o) {
+    if (!o) return;
+    o->sigma = 0.0;
+    o->global_pml = -1;
+    o->bc = RAS_BC_IMP;
+    o->pou = RAS_POU_LINEAR;
+    o->precision = RAS_MIXED;
+    o->flags = 0;
+}
+
+const char *ras_pml_plan_error(void) { return g_plan_error.c_str(); }
+
+int ras_pml_plan(double k, double h, const int grid[2], const int subdomains[2], int overlap,
+                 int pml_width, const ras_pml_opts *opts, int *nsub, int *desc, int desc_cap) {
+    try {
+        ras_pml_opts o;
+        ras_pml_default_opts(&o);
+        if (opts) o = *opts;
+        PlanProblem pl;
+        std::string err;
+        int rc = plan_problem(k, h, grid, subdomains, overlap, pml_width, o, pl, err);
+        if (rc != RAS_OK) {
+            g_plan_error = err;
+            return rc;
+        }
+        const int ns = static_cast<int>(pl.subs.size());
+        if (nsub) *nsub = ns;
+        if (desc) {
+            if (desc_cap < ns) {
+                g_plan_error = "desc_cap too small";
+                return RAS_EINVAL;
+            }
+            for (int s = 0; s < ns; ++s) desc_ints(pl.subs[s], pl, desc + s * RAS_DESC_INTS);
+        }
+        return RAS_OK;
+    } catch (const std::exception &e) {
+        g_plan_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+int ras_pml_setup(double k, double h, const int grid[2], const int subdomains[2], int overlap,
+                  int pml_width, const ras_pml_opts *opts, void *stream, ras_pml_t *out) {
+    try {
+        return setup_common(1, &k, &h, grid, subdomains, &overlap, &pml_width, opts, stream, out);
+    } catch (const std::exception &e) {
+        g_plan_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+int ras_pml_setup_batch(int nprob, const double *k, const double *h, const int *grid,
+                        const int *subdomains, const int *overlap, const int *pml_width,
+                        const ras_pml_opts *opts, void *stream, ras_pml_t *out) {
+    try {
+        return setup_common(nprob, k, h, grid, subdomains, overlap, pml_width, opts, stream, out);
+    } catch (const std::exception &e) {
+        g_plan_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+void ras_pml_destroy(ras_pml_t H) { delete H; }
+
+int ras_pml_num_dofs(ras_pml_t H, long long *n) {
+    if (!H || !n) return RAS_EINVAL;
+    *n = H->ntot;
+    return RAS_OK;
+}
+
+int ras_pml_num_problems(ras_pml_t H, int *nprob) {
+    if (!H || !nprob) return RAS_EINVAL;
+    *nprob = H->nprob;
+    return RAS_OK;
+}
+
+int ras_pml_problem_offset(ras_pml_t H, int p, long long *off, long long *n) {
+    if (!H || p < 0 || p >= H->nprob) return RAS_EINVAL;
+    if (off) *off = H->hprobs[p].dof_off;
+    if (n) *n = H->hprobs[p].ndof;
+    return RAS_OK;
+}
+
+int ras_pml_num_subdomains(ras_pml_t H, int *nsub) {
+    if (!H || !nsub) return RAS_EINVAL;
+    *nsub = H->nsub;
+    return RAS_OK;
+}
+
+int ras_pml_num_local(ras_pml_t H, long long *nloc) {
+    if (!H || !nloc) return RAS_EINVAL;
+    *nloc = H->nloc;
+    return RAS_OK;
+}
+
+int ras_pml_subdomain_desc(ras_pml_t H, int *desc, int desc_cap) {
+    if (!H || !desc || desc_cap < H->nsub) return RAS_EINVAL;
+    for (int s = 0; s < H->nsub; ++s)
+        desc_ints(H->hsubs[s], H->plans[H->hsubs[s].prob], desc + s * RAS_DESC_INTS);
+    return RAS_OK;
+}
+
+int ras_pml_rhs(ras_pml_t H, const void *f, void *b, void *stream) {
+    if (!H || !f || !b) return RAS_EINVAL;
+    launch_rhs(H->d_probs, H->nprob, H->max_ndof, static_cast<const double2 *>(f),
+               static_cast<double2 *>(b), as_stream(stream));
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+int ras_pml_spmv(ras_pml_t H, const void *x, void *y, void *stream) {
+    if (!H || !x || !y || x == y) {
+        if (H) H->last_error = "invalid vectors (x and y must be distinct, non-NULL)";
+        return RAS_EINVAL;
+    }
+    hipStream_t st = as_stream(stream);
+    {
+        Timer t(H, C_SPMV, st);
+        launch_spmv(H->d_probs, H->nprob, H->max_ndof, nullptr, H->d_coef, H->ntot,
+                    static_cast<const double2 *>(x), nullptr, static_cast<double2 *>(y), st);
+    }
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+int ras_pml_apply(ras_pml_t H, const void *v, void *z, void *stream) {
+    if (!H || !v || !z || v == z) {
+        if (H) H->last_error = "invalid vectors (v and z must be distinct, non-NULL)";
+        return RAS_EINVAL;
+    }
+    return do_apply(H, static_cast<const double2 *>(v), static_cast<double2 *>(z), nullptr,
+                    as_stream(stream));
+}
+
+int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
+    if (!H || !v || !xloc) return RAS_EINVAL;
+    hipStream_t st = as_stream(stream);
+    {
+        Timer t(H, C_SOLVE, st);
+        launch_band_solve(H->fp64, H->maxW, H->d_probs, H->d_subs, H->d_order, H->nsub, nullptr,
+                          static_cast<const double2 *>(v), H->d_F, H->d_ybuf, H->d_xout, st);
+    }
+    HCHK(H, hipGetLastError());
+    launch_export_local(H->fp64, H->d_subs, H->nsub, H->max_n, H->d_xout,
+                        static_cast<double2 *>(xloc), st);
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, int maxit,
+                int *iters, double *relres, double *hist, void *stream) {
+    if (!H) return RAS_EINVAL;
+    if (!b || !x || b == x || !(rtol > 0.0) || restart < 1 || maxit < 0) {
+        H->last_error = "invalid gmres arguments";
+        return RAS_EINVAL;
+    }
+    try {
+        return gmres_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
+                          restart, maxit, iters, relres, hist, as_stream(stream));
+    } catch (const std::exception &e) {
+        H->last_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged) {
+    if (!H || p < 0 || p >= H->nprob || H->res_iters.empty()) return RAS_EINVAL;
+    if (iters) *iters = H->res_iters[p];
+    if (relres) *relres = H->res_relres[p];
+    if (converged) *converged = H->res_conv[p];
+    return RAS_OK;
+}
+
+int ras_pml_export_stencil(ras_pml_t H, void *host_out) {
+    if (!H || !host_out) return RAS_EINVAL;
+    HCHK(H, hipDeviceSynchronize());
+    HCHK(H, hipMemcpy(host_out, H->d_coef, sizeof(double2) * 4 * H->ntot, hipMemcpyDeviceToHost));
+    return RAS_OK;
+}
+
+int ras_pml_export_local(ras_pml_t H, int j, void *host_out) {
+    if (!H || !host_out || j < 0 || j >= H->nsub) return RAS_EINVAL;
+    const DevSub &s = H->hsubs[j];
+    HCHK(H, hipDeviceSynchronize());
+    HCHK(H, hipMemcpy(host_out, H->d_lst + 4 * s.loc_off, sizeof(double2) * 4 * s.n,
+                      hipMemcpyDeviceToHost));
+    return RAS_OK;
+}
+
+int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_values) {
+    if (!H || !host_out || j < 0 || j >= H->nsub) return RAS_EINVAL;
+    const DevSub &s = H->hsubs[j];
+    const long long cnt = static_cast<long long>(s.npad) * (s.W + 1);
+    if (cap_values < cnt) {
+        H->last_error = "export_factor: capacity too small";
+        return RAS_EINVAL;
+    }
+    HCHK(H, hipDeviceSynchronize());
+    const char *src = static_cast<const char *>(H->d_F) + H->csize * s.fac_off;
+    double *out = static_cast<double *>(host_out);
+    if (H->fp64) {
+        HCHK(H, hipMemcpy(out, src, 16 * cnt, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(2 * cnt);
+        HCHK(H, hipMemcpy(tmp.data(), src, 8 * cnt, hipMemcpyDeviceToHost));
+        for (long long i = 0; i < 2 * cnt; ++i) out[i] = tmp[i];
+    }
+    return RAS_OK;
+}
+
+int ras_pml_get_stats(ras_pml_t H, ras_pml_stats *out) {
+    if (!H || !out) return RAS_EINVAL;
+    collect_events(H);
+    *out = H->stats;
+    return RAS_OK;
+}
+
+int ras_pml_reset_stats(ras_pml_t H) {
+    if (!H) return RAS_EINVAL;
+    collect_events(H);
+    const double sb = H->stats.solve_bytes, fb = H->stats.factor_bytes;
+    const double a = H->stats.setup_assemble_ms, f = H->stats.setup_factor_ms;
+    std::memset(&H->stats, 0, sizeof(H->stats));
+    H->stats.solve_bytes = sb;
+    H->stats.factor_bytes = fb;
+    H->stats.setup_assemble_ms = a;
+    H->stats.setup_factor_ms = f;
+    return RAS_OK;
+}
+
+const char *ras_pml_strerror(int status) {
+    switch (status) {
+        case RAS_OK: return "success";
+        case RAS_EINVAL: return "invalid argument";
+        case RAS_ENOMEM: return "out of device memory";
+        case RAS_EHIP: return "HIP runtime error";
+        case RAS_EZEROPIVOT: return "zero pivot in a local factorisation";
+        case RAS_ENONFINITE: return "non-finite value";
+        case RAS_ENOTCONV: return "GMRES did not converge within maxit";
+        case RAS_EBREAKDOWN: return "GMRES breakdown";
+        case RAS_ENOTSUP: return "size not supported";
+        default: return "unknown status";
+    }
+}
+
+const char *ras_pml_last_error(ras_pml_t H) { return H ? H->last_error.c_str() : ""; }
+
+}  // extern "C"

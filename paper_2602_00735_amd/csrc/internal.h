@@ -1,0 +1,94 @@
+// Internal data structures shared by the host planner, the kernels and the
+// C ABI.  Plain structs: the device reads them as they are laid out here.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ras_pml.h"
+
+namespace raspml {
+
+// Largest factor column length W = n_fast + 2 the kernels are built for.
+constexpr int kMaxW = 128;
+// Largest number of chunks whose partition-of-unity weight is non-zero at
+// one mesh node along one axis.
+constexpr int kMaxPou = 4;
+// Local vectors and factor columns are padded to a multiple of this.
+constexpr int kPad = 64;
+
+// Flags of a subdomain descriptor.
+enum : int {
+    SD_PML_XLO = 1, SD_PML_XHI = 2, SD_PML_YLO = 4, SD_PML_YHI = 8,
+    SD_IMP_XLO = 16, SD_IMP_XHI = 32, SD_IMP_YLO = 64, SD_IMP_YHI = 128
+};
+
+// One subdomain, as the kernels see it.
+struct DevSub {
+    int n;          // local unknowns
+    int npad;       // n rounded up to kPad
+    int nf;         // unknowns along the fast axis
+    int W;          // factor column length nf + 2 (= half-bandwidth + 1)
+    int xfast;      // 1: x is the fast axis
+    int ix0, nx;    // first unknown node index and count along x
+    int jy0, ny;    // same along y
+    int prob;       // problem index
+    int bx0, bx1, by0, by1;   // Omega_j box in node indices
+    int flags;      // SD_* bits
+    int cp, cq;     // chunk indices along x and y
+    int ix_int0, ix_int1, iy_int0, iy_int1;   // Omega_{j,int} in node indices
+    int pad_;
+    double ax, bx, ay, by;    // Omega_{j,int} edges (coordinates)
+    long long fac_off;  // first L entry (elements); D^{-1} follows npad*W later
+    long long vec_off;  // first entry of this subdomain's padded local vectors
+    long long loc_off;  // first entry in the unpadded back-to-back layout
+};
+
+// One problem, as the kernels see it.
+struct DevProb {
+    double k, h, sigma;
+    int G, Nc, n1;        // n1 = Nc - 1 unknowns per side
+    int Px, Py;
+    int sub_first;        // first subdomain index of this problem
+    int pou_x, pou_y;     // offsets into the PoU tables (in nodes)
+    int pad_;
+    long long dof_off;    // first unknown in the concatenated vectors
+    long long ndof;
+};
+
+// Per-problem GMRES state kept on the device.
+struct KState {
+    double bnorm;      // ||b||
+    double beta;       // ||r0|| of the current cycle
+    double est;        // |g_{j+1}| after the last step
+    double rtol;
+    int kp;            // Arnoldi steps taken in the current cycle
+    int in_cycle;      // 1 while the problem takes steps in this cycle
+    int breakdown;     // Arnoldi broke down in this cycle
+    int pad_;
+};
+
+// Host-side plan of one problem.
+struct PlanProblem {
+    double k, h, sigma;
+    int n_int, G, Nc, Px, Py, delta, kappa, bc, pou;
+    long long ndof;
+    std::vector<DevSub> subs;          // q * Px + p order
+    // 1D partition of unity along each axis: for node i (0..Nc) up to
+    // kMaxPou (chunk, weight) pairs with weight > 0.
+    std::vector<int> pou_cnt[2];
+    std::vector<int> pou_chunk[2];     // (Nc+1) * kMaxPou
+    std::vector<double> pou_w[2];      // (Nc+1) * kMaxPou
+};
+
+// Validate one problem and compute its subdomains and PoU tables.
+// Returns RAS_OK or an error status with a message in `err`.
+int plan_problem(double k, double h, const int grid[2], const int subdomains[2],
+                 int overlap, int pml_width, const ras_pml_opts &opts,
+                 PlanProblem &out, std::string &err);
+
+// Descriptor in the int32 layout documented in ras_pml.h.
+void desc_ints(const DevSub &s, const PlanProblem &pb, int *out);
+
+}  // namespace raspml

@@ -1,0 +1,357 @@
+// Krylov-side kernels, all complex128 (Section 4.1: GMRES accelerated by
+// RAS-PML).  Every kernel runs over all problems of a handle at once: grid
+// row blockIdx.y is the problem, and a problem whose `active` flag is 0 is
+// skipped.
+//
+//   k_spmv       y = A x or y = b - A x with the 7-point stencil
+//   k_mgs        one modified Gram-Schmidt projection, fused with the
+//                previous one's update:  w -= h_{i-1} v_{i-1};  h_i = <v_i, w>
+//                (or the final update and ||w||); deterministic two-level
+//                reduction finished by the last block of each problem
+//   k_normalize  v_{j+1} = w / h_{j+1,j}
+//   k_givens     complex Givens rotations on the Hessenberg column, residual
+//                estimate |g_{j+1}|, cycle bookkeeping
+//   k_cycle_end  back substitution R y = g and x += Z y
+#include "device.h"
+
+namespace raspml {
+
+constexpr int kRedBlocks = 512;   // blocks per problem of a reduction
+constexpr int kRedThreads = 256;
+
+namespace {
+
+__device__ __forceinline__ cplx<double> ld(const double2 *p, long long i) {
+    double2 v = p[i];
+    return {v.x, v.y};
+}
+__device__ __forceinline__ void st(double2 *p, long long i, cplx<double> v) {
+    p[i] = make_double2(v.re, v.im);
+}
+
+__global__ void k_spmv(const DevProb *__restrict__ probs, const int *__restrict__ active,
+                       const double2 *__restrict__ coef, long long ntot,
+                       const double2 *__restrict__ x, const double2 *__restrict__ b,
+                       double2 *__restrict__ y) {
+    const DevProb P = probs[blockIdx.y];
+    if (active != nullptr && active[blockIdx.y] == 0) return;
+    const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= P.ndof) return;
+    const int n1 = P.n1;
+    const int i = static_cast<int>(idx % n1) + 1;
+    const int j = static_cast<int>(idx / n1) + 1;
+    const long long g = P.dof_off + idx;
+    const double2 *C = coef, *E = coef + ntot, *N = coef + 2 * ntot, *NE = coef + 3 * ntot;
+    cplx<double> acc = cmul(ld(C, g), ld(x, g));
+    if (i < n1) acc = cfma(acc, ld(E, g), ld(x, g + 1));
+    if (i > 1) acc = cfma(acc, ld(E, g - 1), ld(x, g - 1));
+    if (j < n1) acc = cfma(acc, ld(N, g), ld(x, g + n1));
+    if (j > 1) acc = cfma(acc, ld(N, g - n1), ld(x, g - n1));
+    if (i < n1 && j < n1) acc = cfma(acc, ld(NE, g), ld(x, g + n1 + 1));
+    if (i > 1 && j > 1) acc = cfma(acc, ld(NE, g - n1 - 1), ld(x, g - n1 - 1));
+    if (b != nullptr) acc = csub(ld(b, g), acc);
+    st(y, g, acc);
+}
+
+__device__ __forceinline__ int red_blocks(long long n) {
+    long long nb = (n + kRedThreads - 1) / kRedThreads;
+    return static_cast<int>(nb < kRedBlocks ? (nb < 1 ? 1 : nb) : kRedBlocks);
+}
+
+// Block sum of a complex value held by every thread (fixed order).
+__device__ cplx<double> block_sum(cplx<double> v, cplx<double> *sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) sh[tid] = cadd(sh[tid], sh[tid + o]);
+        __syncthreads();
+    }
+    cplx<double> r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Write this block's partial; the last block of the problem to arrive sums
+// all partials in index order and returns true with the total in *out.
+__device__ bool finish_reduction(cplx<double> part, int p, int nb, double2 *partials,
+                                 unsigned int *counters, cplx<double> *sh, cplx<double> *out) {
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        partials[static_cast<long long>(p) * kRedBlocks + blockIdx.x] = make_double2(part.re, part.im);
+        __threadfence();
+        const unsigned int ticket = atomicAdd(&counters[p], 1u);
+        last = (ticket == static_cast<unsigned int>(nb - 1)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    cplx<double> acc{0, 0};
+    for (int e = tid; e < nb; e += kRedThreads) {
+        double2 v = partials[static_cast<long long>(p) * kRedBlocks + e];
+        acc = cadd(acc, cplx<double>{v.x, v.y});
+    }
+    *out = block_sum(acc, sh);
+    if (tid == 0) counters[p] = 0u;
+    return true;
+}
+
+// mode 0: h_{0,j} = <v_0, w>
+// mode 1: w -= h_{i-1,j} v_{i-1};  h_{i,j} = <v_i, w>
+// mode 2: w -= h_{j,j} v_j;        h_{j+1,j} = ||w||
+// H is column-major with leading dimension m+1, one matrix per problem.
+__global__ __launch_bounds__(kRedThreads) void k_mgs(
+    const DevProb *__restrict__ probs, const KState *__restrict__ ks, double2 *__restrict__ w,
+    const double2 *__restrict__ V, long long ntot, int j, int i, int mode, int m,
+    double2 *__restrict__ H, double2 *__restrict__ partials, unsigned int *__restrict__ counters) {
+    __shared__ cplx<double> sh[kRedThreads];
+    const int p = blockIdx.y;
+    if (ks[p].in_cycle == 0) return;
+    const DevProb P = probs[p];
+    const int nb = red_blocks(P.ndof);
+    if (static_cast<int>(blockIdx.x) >= nb) return;
+    double2 *Hp = H + static_cast<long long>(p) * (m + 1) * m;
+    const long long col = static_cast<long long>(j) * (m + 1);
+    cplx<double> hprev{0, 0};
+    const double2 *vprev = nullptr;
+    if (mode == 1) {
+        hprev = ld(Hp, col + i - 1);
+        vprev = V + static_cast<long long>(i - 1) * ntot;
+    } else if (mode == 2) {
+        hprev = ld(Hp, col + j);
+        vprev = V + static_cast<long long>(j) * ntot;
+    }
+    const double2 *vi = (mode == 2) ? nullptr : V + static_cast<long long>(i) * ntot;
+    cplx<double> acc{0, 0};
+    const long long stride = static_cast<long long>(nb) * kRedThreads;
+    for (long long e = static_cast<long long>(blockIdx.x) * kRedThreads + threadIdx.x; e < P.ndof;
+         e += stride) {
+        const long long g = P.dof_off + e;
+        cplx<double> x = ld(w, g);
+        if (mode != 0) {
+            x = cfms(x, hprev, ld(vprev, g));
+            st(w, g, x);
+        }
+        if (mode == 2)
+            acc.re = fma(x.re, x.re, fma(x.im, x.im, acc.re));
+        else
+            acc = cdotacc(acc, ld(vi, g), x);
+    }
+    cplx<double> part = block_sum(acc, sh);
+    cplx<double> tot;
+    if (finish_reduction(part, p, nb, partials, counters, sh, &tot) && threadIdx.x == 0) {
+        if (mode == 2)
+            st(Hp, col + j + 1, cplx<double>{sqrt(tot.re), 0.0});
+        else
+            st(Hp, col + i, tot);
+    }
+}
+
+// Plain deterministic reductions used outside the Arnoldi step:
+// mode 0: out[p] = ||a_p||^2 (real part), mode 1: out[p] = <a_p, b_p>.
+__global__ __launch_bounds__(kRedThreads) void k_reduce(
+    const DevProb *__restrict__ probs, const int *__restrict__ active, const double2 *__restrict__ a,
+    const double2 *__restrict__ b, int mode, double2 *__restrict__ out,
+    double2 *__restrict__ partials, unsigned int *__restrict__ counters) {
+    __shared__ cplx<double> sh[kRedThreads];
+    const int p = blockIdx.y;
+    if (active != nullptr && active[p] == 0) return;
+    const DevProb P = probs[p];
+    const int nb = red_blocks(P.ndof);
+    if (static_cast<int>(blockIdx.x) >= nb) return;
+    cplx<double> acc{0, 0};
+    const long long stride = static_cast<long long>(nb) * kRedThreads;
+    for (long long e = static_cast<long long>(blockIdx.x) * kRedThreads + threadIdx.x; e < P.ndof;
+         e += stride) {
+        const long long g = P.dof_off + e;
+        cplx<double> x = ld(a, g);
+        if (mode == 0)
+            acc.re = fma(x.re, x.re, fma(x.im, x.im, acc.re));
+        else
+            acc = cdotacc(acc, x, ld(b, g));
+    }
+    cplx<double> part = block_sum(acc, sh);
+    cplx<double> tot;
+    if (finish_reduction(part, p, nb, partials, counters, sh, &tot) && threadIdx.x == 0)
+        out[p] = make_double2(tot.re, tot.im);
+}
+
+__global__ void k_normalize(const DevProb *__restrict__ probs, const KState *__restrict__ ks,
+                            double2 *__restrict__ w, int j, int m, const double2 *__restrict__ H) {
+    const int p = blockIdx.y;
+    if (ks[p].in_cycle == 0) return;
+    const DevProb P = probs[p];
+    const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= P.ndof) return;
+    const double hn = H[static_cast<long long>(p) * (m + 1) * m + static_cast<long long>(j) * (m + 1) + j + 1].x;
+    const double s = hn > 0.0 ? 1.0 / hn : 0.0;
+    const long long g = P.dof_off + idx;
+    st(w, g, cscale(ld(w, g), s));
+}
+
+// v0 = r / beta for problems that start a cycle (beta from ks).
+__global__ void k_start_cycle(const DevProb *__restrict__ probs, const KState *__restrict__ ks,
+                              const double2 *__restrict__ r, double2 *__restrict__ v0) {
+    const int p = blockIdx.y;
+    if (ks[p].in_cycle == 0) return;
+    const DevProb P = probs[p];
+    const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= P.ndof) return;
+    const long long g = P.dof_off + idx;
+    st(v0, g, cscale(ld(r, g), 1.0 / ks[p].beta));
+}
+
+// One thread per problem.  Rotation [[c, s], [-conj(s), c]] with c real
+// zeroes h_{j+1,j}; g_{j+1} = -conj(s) g_j, g_j = c g_j.
+__global__ void k_givens(KState *__restrict__ ks, int nprob, int j, int m, double2 *__restrict__ H,
+                         double *__restrict__ cs, double2 *__restrict__ sn,
+                         double2 *__restrict__ gv, double *__restrict__ hist) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || ks[p].in_cycle == 0) return;
+    double2 *Hc = H + static_cast<long long>(p) * (m + 1) * m + static_cast<long long>(j) * (m + 1);
+    double *c_ = cs + static_cast<long long>(p) * m;
+    double2 *s_ = sn + static_cast<long long>(p) * m;
+    double2 *g = gv + static_cast<long long>(p) * (m + 1);
+    double colnorm2 = 0.0;
+    for (int i = 0; i <= j + 1; ++i) colnorm2 += Hc[i].x * Hc[i].x + Hc[i].y * Hc[i].y;
+    const double hn = Hc[j + 1].x;
+    for (int i = 0; i < j; ++i) {
+        cplx<double> a{Hc[i].x, Hc[i].y}, b{Hc[i + 1].x, Hc[i + 1].y};
+        cplx<double> s{s_[i].x, s_[i].y};
+        const double c = c_[i];
+        cplx<double> t = cadd(cscale(a, c), cmul(s, b));
+        cplx<double> nb = cadd(cscale(cmul(cplx<double>{-s.re, s.im}, a), 1.0), cscale(b, c));
+        Hc[i] = make_double2(t.re, t.im);
+        Hc[i + 1] = make_double2(nb.re, nb.im);
+    }
+    cplx<double> a{Hc[j].x, Hc[j].y};
+    const double aa = sqrt(a.re * a.re + a.im * a.im);
+    double c;
+    cplx<double> s;
+    if (hn == 0.0) {
+        c = 1.0;
+        s = {0.0, 0.0};
+    } else if (aa == 0.0) {
+        c = 0.0;
+        s = {1.0, 0.0};
+    } else {
+        const double rho = hypot(aa, hn);
+        c = aa / rho;
+        s = cscale(a, hn / (aa * rho));
+    }
+    c_[j] = c;
+    s_[j] = make_double2(s.re, s.im);
+    cplx<double> r = cadd(cscale(a, c), cscale(s, hn));
+    Hc[j] = make_double2(r.re, r.im);
+    Hc[j + 1] = make_double2(0.0, 0.0);
+    cplx<double> gj{g[j].x, g[j].y};
+    cplx<double> g1 = cmul(cplx<double>{-s.re, s.im}, gj);
+    g[j + 1] = make_double2(g1.re, g1.im);
+    g[j] = make_double2(c * gj.re, c * gj.im);
+    const double est = sqrt(g1.re * g1.re + g1.im * g1.im);
+    KState &K = ks[p];
+    K.est = est;
+    K.kp = j + 1;
+    if (hist != nullptr) hist[p] = est / K.bnorm;
+    const bool brk = hn <= 1e-14 * sqrt(colnorm2);
+    if (brk) K.breakdown = 1;
+    if (est <= K.rtol * K.bnorm || brk || j + 1 == m) K.in_cycle = 0;
+}
+
+// Back substitution R y = g (one thread per problem, kp <= m).
+__global__ void k_solve_y(const KState *__restrict__ ks, int nprob, int m,
+                          const double2 *__restrict__ H, const double2 *__restrict__ gv,
+                          double2 *__restrict__ y) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const int kp = ks[p].kp;
+    const double2 *Hp = H + static_cast<long long>(p) * (m + 1) * m;
+    const double2 *g = gv + static_cast<long long>(p) * (m + 1);
+    double2 *yp = y + static_cast<long long>(p) * m;
+    for (int i = kp - 1; i >= 0; --i) {
+        cplx<double> acc{g[i].x, g[i].y};
+        for (int l = i + 1; l < kp; ++l) {
+            double2 h = Hp[static_cast<long long>(l) * (m + 1) + i];
+            acc = cfms(acc, cplx<double>{h.x, h.y}, cplx<double>{yp[l].x, yp[l].y});
+        }
+        double2 d = Hp[static_cast<long long>(i) * (m + 1) + i];
+        cplx<double> yi = cmul(acc, crecip(cplx<double>{d.x, d.y}));
+        yp[i] = make_double2(yi.re, yi.im);
+    }
+}
+
+// x += Z y for problems that took steps in this cycle (kp > 0).
+__global__ void k_update_x(const DevProb *__restrict__ probs, const KState *__restrict__ ks,
+                           const int *__restrict__ active, int m, const double2 *__restrict__ Z,
+                           long long ntot, const double2 *__restrict__ y, double2 *__restrict__ x) {
+    const int p = blockIdx.y;
+    if (active[p] == 0) return;
+    const int kp = ks[p].kp;
+    const DevProb P = probs[p];
+    const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= P.ndof || kp == 0) return;
+    const long long g = P.dof_off + idx;
+    const double2 *yp = y + static_cast<long long>(p) * m;
+    cplx<double> acc = ld(x, g);
+    for (int i = 0; i < kp; ++i)
+        acc = cfma(acc, cplx<double>{yp[i].x, yp[i].y}, ld(Z, static_cast<long long>(i) * ntot + g));
+    st(x, g, acc);
+}
+
+}  // namespace
+
+void launch_spmv(const DevProb *probs, int nprob, long long max_ndof, const int *active,
+                 const double2 *coef, long long ntot, const double2 *x, const double2 *b,
+                 double2 *y, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
+    hipLaunchKernelGGL(k_spmv, grid, dim3(256), 0, s, probs, active, coef, ntot, x, b, y);
+}
+
+void launch_mgs(const DevProb *probs, int nprob, const KState *ks, double2 *w, const double2 *V,
+                long long ntot, int j, int i, int mode, int m, double2 *H, double2 *partials,
+                unsigned int *counters, hipStream_t s) {
+    dim3 grid(kRedBlocks, nprob);
+    hipLaunchKernelGGL(k_mgs, grid, dim3(kRedThreads), 0, s, probs, ks, w, V, ntot, j, i, mode, m,
+                       H, partials, counters);
+}
+
+void launch_reduce(const DevProb *probs, int nprob, const int *active, const double2 *a,
+                   const double2 *b, int mode, double2 *out, double2 *partials,
+                   unsigned int *counters, hipStream_t s) {
+    dim3 grid(kRedBlocks, nprob);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(kRedThreads), 0, s, probs, active, a, b, mode, out,
+                       partials, counters);
+}
+
+void launch_normalize(const DevProb *probs, int nprob, long long max_ndof, const KState *ks,
+                      double2 *w, int j, int m, const double2 *H, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
+    hipLaunchKernelGGL(k_normalize, grid, dim3(256), 0, s, probs, ks, w, j, m, H);
+}
+
+void launch_start_cycle(const DevProb *probs, int nprob, long long max_ndof, const KState *ks,
+                        const double2 *r, double2 *v0, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
+    hipLaunchKernelGGL(k_start_cycle, grid, dim3(256), 0, s, probs, ks, r, v0);
+}
+
+void launch_givens(KState *ks, int nprob, int j, int m, double2 *H, double *cs, double2 *sn,
+                   double2 *g, double *hist, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, dim3((nprob + 63) / 64), dim3(64), 0, s, ks, nprob, j, m, H, cs,
+                       sn, g, hist);
+}
+
+void launch_solve_y(const KState *ks, int nprob, int m, const double2 *H, const double2 *g,
+                    double2 *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_y, dim3((nprob + 63) / 64), dim3(64), 0, s, ks, nprob, m, H, g, y);
+}
+
+void launch_update_x(const DevProb *probs, int nprob, long long max_ndof, const KState *ks,
+                     const int *active, int m, const double2 *Z, long long ntot,
+                     const double2 *y, double2 *x, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
+    hipLaunchKernelGGL(k_update_x, grid, dim3(256), 0, s, probs, ks, active, m, Z, ntot, y, x);
+}
+
+}  // namespace raspml

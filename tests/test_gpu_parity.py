@@ -1,0 +1,312 @@
+"""GPU parity of every step of the hot path against the CPU oracle.
+
+Every input is seeded and synthetic; every expected value comes from the
+oracle (never from the HIP path).  Tolerances: complex128 results within
+1e-12 (operators 1e-14), complex64 local factors/solves within 1e-4 of the
+complex128 oracle, GMRES within +-1 iteration and 1e-10 (FP64) / 1e-5
+(mixed) of the oracle's solution at the same rtol.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_2602_00735_amd as rp
+from paper_2602_00735_amd import inputs
+from oracle import fem, geometry, gmres, ras
+from oracle.geometry import BC_DRCH, BC_IMP, POU_BOOLEAN, POU_LINEAR, Problem
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def setup_gpu(pb, precision, flags=0):
+    o = rp.default_opts(sigma=pb.sigma, global_pml=pb.G, bc=pb.bc, pou=pb.pou,
+                        precision=precision, flags=flags)
+    return rp.ras_pml_setup(pb.k, 1.0 / pb.n_int, (pb.n_int, pb.n_int), (pb.Px, pb.Py),
+                            pb.delta, pb.kappa, o)
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# name -> problem; W covers the one-register (<= 64) and two-register
+# (65..128) kernels, ragged chunks, clipped PML, Dirichlet and Boolean PoU.
+PROBLEMS = {
+    "k20": geometry.config_problem("k20"),
+    "k40_two_slot": Problem(k=40.0, n_int=80, G=8, Px=2, Py=2, delta=8, kappa=8, sigma=400.0),
+    "ragged": Problem(k=12.0, n_int=45, G=3, Px=3, Py=4, delta=3, kappa=3, sigma=120.0),
+    "clip_drch": Problem(k=9.0, n_int=30, G=2, Px=5, Py=5, delta=3, kappa=4, sigma=90.0, bc=BC_DRCH),
+    "boolean": Problem(k=12.0, n_int=40, G=4, Px=3, Py=3, delta=3, kappa=4, sigma=120.0,
+                       pou=POU_BOOLEAN),
+    "max_band": Problem(k=30.0, n_int=115, G=6, Px=1, Py=1, delta=0, kappa=0, sigma=300.0),
+}
+
+_oracles = {}
+
+
+def oracle_for(name):
+    if name not in _oracles:
+        _oracles[name] = ras.RasPml(PROBLEMS[name])
+    return _oracles[name]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_available():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rp.lib()
+
+
+# ------------------------------------------------------------------ a2
+@pytest.mark.parametrize("name", ["k20", "ragged", "clip_drch"])
+def test_global_stencil(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    st = rp.ras_pml_export_stencil(H)
+    A = R.A.tocsr()
+    n1 = pb.Nc - 1
+    idx = np.arange(pb.ndof)
+    i = idx % n1 + 1
+    j = idx // n1 + 1
+    scale = np.abs(A.diagonal()).max()
+    C = A.diagonal()
+    E = np.where(i < n1, np.asarray(A[idx, np.minimum(idx + 1, pb.ndof - 1)]).ravel(), 0)
+    N = np.where(j < n1, np.asarray(A[idx, np.minimum(idx + n1, pb.ndof - 1)]).ravel(), 0)
+    NE = np.where((i < n1) & (j < n1), np.asarray(A[idx, np.minimum(idx + n1 + 1, pb.ndof - 1)]).ravel(), 0)
+    for got, ref in zip(st, (C, E, N, NE)):
+        assert np.abs(got - ref).max() <= 1e-14 * scale
+
+
+# ------------------------------------------------------------------ a3
+@pytest.mark.parametrize("name", ["k20", "ragged", "clip_drch", "k40_two_slot"])
+def test_local_operators(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    for m, (sd, Aj) in enumerate(zip(R.sds, R.local)):
+        got = rp.ras_pml_export_local(H, m, sd.n)
+        Aj = Aj.tocsr()
+        nf = sd.n_fast
+        r = np.arange(sd.n)
+        def at(c):
+            ok = c < sd.n
+            return np.where(ok, np.asarray(Aj[r, np.minimum(c, sd.n - 1)]).ravel(), 0)
+        fast = np.where((r + 1) % nf != 0, at(r + 1), 0)
+        ne = np.where((r + 1) % nf != 0, at(r + nf + 1), 0)
+        ref = np.stack([Aj.diagonal(), fast, at(r + nf), ne], axis=1)
+        scale = np.abs(Aj.diagonal()).max()
+        assert np.abs(got - ref).max() <= 1e-14 * scale, (name, m)
+
+
+# ------------------------------------------------------------------ a4
+def unpack_slots(Lcols, n, W):
+    """L (dense, n x n lower part) from the slot-ordered columns."""
+    Ld = np.zeros((n, n), dtype=np.complex128)
+    for c in range(n):
+        for r in range(c + 1, min(c + W, n)):
+            Ld[r, c] = Lcols[c, r % W]
+    return Ld
+
+
+@pytest.mark.parametrize("name,precision", [("k20", rp.RAS_FP64), ("ragged", rp.RAS_FP64),
+                                            ("k40_two_slot", rp.RAS_FP64), ("k20", rp.RAS_MIXED)])
+def test_factors(name, precision):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, precision)
+    tol = 1e-12 if precision == rp.RAS_FP64 else 2e-5
+    for m, sd in enumerate(R.sds[:4]):
+        W = sd.band + 1
+        npad = (sd.n + 63) // 64 * 64
+        Lcols, Dinv = rp.ras_pml_export_factor(H, m, npad, W)
+        LU = R.batch.factors(m)
+        b = sd.band
+        n = sd.n
+        # slot position c mod W of column c holds 0
+        assert np.all(Lcols[np.arange(npad), np.arange(npad) % W] == 0)
+        D = LU[:, b]
+        assert np.abs(1.0 / Dinv[:n] - D).max() <= tol * np.abs(D).max()
+        assert np.allclose(Dinv[n:], 1.0)
+        for c in range(0, n, max(1, n // 97)):
+            for r in range(c + 1, min(c + W, n)):
+                ref = LU[r, b + c - r]
+                assert abs(Lcols[c, r % W] - ref) <= tol * max(1.0, abs(ref)), (m, r, c)
+
+
+# ------------------------------------------------------------------ a5
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_local_solves_fp64(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    v = inputs.random_vector(pb.ndof, 7)
+    xl = torch.zeros(H.nloc, dtype=torch.complex128, device="cuda")
+    rp.ras_pml_local_solve(H, dev(v), xl)
+    got = host(xl)
+    ref = R.local_solve(v)
+    for m in range(len(R.sds)):
+        a, b = R.local_part(got, m), R.local_part(ref, m)
+        assert relerr(a, b) <= 1e-12, (name, m, relerr(a, b))
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("precision,tol", [(rp.RAS_FP64, 1e-12), (rp.RAS_MIXED, 1e-4)])
+def test_apply(name, precision, tol):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, precision)
+    for seed in (1, 2):
+        v = inputs.random_vector(pb.ndof, seed)
+        z = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+        rp.ras_pml_apply(H, dev(v), z)
+        err = relerr(host(z), R.apply(v))
+        assert err <= tol, (name, precision, err)
+
+
+def test_apply_is_deterministic():
+    pb = PROBLEMS["ragged"]
+    H = setup_gpu(pb, rp.RAS_MIXED)
+    v = dev(inputs.random_vector(pb.ndof, 3))
+    z1 = torch.zeros_like(v)
+    z2 = torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, z1)
+    rp.ras_pml_apply(H, v, z2)
+    assert torch.equal(z1, z2)
+
+
+# ------------------------------------------------------------------ a6
+@pytest.mark.parametrize("name", ["k20", "ragged", "max_band"])
+def test_spmv_and_rhs(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    H = setup_gpu(pb, rp.RAS_MIXED)
+    x = inputs.random_vector(pb.ndof, 4)
+    y = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rp.ras_pml_spmv(H, dev(x), y)
+    assert relerr(host(y), R.A @ x) <= 1e-14
+    f = inputs.centre_gaussian(pb.n_int, pb.G, 0.1)
+    b = torch.zeros_like(y)
+    rp.ras_pml_rhs(H, dev(f), b)
+    assert relerr(host(b), fem.rhs(R.M1, f)) <= 1e-14
+
+
+# ------------------------------------------------------------------ a7
+@pytest.mark.parametrize("name,restart", [("k20", 50), ("ragged", 50), ("k40_two_slot", 100),
+                                          ("ragged", 4), ("clip_drch", 50), ("boolean", 50)])
+def test_gmres_fp64_matches_oracle(name, restart):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    f = inputs.centre_gaussian(pb.n_int, pb.G, 0.05 if name == "k20" else 0.1)
+    b = fem.rhs(R.M1, f)
+    ref = gmres.gmres(lambda x: R.A @ x, R.apply, b, rtol=1e-6, restart=restart, maxit=500)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.gmres_solve(H, dev(b), x, rtol=1e-6, restart=restart, maxit=500)
+    assert rc == rp.RAS_OK
+    assert abs(it - ref.iters) <= 1, (it, ref.iters)
+    xs = host(x)
+    assert np.linalg.norm(b - R.A @ xs) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)
+    assert rr <= 1e-6
+    if it == ref.iters:
+        assert relerr(xs, ref.x) <= 1e-10
+    # the residual estimates agree step by step while both run
+    k = min(len(ref.history), len(hist) - 1)
+    assert np.allclose(hist[1:k + 1], ref.history[:k], rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["k20", "k40_two_slot", "ragged"])
+def test_gmres_mixed_matches_fp64_oracle(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    ref = gmres.gmres(lambda x: R.A @ x, R.apply, b, rtol=1e-6, restart=100, maxit=500)
+    tight = gmres.gmres(lambda x: R.A @ x, R.apply, b, rtol=1e-12, restart=100, maxit=500)
+    H = setup_gpu(pb, rp.RAS_MIXED)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, _ = rp.gmres_solve(H, dev(b), x, rtol=1e-6, restart=100, maxit=500)
+    assert rc == rp.RAS_OK
+    xs = host(x)
+    assert np.linalg.norm(b - R.A @ xs) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)
+    assert abs(it - ref.iters) <= 2
+    assert relerr(xs, tight.x) <= 1e-5
+    assert relerr(xs, ref.x) <= 1e-5
+
+
+@pytest.mark.parametrize("bc", [BC_IMP, BC_DRCH])
+def test_one_subdomain_converges_in_one_iteration(bc):
+    pb = Problem(k=8.0, n_int=24, G=3, Px=1, Py=1, delta=3, kappa=3, sigma=80.0, bc=bc)
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    H = setup_gpu(pb, rp.RAS_FP64)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, _ = rp.gmres_solve(H, dev(b), x, rtol=1e-10, restart=20, maxit=50)
+    assert rc == rp.RAS_OK and it == 1 and rr <= 1e-12
+
+
+def test_gmres_edge_cases():
+    pb = PROBLEMS["k20"]
+    R = oracle_for("k20")
+    H = setup_gpu(pb, rp.RAS_FP64)
+    zero = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    x = torch.ones_like(zero)
+    rc, it, rr, _ = rp.gmres_solve(H, zero, x, rtol=1e-6)
+    assert rc == rp.RAS_OK and it == 0 and torch.count_nonzero(x) == 0
+    b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G)))
+    x = torch.zeros_like(zero)
+    rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, maxit=1)
+    assert rc == rp.RAS_ENOTCONV and it == 1 and rr > 1e-6
+    # resume from the last iterate (restart carries only x)
+    rc, it2, rr2, _ = rp.gmres_solve(H, b, x, rtol=1e-6)
+    assert rc == rp.RAS_OK and rr2 <= 1e-6
+    bad = b.clone()
+    bad[5] = complex(float("nan"), 0.0)
+    rc, *_ = rp.gmres_solve(H, bad, torch.zeros_like(zero), rtol=1e-6, check=False)
+    assert rc == rp.RAS_ENONFINITE
+
+
+# ------------------------------------------------------------------ batch
+def test_batch_handle_matches_separate_problems():
+    names = ["k20", "ragged", "k40_two_slot"]
+    pbs = [PROBLEMS[n] for n in names]
+    o = rp.default_opts(precision=rp.RAS_FP64)
+    # per-problem sigma / G must match the shared opts: use sigma=10k, G=pml
+    pbs = [Problem(k=p.k, n_int=p.n_int, G=p.kappa, Px=p.Px, Py=p.Py, delta=p.delta,
+                   kappa=p.kappa, sigma=10 * p.k) for p in pbs]
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs], o)
+    Rs = [ras.RasPml(p) for p in pbs]
+    n = sum(p.ndof for p in pbs)
+    assert H.ndof == n and H.nprob == 3
+    v = inputs.random_vector(n, 9)
+    z = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    rp.ras_pml_apply(H, dev(v), z)
+    zh = host(z)
+    bs = []
+    for p, R in enumerate(Rs):
+        off, m = H.problem_offset(p)
+        assert relerr(zh[off:off + m], R.apply(v[off:off + m])) <= 1e-12
+        bs.append(fem.rhs(R.M1, inputs.centre_gaussian(pbs[p].n_int, pbs[p].G, 0.1)))
+    b = np.concatenate(bs)
+    x = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    rc, it, rr, _ = rp.gmres_solve(H, dev(b), x, rtol=1e-6, restart=50, maxit=300)
+    assert rc == rp.RAS_OK
+    xs = host(x)
+    for p, R in enumerate(Rs):
+        off, m = H.problem_offset(p)
+        ref = gmres.gmres(lambda y: R.A @ y, R.apply, bs[p], rtol=1e-6, restart=50)
+        itp, rrp, conv = rp.ras_pml_batch_result(H, p)
+        assert conv and rrp <= 1e-6
+        assert abs(itp - ref.iters) <= 1
+        assert np.linalg.norm(bs[p] - R.A @ xs[off:off + m]) <= 1e-6 * np.linalg.norm(bs[p]) * (1 + 1e-9)
