@@ -93,9 +93,17 @@ _lib = None
 
 
 def lib():
-    """Load libras_pml.so; raise (never fall back) if it is not built."""
+    """Load libras_pml.so; raise (never fall back) if it is not built.
+
+    torch is imported first when it is installed: it carries its own HIP
+    runtime, and the library must bind to that same runtime (a second HIP
+    runtime in the process would not see the GPU that torch holds)."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libras_pml.so is not built; run "
                               "`python -m paper_2602_00735_amd.build` (HIP for gfx950)")

@@ -40,6 +40,24 @@ def _run(cmd, verbose):
     return r
 
 
+def _runtime_dir() -> str:
+    """Directory of the HIP runtime the process will use.
+
+    PyTorch ships its own libamdhip64; two HIP runtimes in one process do
+    not share devices, so the library links against torch's copy when torch
+    is installed, else against /opt/rocm/lib."""
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec and spec.origin:
+            d = os.path.join(os.path.dirname(spec.origin), "lib")
+            if os.path.exists(os.path.join(d, "libamdhip64.so")):
+                return d
+    except Exception:
+        pass
+    return "/opt/rocm/lib"
+
+
 def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs_list = []
@@ -54,7 +72,9 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
             f.result()
     objs = [c[-1] for c in jobs_list]
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp], verbose)
+    rt = _runtime_dir()
+    _run(["g++", "-shared", "-fPIC", *objs, "-o", tmp, "-L" + rt, "-l:libamdhip64.so",
+          "-Wl,-rpath," + rt, "-Wl,--no-undefined"], verbose)
     os.replace(tmp, LIB)
     return LIB
 
