@@ -310,3 +310,97 @@ def test_batch_handle_matches_separate_problems():
         assert conv and rrp <= 1e-6
         assert abs(itp - ref.iters) <= 1
         assert np.linalg.norm(bs[p] - R.A @ xs[off:off + m]) <= 1e-6 * np.linalg.norm(bs[p]) * (1 + 1e-9)
+
+
+# ------------------------------------------------------------------ full sizes
+def covering(pb, wx, wy, i, j):
+    """Subdomains whose partition-of-unity weight is non-zero at node (i, j)."""
+    ps = [p for p in range(pb.Px) if wx[p][i] > 0]
+    qs = [q for q in range(pb.Py) if wy[q][j] > 0]
+    return [q * pb.Px + p for q in qs for p in ps]
+
+
+@pytest.mark.parametrize("precision,tol", [(rp.RAS_MIXED, 1e-4), (rp.RAS_FP64, 1e-12)])
+def test_k640_sampled_local_solves_and_apply(precision, tol):
+    """The benchmark's workload and launch configuration (k = 640, h = 1/1280,
+    32 x 32 subdomains, all in one launch): local solutions of sampled
+    subdomains and B^{-1} v at sampled unknowns against the oracle."""
+    pb = geometry.config_problem("k640")
+    H = setup_gpu(pb, precision)
+    desc = H.desc()
+    loc_off = np.concatenate([[0], np.cumsum([d[0] for d in desc])])
+    v = inputs.random_vector(pb.ndof, 21)
+    vd = dev(v)
+    xl = torch.zeros(H.nloc, dtype=torch.complex128, device="cuda")
+    rp.ras_pml_local_solve(H, vd, xl)
+    z = torch.zeros_like(vd)
+    rp.ras_pml_apply(H, vd, z)
+    xg, zg = host(xl), host(z)
+    wx, wy = geometry.pou_2d(pb)
+    rng = np.random.default_rng(5)
+    nodes = [(1, 1), (pb.Nc - 1, pb.Nc - 1), (653, 653), (40, 700), (41, 41)]
+    nodes += [tuple(int(t) for t in rng.integers(1, pb.Nc, 2)) for _ in range(4)]
+    ids = {0, 31, 992, 1023, 15, 528}
+    for (i, j) in nodes:
+        ids.update(covering(pb, wx, wy, i, j))
+    ids = sorted(ids)
+    R = ras.RasPml(pb, subset=ids, with_global=False)
+    ref = R.local_solve(v)
+    loc = {}
+    for m, s in enumerate(ids):
+        a = xg[loc_off[s]:loc_off[s + 1]]
+        b = R.local_part(ref, m)
+        assert relerr(a, b) <= tol, (s, relerr(a, b))
+        loc[s] = b
+    scale = np.abs(zg).max()
+    for (i, j) in nodes:
+        zi = 0.0
+        for s in covering(pb, wx, wy, i, j):
+            sd = R.sds[ids.index(s)]
+            zi += wx[sd.px.p][i] * wy[sd.py.p][j] * loc[s][int(sd.local_index(i, j))]
+        g = int(geometry.global_index(pb, i, j))
+        assert abs(zg[g] - zi) <= tol * scale, ((i, j), zg[g], zi)
+
+
+def test_k640_gmres_mixed_vs_fp64_and_true_residual():
+    pb = geometry.config_problem("k640")
+    f = inputs.centre_gaussian(pb.n_int, pb.G, 0.05)
+    xs = {}
+    for prec in (rp.RAS_MIXED, rp.RAS_FP64):
+        H = setup_gpu(pb, prec)
+        fd = dev(f)
+        b = torch.zeros_like(fd)
+        rp.ras_pml_rhs(H, fd, b)
+        x = torch.zeros_like(fd)
+        rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+        assert rc == rp.RAS_OK and rr <= 1e-6
+        xs[prec] = host(x)
+        bh = host(b)
+        H.close()
+    A, M1 = fem.assemble_global(pb)
+    # the oracle forms element areas from coordinate differences (|x| ~ 0.5,
+    # h ~ 8e-4 here), which costs about three digits: 1e-12, not 1e-14
+    assert np.linalg.norm(bh - fem.rhs(M1, f)) <= 1e-12 * np.linalg.norm(bh)
+    for prec, x in xs.items():
+        assert np.linalg.norm(bh - A @ x) <= 1e-6 * np.linalg.norm(bh) * (1 + 1e-9), prec
+    assert relerr(xs[rp.RAS_MIXED], xs[rp.RAS_FP64]) <= 1e-5
+
+
+def test_k160_gmres_mixed_against_full_oracle():
+    """k = 160, h = 1/320, 16 x 16 subdomains: the whole oracle solve."""
+    pb = geometry.config_problem("k160")
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.05))
+    ref = gmres.gmres(lambda x: R.A @ x, R.apply, b, rtol=1e-6, restart=100, maxit=500)
+    H = setup_gpu(pb, rp.RAS_MIXED)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, _ = rp.gmres_solve(H, dev(b), x, rtol=1e-6, restart=100, maxit=500)
+    assert rc == rp.RAS_OK
+    xs = host(x)
+    assert abs(it - ref.iters) <= 2, (it, ref.iters)
+    assert relerr(xs, ref.x) <= 1e-5
+    assert np.linalg.norm(b - R.A @ xs) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)
+    v = inputs.random_vector(pb.ndof, 8)
+    z = torch.zeros_like(x)
+    rp.ras_pml_apply(H, dev(v), z)
+    assert relerr(host(z), R.apply(v)) <= 1e-4
