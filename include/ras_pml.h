@@ -55,7 +55,8 @@ enum ras_status {
 enum { RAS_BC_IMP = 0, RAS_BC_DRCH = 1 };          /* local boundary condition */
 enum { RAS_POU_LINEAR = 0, RAS_POU_BOOLEAN = 1 };  /* partition of unity       */
 enum { RAS_MIXED = 0, RAS_FP64 = 1 };              /* local factor precision   */
-enum { RAS_FLAG_TIMING = 1 };                      /* record HIP events        */
+enum { RAS_FLAG_TIMING = 1,                        /* record HIP events        */
+       RAS_FLAG_UNFUSED_ARNOLDI = 2 };             /* one launch per MGS step  */
 
 typedef struct ras_pml_handle *ras_pml_t;
 

@@ -20,6 +20,7 @@ RAS_BC_IMP, RAS_BC_DRCH = 0, 1
 RAS_POU_LINEAR, RAS_POU_BOOLEAN = 0, 1
 RAS_MIXED, RAS_FP64 = 0, 1
 RAS_FLAG_TIMING = 1
+RAS_FLAG_UNFUSED_ARNOLDI = 2
 RAS_DESC_INTS = 24
 
 

@@ -44,6 +44,11 @@ void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, 
                     hipStream_t);
 void launch_update_x(const DevProb *, int, long long, const KState *, const int *, int,
                      const double2 *, long long, const double2 *, double2 *, hipStream_t);
+int arnoldi_block_capacity(int E, int *blocks_per_cu);
+hipError_t launch_arnoldi(int E, int nblocks, const DevProb *, const KState *, const ArnoldiBlock *,
+                          const double2 *, long long, const double2 *, double2 *, int, int,
+                          double2 *, double2 *, unsigned long long *, unsigned long long, int *,
+                          hipStream_t);
 
 constexpr int kRedBlocksHost = 512;
 
@@ -89,7 +94,16 @@ struct ras_pml_handle {
     int *d_active = nullptr;
     double2 *d_partials = nullptr, *d_redout = nullptr;
     unsigned int *d_counters = nullptr;
+    // fused Arnoldi step (cooperative launch); E = 0 selects the
+    // one-launch-per-projection path
+    int arn_E = -1, arn_nblocks = 0;
+    ArnoldiBlock *d_ablocks = nullptr;
+    double2 *d_part2 = nullptr;
+    unsigned long long *d_bar = nullptr;
+    unsigned long long bar_base = 0;
+    int *d_err = nullptr;
     KState *h_ks = nullptr;        // pinned
+    int *h_err = nullptr;          // pinned
     double2 *h_red = nullptr;      // pinned
     std::vector<int> res_iters;
     std::vector<double> res_relres;
@@ -205,10 +219,11 @@ ras_pml_handle::~ras_pml_handle() {
     void *ptrs[] = {d_probs, d_subs,  d_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
-                    d_redout, d_counters};
+                    d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err};
     for (void *p : ptrs) dfree(p);
     if (h_ks) (void)hipHostFree(h_ks);
     if (h_red) (void)hipHostFree(h_red);
+    if (h_err) (void)hipHostFree(h_err);
     for (int c = 0; c < C_NCAT; ++c)
         for (auto &p : ev[c]) pool.push_back(p);
     for (auto &p : pool) {
@@ -365,6 +380,57 @@ int build(ras_pml_handle *H, hipStream_t st) {
     return RAS_OK;
 }
 
+// Choose the register slice per thread (E unknowns) so that every block of
+// the fused Arnoldi step is co-resident, and build the block table.
+int plan_arnoldi(ras_pml_handle *H) {
+    H->arn_E = 0;
+    if (H->flags & RAS_FLAG_UNFUSED_ARNOLDI) return RAS_OK;
+    int dev = 0, cus = 0;
+    HCHK(H, hipGetDevice(&dev));
+    HCHK(H, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int coop = 0;
+    HCHK(H, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return RAS_OK;
+    for (int E : {8, 16}) {
+        int per_cu = 0;
+        if (arnoldi_block_capacity(E, &per_cu) != 0 || per_cu < 1) continue;
+        const long long cap = static_cast<long long>(per_cu) * cus;
+        const long long slice = 256LL * E;
+        long long need = 0;
+        for (const DevProb &P : H->hprobs) need += (P.ndof + slice - 1) / slice;
+        if (need > cap) continue;
+        std::vector<ArnoldiBlock> tab;
+        for (int p = 0; p < H->nprob; ++p) {
+            const DevProb &P = H->hprobs[p];
+            const int nb = static_cast<int>((P.ndof + slice - 1) / slice);
+            const int first = static_cast<int>(tab.size());
+            for (int b = 0; b < nb; ++b) {
+                ArnoldiBlock B{};
+                B.prob = p;
+                B.first_blk = first;
+                B.nblk = nb;
+                B.first = P.dof_off + b * slice;
+                B.n = static_cast<int>(std::min<long long>(slice, P.ndof - b * slice));
+                tab.push_back(B);
+            }
+        }
+        H->arn_nblocks = static_cast<int>(tab.size());
+        RCHK(dalloc(H, &H->d_ablocks, sizeof(ArnoldiBlock) * tab.size()));
+        RCHK(dalloc(H, &H->d_part2, sizeof(double2) * 2 * tab.size()));
+        const size_t bar_words = 32 * (tab.size() / 16 + 2);
+        RCHK(dalloc(H, &H->d_bar, sizeof(unsigned long long) * bar_words));
+        RCHK(dalloc(H, &H->d_err, sizeof(int)));
+        HCHK(H, hipMemcpy(H->d_ablocks, tab.data(), sizeof(ArnoldiBlock) * tab.size(),
+                          hipMemcpyHostToDevice));
+        HCHK(H, hipMemset(H->d_bar, 0, sizeof(unsigned long long) * bar_words));
+        HCHK(H, hipMemset(H->d_err, 0, sizeof(int)));
+        H->bar_base = 0;
+        H->arn_E = E;
+        return RAS_OK;
+    }
+    return RAS_OK;
+}
+
 int ensure_krylov(ras_pml_handle *H, int m) {
     if (H->m_alloc >= m) return RAS_OK;
     void *ptrs[] = {H->d_V, H->d_Z, H->d_r, H->d_H, H->d_g, H->d_sn, H->d_y, H->d_cs, H->d_hist};
@@ -391,9 +457,12 @@ int ensure_krylov(ras_pml_handle *H, int m) {
         RCHK(dalloc(H, &H->d_counters, sizeof(unsigned int) * P));
         HCHK(H, hipMemset(H->d_counters, 0, sizeof(unsigned int) * P));
         HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_ks), sizeof(KState) * P));
+        HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_err), sizeof(int)));
+        *H->h_err = 0;
         HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_red), sizeof(double2) * P));
     }
     H->m_alloc = m;
+    if (H->arn_E < 0) RCHK(plan_arnoldi(H));
     return RAS_OK;
 }
 
@@ -496,13 +565,23 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
             double2 *Vj1 = H->d_V + static_cast<long long>(j + 1) * n;
             double2 *Zj = H->d_Z + static_cast<long long>(j) * n;
             RCHK(do_apply(H, Vj, Zj, H->d_active, st));
-            {
-                Timer t(H, C_SPMV, st);
-                launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, n, Zj, nullptr, Vj1,
-                            st);
-            }
-            HCHK(H, hipGetLastError());
-            {
+            if (H->arn_E > 0) {
+                Timer t(H, C_MGS, st);
+                hipError_t e = launch_arnoldi(H->arn_E, H->arn_nblocks, H->d_probs, H->d_ks,
+                                              H->d_ablocks, H->d_coef, n, Zj, H->d_V, j, m, H->d_H,
+                                              H->d_part2, H->d_bar, H->bar_base, H->d_err, st);
+                if (e != hipSuccess) {
+                    H->last_error = std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e);
+                    return RAS_EHIP;
+                }
+                H->bar_base += static_cast<unsigned long long>(j + 2);
+            } else {
+                {
+                    Timer t(H, C_SPMV, st);
+                    launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, n, Zj, nullptr,
+                                Vj1, st);
+                }
+                HCHK(H, hipGetLastError());
                 Timer t(H, C_MGS, st);
                 for (int i = 0; i <= j; ++i)
                     launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, i, i == 0 ? 0 : 1, m,
@@ -518,7 +597,13 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
             }
             HCHK(H, hipGetLastError());
             HCHK(H, hipMemcpyAsync(H->h_ks, H->d_ks, sizeof(KState) * P, hipMemcpyDeviceToHost, st));
+            if (H->arn_E > 0)
+                HCHK(H, hipMemcpyAsync(H->h_err, H->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
             HCHK(H, hipStreamSynchronize(st));
+            if (H->arn_E > 0 && *H->h_err != 0) {
+                H->last_error = "grid barrier of the fused Arnoldi step timed out";
+                return RAS_EHIP;
+            }
             ++total;
             int still = 0;
             double worst = 0.0;

@@ -69,6 +69,16 @@ struct KState {
     int pad_;
 };
 
+// One block of the fused Arnoldi-step kernel: a contiguous slice of one
+// problem's unknowns.
+struct ArnoldiBlock {
+    int prob;        // problem of this block
+    int first_blk;   // first block of that problem
+    int nblk;        // blocks of that problem
+    int n;           // unknowns of this block (<= 256 E)
+    long long first; // first unknown (index into the concatenated vectors)
+};
+
 // Host-side plan of one problem.
 struct PlanProblem {
     double k, h, sigma;

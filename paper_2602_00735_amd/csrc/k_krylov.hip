@@ -299,6 +299,166 @@ __global__ void k_update_x(const DevProb *__restrict__ probs, const KState *__re
     st(x, g, acc);
 }
 
+// ---------------------------------------------------------------- fused step
+// Values exchanged between blocks inside one launch (partial sums) are
+// written and read with device-scope atomic accesses, which are coherent
+// across the XCDs without L2 write-back/invalidate fences; the store is
+// complete (s_waitcnt) before the arrival is counted.
+__device__ __forceinline__ void put_agent(double2 *p, cplx<double> v) {
+    __hip_atomic_store(&p->x, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->y, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ cplx<double> get_agent(const double2 *p) {
+    double2 *q = const_cast<double2 *>(p);
+    return {__hip_atomic_load(&q->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            __hip_atomic_load(&q->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+__device__ __forceinline__ unsigned long long peek(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier words, each on its own 256-byte line: [0] top arrivals,
+// [32 (g+1)] arrivals of group g, [32 (g+1) + 16] release epoch of group g.
+constexpr int kBarGroup = 16;           // blocks per group
+constexpr int kBarStride = 32;          // unsigned long long per line
+
+// Grid-wide barrier for a cooperative launch (every block co-resident).
+// Counters only grow: barrier `epoch` (absolute, counted since the handle
+// was created) completes when group g has epoch * size(g) arrivals and the
+// top word epoch * ngroups.  The first block of each group waits on the top
+// word and then publishes the epoch to its group.  Polls are bounded;
+// running out sets *err and lets the block continue (wrong numbers that the
+// host reports, never a hang).
+__device__ __forceinline__ bool spin_until(unsigned long long *p, unsigned long long target) {
+    unsigned int polls = 0;
+    while (peek(p) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++polls > (1u << 26)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned long long epoch,
+                                             int *err) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);          // this block's published values are complete
+        const int nb = gridDim.x;
+        const int ngroups = (nb + kBarGroup - 1) / kBarGroup;
+        const int g = blockIdx.x / kBarGroup;
+        const int gsize = min(kBarGroup, nb - g * kBarGroup);
+        unsigned long long *garr = bar + kBarStride * (g + 1);
+        unsigned long long *grel = garr + 16;
+        atomicAdd(garr, 1ull);
+        bool ok = true;
+        if (blockIdx.x % kBarGroup == 0) {
+            ok = spin_until(garr, epoch * gsize);
+            atomicAdd(bar, 1ull);
+            ok = spin_until(bar, epoch * ngroups) && ok;
+            __hip_atomic_store(grel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = spin_until(grel, epoch);
+        }
+        if (!ok) atomicOr(err, 1);
+    }
+    __syncthreads();
+}
+
+// Sum the problem's per-block partials in index order (every block of the
+// problem obtains the same value).
+__device__ cplx<double> problem_sum(const double2 *__restrict__ part, const ArnoldiBlock &B,
+                                    cplx<double> *sh) {
+    cplx<double> acc{0, 0};
+    for (int e = threadIdx.x; e < B.nblk; e += kRedThreads)
+        acc = cadd(acc, get_agent(part + B.first_blk + e));
+    return block_sum(acc, sh);
+}
+
+// One Arnoldi step for every problem in one launch:
+//   w = A z_j (7-point stencil);
+//   for i = 0..j: h_ij = <v_i, w>; w -= h_ij v_i   (modified Gram-Schmidt)
+//   h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}.
+// Each block keeps its slice of w (and the current v_i) in registers, so w is
+// never re-read; j + 2 grid barriers separate the reductions.  Problems not
+// in the cycle skip the arithmetic but take part in every barrier.
+template <int E>
+__global__ __launch_bounds__(kRedThreads) void k_arnoldi(
+    const DevProb *__restrict__ probs, const KState *__restrict__ ks,
+    const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef, long long ntot,
+    const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,
+    double2 *__restrict__ H, double2 *__restrict__ part2, unsigned long long *bar,
+    unsigned long long epoch0, int *err) {
+    __shared__ cplx<double> sh[kRedThreads];
+    const ArnoldiBlock B = blocks[blockIdx.x];
+    const int nblocks = gridDim.x;
+    const int p = B.prob;
+    const bool on = ks[p].in_cycle != 0;
+    const DevProb P = probs[p];
+    const int n1 = P.n1;
+    double2 *Hp = H + static_cast<long long>(p) * (m + 1) * m;
+    const long long col = static_cast<long long>(j) * (m + 1);
+    cplx<double> w[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int o = threadIdx.x + q * kRedThreads;
+        w[q] = cplx<double>{0, 0};
+        if (on && o < B.n) {
+            const long long g = B.first + o;
+            const long long idx = g - P.dof_off;
+            const int i = static_cast<int>(idx % n1) + 1;
+            const int jj = static_cast<int>(idx / n1) + 1;
+            const double2 *C = coef, *Ec = coef + ntot, *N = coef + 2 * ntot, *NE = coef + 3 * ntot;
+            cplx<double> acc = cmul(ld(C, g), ld(zj, g));
+            if (i < n1) acc = cfma(acc, ld(Ec, g), ld(zj, g + 1));
+            if (i > 1) acc = cfma(acc, ld(Ec, g - 1), ld(zj, g - 1));
+            if (jj < n1) acc = cfma(acc, ld(N, g), ld(zj, g + n1));
+            if (jj > 1) acc = cfma(acc, ld(N, g - n1), ld(zj, g - n1));
+            if (i < n1 && jj < n1) acc = cfma(acc, ld(NE, g), ld(zj, g + n1 + 1));
+            if (i > 1 && jj > 1) acc = cfma(acc, ld(NE, g - n1 - 1), ld(zj, g - n1 - 1));
+            w[q] = acc;
+        }
+    }
+    unsigned long long epoch = 0;
+    for (int i = 0; i <= j; ++i) {
+        const double2 *vi = V + static_cast<long long>(i) * ntot;
+        cplx<double> v[E];
+        cplx<double> acc{0, 0};
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int o = threadIdx.x + q * kRedThreads;
+            v[q] = (on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0};
+            acc = cdotacc(acc, v[q], w[q]);
+        }
+        double2 *part = part2 + static_cast<long long>(i & 1) * nblocks;
+        const cplx<double> bs = block_sum(acc, sh);
+        if (threadIdx.x == 0) put_agent(part + blockIdx.x, bs);
+        ++epoch;
+        grid_barrier(bar, epoch0 + epoch, err);
+        const cplx<double> h = problem_sum(part, B, sh);
+#pragma unroll
+        for (int q = 0; q < E; ++q) w[q] = cfms(w[q], h, v[q]);
+        if (on && blockIdx.x == B.first_blk && threadIdx.x == 0) st(Hp, col + i, h);
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) nrm = fma(w[q].re, w[q].re, fma(w[q].im, w[q].im, nrm));
+    double2 *part = part2 + static_cast<long long>((j + 1) & 1) * nblocks;
+    const cplx<double> bs = block_sum(cplx<double>{nrm, 0.0}, sh);
+    if (threadIdx.x == 0) put_agent(part + blockIdx.x, cplx<double>{bs.re, 0.0});
+    ++epoch;
+    grid_barrier(bar, epoch0 + epoch, err);
+    const double hn = sqrt(problem_sum(part, B, sh).re);
+    if (!on) return;
+    const double s = hn > 0.0 ? 1.0 / hn : 0.0;
+    double2 *vn = V + static_cast<long long>(j + 1) * ntot;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int o = threadIdx.x + q * kRedThreads;
+        if (o < B.n) st(vn, B.first + o, cscale(w[q], s));
+    }
+    if (blockIdx.x == B.first_blk && threadIdx.x == 0) st(Hp, col + j + 1, cplx<double>{hn, 0.0});
+}
+
 }  // namespace
 
 void launch_spmv(const DevProb *probs, int nprob, long long max_ndof, const int *active,
@@ -352,6 +512,32 @@ void launch_update_x(const DevProb *probs, int nprob, long long max_ndof, const 
                      const double2 *y, double2 *x, hipStream_t s) {
     dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
     hipLaunchKernelGGL(k_update_x, grid, dim3(256), 0, s, probs, ks, active, m, Z, ntot, y, x);
+}
+
+}  // namespace raspml
+
+namespace raspml {
+
+int arnoldi_block_capacity(int E, int *blocks_per_cu) {
+    int nb = 0;
+    hipError_t e = E <= 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_arnoldi<8>, kRedThreads, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_arnoldi<16>, kRedThreads, 0);
+    if (e != hipSuccess) return -1;
+    *blocks_per_cu = nb;
+    return 0;
+}
+
+hipError_t launch_arnoldi(int E, int nblocks, const DevProb *probs, const KState *ks,
+                          const ArnoldiBlock *blocks, const double2 *coef, long long ntot,
+                          const double2 *zj, double2 *V, int j, int m, double2 *H, double2 *part2,
+                          unsigned long long *bar, unsigned long long epoch0, int *err,
+                          hipStream_t s) {
+    void *args[] = {(void *)&probs, (void *)&ks, (void *)&blocks, (void *)&coef, (void *)&ntot,
+                    (void *)&zj, (void *)&V, (void *)&j, (void *)&m, (void *)&H, (void *)&part2,
+                    (void *)&bar, (void *)&epoch0, (void *)&err};
+    const void *fn = E <= 8 ? reinterpret_cast<const void *>(k_arnoldi<8>)
+                            : reinterpret_cast<const void *>(k_arnoldi<16>);
+    return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kRedThreads), args, 0, s);
 }
 
 }  // namespace raspml

@@ -404,3 +404,23 @@ def test_k160_gmres_mixed_against_full_oracle():
     z = torch.zeros_like(x)
     rp.ras_pml_apply(H, dev(v), z)
     assert relerr(host(z), R.apply(v)) <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["ragged", "k40_two_slot"])
+def test_fused_and_unfused_arnoldi_agree(name):
+    """The one-launch Arnoldi step (stencil SpMV + all MGS projections +
+    normalisation with grid barriers) and the one-launch-per-projection path
+    give the same iterations and solutions up to rounding order."""
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+    out = []
+    for flags in (0, rp.RAS_FLAG_UNFUSED_ARNOLDI):
+        H = setup_gpu(pb, rp.RAS_FP64, flags=flags)
+        x = torch.zeros_like(b)
+        rc, it, rr, hist = rp.gmres_solve(H, b, x, rtol=1e-8, restart=30, maxit=300)
+        assert rc == rp.RAS_OK
+        out.append((it, host(x), hist))
+    assert out[0][0] == out[1][0]
+    assert relerr(out[0][1], out[1][1]) <= 1e-12
+    assert np.allclose(out[0][2], out[1][2], rtol=1e-9, atol=1e-15)
