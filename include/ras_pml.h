@@ -174,8 +174,10 @@ int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *co
  *   export_local: 4 * n_local values for subdomain j in the local ordering:
  *     diagonal, fast-axis (+1), slow-axis (+n_fast), diagonal (+n_fast+1).
  *   export_factor: (n_pad * W) L entries of subdomain j, column c at
- *     c * W, row r at position r mod W (position c mod W holds 0), then
- *     n_pad values of D^{-1}; n_pad = n_local rounded up to 64.            */
+ *     c * W, row r at position r mod W (position c mod W holds 0); then the
+ *     same entries by rows (row r at r * W, column c at position c mod W,
+ *     position r mod W holds 0); then n_pad values of D^{-1};
+ *     n_pad = n_local rounded up to 64, 2 * n_pad * W + n_pad values.      */
 int ras_pml_export_stencil(ras_pml_t H, void *host_out);
 int ras_pml_export_local(ras_pml_t H, int j, void *host_out);
 int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_values);

@@ -319,14 +319,16 @@ def ras_pml_export_local(H: Handle, j, n_local):
 
 
 def ras_pml_export_factor(H: Handle, j, npad, W):
-    """Returns (L columns (npad, W), D^{-1} (npad,)) in slot order."""
+    """Returns (L by columns (npad, W), L by rows (npad, W), D^{-1} (npad,)),
+    both copies in slot order."""
     import numpy as np
-    cnt = npad * (W + 1)
+    cnt = npad * (2 * W + 1)
     out = np.zeros(cnt, dtype=np.complex128)
     rc = lib().ras_pml_export_factor(H.ptr, j, out.ctypes.data_as(_P), cnt)
     if rc:
         H._raise(rc)
-    return out[:npad * W].reshape(npad, W), out[npad * W:]
+    return (out[:npad * W].reshape(npad, W), out[npad * W:2 * npad * W].reshape(npad, W),
+            out[2 * npad * W:])
 
 
 def ras_pml_get_stats(H: Handle) -> dict:

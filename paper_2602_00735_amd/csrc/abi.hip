@@ -273,7 +273,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
             s.fac_off = static_cast<long long>(fac);
             s.vec_off = vec;
             s.loc_off = loc;
-            fac += static_cast<size_t>(s.npad) * (s.W + 1);
+            fac += static_cast<size_t>(s.npad) * (2 * s.W + 1);   // L, rows of L, D^{-1}
             vec += s.npad;
             loc += s.n;
             H->maxW = std::max(H->maxW, s.W);
@@ -306,7 +306,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
     double sb = 0.0, fb = 0.0;
     for (const DevSub &s : H->hsubs) {
         sb += (2.0 * s.npad * s.W + s.npad + 3.0 * s.npad) * H->csize + 16.0 * s.n;
-        fb += static_cast<double>(s.npad) * (s.W + 1) * H->csize;
+        fb += static_cast<double>(s.npad) * (2 * s.W + 1) * H->csize;
     }
     H->stats.solve_bytes = sb;
     H->stats.factor_bytes = fb;
@@ -321,6 +321,8 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_coef, sizeof(double2) * 4 * H->ntot));
     RCHK(dalloc(H, &H->d_lst, sizeof(double2) * 4 * H->nloc));
     RCHK(dalloc(H, &H->d_F, H->csize * fac));
+    // rows of L are written scattered; positions before row 0 must read 0
+    HCHK(H, hipMemsetAsync(H->d_F, 0, H->csize * fac, st));
     RCHK(dalloc(H, &H->d_ybuf, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_xout, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_status, sizeof(int) * H->nsub));
@@ -897,7 +899,7 @@ int ras_pml_export_local(ras_pml_t H, int j, void *host_out) {
 int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_values) {
     if (!H || !host_out || j < 0 || j >= H->nsub) return RAS_EINVAL;
     const DevSub &s = H->hsubs[j];
-    const long long cnt = static_cast<long long>(s.npad) * (s.W + 1);
+    const long long cnt = static_cast<long long>(s.npad) * (2 * s.W + 1);
     if (cap_values < cnt) {
         H->last_error = "export_factor: capacity too small";
         return RAS_EINVAL;

@@ -65,6 +65,14 @@ __device__ __forceinline__ cplx<T> crecip(cplx<T> a) {
 }
 template <typename T>
 __device__ __forceinline__ T cabs2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+// c ? a : b per component (keeps the select in registers)
+template <typename T>
+__device__ __forceinline__ cplx<T> csel(bool c, cplx<T> a, cplx<T> b) {
+    cplx<T> r;
+    r.re = c ? a.re : b.re;
+    r.im = c ? a.im : b.im;
+    return r;
+}
 
 template <typename T, typename U>
 __device__ __forceinline__ cplx<T> ccast(cplx<U> a) {

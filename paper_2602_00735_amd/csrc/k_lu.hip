@@ -14,7 +14,9 @@
 //   2. every thread forms l = column / pivot and applies the rank-1 update
 //      S -= l u^T to its slots;
 //   3. L[:, c] is written in slot order (row r at position r mod W, the
-//      pivot position holds 0), D^{-1}_c separately;
+//      pivot position holds 0), D^{-1}_c separately, and every entry L[r, c]
+//      also into row r of a second, row-ordered copy R (position c mod W) so
+//      that the backward sweep can run in column form too;
 //   4. the retired slot receives the band row/column c + W, whose only
 //      non-zeros are the 7-point stencil couplings (diagonal, fast -1,
 //      slow -n_fast, diagonal -n_fast-1), staged in LDS one block of 64 rows
@@ -96,7 +98,8 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
     const int ty = tid / TX, tx = tid % TX;
     const double2 *lst = lst_all + 4 * S.loc_off;
     cplx<T> *L = F + S.fac_off;
-    cplx<T> *Dinv = L + static_cast<long long>(npad) * W;
+    cplx<T> *Rw = L + static_cast<long long>(npad) * W;        // rows of L
+    cplx<T> *Dinv = Rw + static_cast<long long>(npad) * W;
 
     cplx<T> A[RY][RX];
 #pragma unroll
@@ -157,10 +160,14 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
         for (int a = 0; a < RY; ++a)
 #pragma unroll
             for (int b = 0; b < RX; ++b) A[a][b] = cfms(A[a][b], l[a], u[b]);
-        // 3. write L[:, c] in slot order and D^{-1}_c
-        for (int p = tid; p < W; p += NT)
-            L[static_cast<long long>(c) * W + p] =
-                (p == sl) ? cplx<T>{0, 0} : cmul(ubuf[buf][p], dinv);
+        // 3. write L[:, c] in slot order, each entry also into its row of R,
+        //    and D^{-1}_c; slot p holds row c + ((p - sl) mod W)
+        for (int p = tid; p < W; p += NT) {
+            const cplx<T> lv = (p == sl) ? cplx<T>{0, 0} : cmul(ubuf[buf][p], dinv);
+            L[static_cast<long long>(c) * W + p] = lv;
+            const int r = c + (p >= sl ? p - sl : p - sl + W);
+            if (r < npad) Rw[static_cast<long long>(r) * W + sl] = lv;
+        }
         if (tid == 0) Dinv[c] = dinv;
         // 4. band row/column c + W enters slot sl
         const cplx<T> *nr = newrow[(c >> 6) & 1][c & 63];

@@ -3,20 +3,21 @@
 //
 // k_band_solve: one wave64 per subdomain (largest first).  With
 // A_j = L D L^T it runs
-//   forward   L y = R_j v  (column form: y_c is final, then every row below
-//             it in the band takes -L[r,c] y_c),
-//   diagonal  z = D^{-1} y,
-//   backward  L^T x = z    (dot form: x_c = z_c - sum_r L[r,c] x_r over the
-//             band rows below c).
-// Both sweeps keep the band rows of the current window in registers as a
-// ring spread over the lanes: row r lives in slot r mod W, slot s in lane
-// s mod 64 (second register for slots 64..127).  Factor column c is stored in
-// the same slot order, so each step reads one contiguous column, fully
-// coalesced, prefetched PD steps ahead into registers.  The pivot value is
-// broadcast with v_readlane, incoming right-hand-side values and the
-// outputs move with v_writelane; the backward dot product is a DPP wave sum.
-// The restricted right-hand side R_j v is gathered from the global complex128
-// vector one block of 64 rows ahead and converted to the factor precision.
+//   forward   L y = R_j v   and   backward   L^T x = D^{-1} y,
+// both in column form: once the pivot value of row c is final, every other
+// row of the band window takes -(factor entry) * pivot.  The forward reads
+// column c of L, the backward row c of L (the factorisation stores L both
+// ways), so both sweeps are the same short step: one v_readlane broadcast of
+// the pivot, one complex FMA per ring slot, one LDS write of the output.
+// The window rows live in registers as a ring spread over the lanes: row r
+// in slot r mod W, slot s in lane s mod 64 (a second register for slots
+// 64..127).  Factor vectors are stored in the same slot order, so a step
+// reads one contiguous, coalesced vector, prefetched PD steps ahead into
+// registers.  A slot whose row is finished is not reset: it keeps
+// accumulating for the row W further on, and when that row's block of 64
+// steps starts the slot is corrected by (right-hand side - finished value),
+// read from an LDS history of the last 128 outputs (for W <= 64 the
+// right-hand side enters the slot at retirement instead).
 //
 // k_pou_sum: deterministic partition-of-unity weighted sum of the local
 // solutions into z (fixed summation order, complex128).
@@ -66,9 +67,8 @@ __device__ __forceinline__ cplx<T> gather_rhs(const DevSub &S, int dof_off, int 
 }
 
 // Column `col` of L in slot order.  Lanes past the column end re-read its
-// last entry (always in bounds, no branch): their ring registers are never
-// read in the forward sweep and stay exactly zero in the backward sweep, so
-// those values never reach a result.
+// last entry (always in bounds, no branch): the ring registers of those
+// lanes hold no slot and are never read.
 template <typename T, bool TWO>
 __device__ __forceinline__ void load_col(const cplx<T> *__restrict__ L, int W, int col, int lane,
                                          cplx<T> &lo, cplx<T> &hi) {
@@ -77,99 +77,163 @@ __device__ __forceinline__ void load_col(const cplx<T> *__restrict__ L, int W, i
     if (TWO) hi = p[min(lane + 64, W - 1)];
 }
 
-// PD: factor prefetch depth in columns (divides 64).
+// Offset of slot s (held by this lane) from slot `sl` in the ring, in the
+// direction of the sweep: the slot holds row (pivot row) +/- that offset.
+__device__ __forceinline__ int ring_offset(int s, int sl, int W, bool down) {
+    int t = down ? sl - s : s - sl;
+    return t < 0 ? t + W : t;
+}
+
+// Both sweeps for one subdomain.  TWO: the ring has a second register
+// (W > 64, block correction); otherwise W <= 64 and incoming rows enter at
+// retirement.  PD: factor prefetch depth in vectors (divides 64).
 template <typename T, bool TWO, int PD>
-__global__ __launch_bounds__(64) void k_band_solve(const DevProb *__restrict__ probs,
-                                                   const DevSub *__restrict__ subs,
-                                                   const int *__restrict__ order,
-                                                   const int *__restrict__ active,
-                                                   const double2 *__restrict__ v,
-                                                   const cplx<T> *__restrict__ F,
-                                                   cplx<T> *__restrict__ ybuf,
-                                                   cplx<T> *__restrict__ xout) {
-    const int s = order[blockIdx.x];
-    const DevSub S = subs[s];
-    if (active != nullptr && active[S.prob] == 0) return;
+__device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ probs, const DevSub &S,
+                                                const double2 *__restrict__ v,
+                                                const cplx<T> *__restrict__ F,
+                                                cplx<T> *__restrict__ ybuf,
+                                                cplx<T> *__restrict__ xout, cplx<T> *hist,
+                                                cplx<T> *inc) {
     const int dof_off = static_cast<int>(probs[S.prob].dof_off);
     const int n1 = probs[S.prob].n1;
     const int lane = threadIdx.x;
     const int W = S.W, npad = S.npad;
-    const cplx<T> *L = F + S.fac_off;
-    const cplx<T> *Dv = L + static_cast<long long>(npad) * W;
+    const long long NW = static_cast<long long>(npad) * W;
+    const cplx<T> *L = F + S.fac_off;          // columns of L
+    const cplx<T> *Rw = L + NW;                 // rows of L
+    const cplx<T> *Dv = Rw + NW;                // D^{-1}
     cplx<T> *yb = ybuf + S.vec_off;
     cplx<T> *xo = xout + S.vec_off;
+    const cplx<T> zero{0, 0};
+    const bool hi_ok = lane + 64 < W;
 
-    __shared__ cplx<T> stage[64];     // per-step outputs of one block of 64 rows
+    auto pivot = [&](const cplx<T> &lo, const cplx<T> &hi, int q) {
+        return readlane(csel(!TWO || q < 64, lo, hi), q & 63);
+    };
+    // block correction (W > 64): the slot of every row r of the block gets
+    // rhs_r - (finished value of the row W before it)
+    auto correct = [&](cplx<T> &lo, cplx<T> &hi, int sl, int rfirst, bool down) {
+        __builtin_amdgcn_wave_barrier();
+        const int tlo = ring_offset(lane, sl, W, down);
+        const int thi = ring_offset(lane + 64, sl, W, down);
+        const int qlo = down ? 63 - tlo : tlo, qhi = down ? 63 - thi : thi;   // index into inc
+        const int rlo = rfirst + qlo, rhi = rfirst + qhi;                     // rows
+        const int olo = down ? rlo + W : rlo - W, ohi = down ? rhi + W : rhi - W;
+        const cplx<T> dlo = csub(inc[min(max(qlo, 0), 63)], hist[olo & 127]);
+        const cplx<T> dhi = csub(inc[min(max(qhi, 0), 63)], hist[ohi & 127]);
+        lo = cadd(lo, csel(tlo < 64, dlo, zero));
+        if (TWO) hi = cadd(hi, csel(hi_ok && thi < 64, dhi, zero));
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    cplx<T> flo[PD], fhi[PD];
+    hist[lane] = zero;
+    hist[lane + 64] = zero;
 
     // ------------------------------------------------------------ forward
-    cplx<T> ylo = gather_rhs<T>(S, dof_off, n1, v, lane);
-    cplx<T> yhi{0, 0};
-    if (TWO) yhi = gather_rhs<T>(S, dof_off, n1, v, lane + 64);
-    if (lane >= W) ylo = cplx<T>{0, 0};
-    if (lane + 64 >= W) yhi = cplx<T>{0, 0};
-    cplx<T> rnext = gather_rhs<T>(S, dof_off, n1, v, W + lane);
-    cplx<T> flo[PD], fhi[PD];
+    cplx<T> ylo = zero, yhi = zero;
+    if (!TWO) ylo = csel(lane < W, gather_rhs<T>(S, dof_off, n1, v, lane), zero);
 #pragma unroll
     for (int u = 0; u < PD; ++u) load_col<T, TWO>(L, W, min(u, npad - 1), lane, flo[u], fhi[u]);
+    // rows of the next block: TWO -> rows whose pivot step is in it,
+    // one register -> rows entering the window during it
+    const int ahead = TWO ? 0 : W;
+    cplx<T> rnext = gather_rhs<T>(S, dof_off, n1, v, ahead + lane);
     int sl = 0;
     for (int c0 = 0; c0 < npad; c0 += 64) {
-        // rows entering the window during this block: c0 + W + t
-        // rows entering during this block were gathered one block ago; the
-        // next block's rows are gathered now and converted after the steps
         const cplx<T> rblk = rnext;
-        const double2 rraw = gather_raw(S, dof_off, n1, v, c0 + 64 + W + lane);
+        const double2 rraw = gather_raw(S, dof_off, n1, v, c0 + 64 + ahead + lane);
+        if (TWO) {
+            inc[lane] = rblk;
+            correct(ylo, yhi, sl, c0, false);
+        }
 #pragma unroll
         for (int t = 0; t < 64; ++t) {
             const int u = t % PD;
             const int c = c0 + t;
-            const cplx<T> yc = readlane((!TWO || sl < 64) ? ylo : yhi, sl & 63);
-            ylo = cfms(ylo, flo[u], yc);
-            if (TWO) yhi = cfms(yhi, fhi[u], yc);
-            const cplx<T> rin = readlane(rblk, t);
-            ylo = writelane(ylo, rin, sl);
-            if (TWO) yhi = writelane(yhi, rin, sl - 64);
-            stage[t] = yc;                              // same value from every lane
+            const cplx<T> piv = pivot(ylo, yhi, sl);                 // y_c
+            ylo = cfms(ylo, flo[u], piv);
+            if (TWO) yhi = cfms(yhi, fhi[u], piv);
+            if (!TWO) ylo = writelane(ylo, readlane(rblk, t), sl);   // row c + W enters
+            hist[c & 127] = piv;                                    // same value from every lane
             load_col<T, TWO>(L, W, min(c + PD, npad - 1), lane, flo[u], fhi[u]);
             sl = (sl + 1 == W) ? 0 : sl + 1;
             __builtin_amdgcn_sched_barrier(0);   // keep each step's loads in place
         }
-        rnext = to_T<T>(rraw, c0 + 64 + W + lane < S.n);
+        rnext = to_T<T>(rraw, c0 + 64 + ahead + lane < S.n);
         __builtin_amdgcn_wave_barrier();
-        yb[c0 + lane] = stage[lane];
+        yb[c0 + lane] = hist[(c0 + lane) & 127];
         __builtin_amdgcn_wave_barrier();
     }
 
     // ------------------------------------------------------------ backward
-    cplx<T> xlo{0, 0}, xhi{0, 0};
-    cplx<T> znext = cmul(yb[npad - 64 + lane], Dv[npad - 64 + lane]);
+    // L^T x = z with z = D^{-1} y: after x_c is final, rows r < c in the
+    // window take -L[c, r] x_c, i.e. row c of L.
+    hist[lane] = zero;
+    hist[lane + 64] = zero;
+    cplx<T> xlo = zero, xhi = zero;
+    // z of the rows of the next block: TWO -> rows whose pivot step is in it
+    // (c0 .. c0+63), one register -> rows entering the window (c0-W .. c0+63-W)
+    const int behind = TWO ? 0 : W;
+    auto zrow = [&](int r) {           // z_r, 0 for r < 0
+        const int rr = max(r, 0);
+        return csel(r >= 0, cmul(yb[rr], Dv[rr]), zero);
+    };
+    if (!TWO) {
+        const int r0 = npad - 1 - ((npad - 1 - lane) % W + W) % W;   // row of slot `lane`
+        xlo = csel(lane < W && r0 >= npad - W, zrow(r0), zero);
+    }
 #pragma unroll
-    for (int u = 0; u < PD; ++u) load_col<T, TWO>(L, W, max(npad - 1 - u, 0), lane, flo[u], fhi[u]);
+    for (int u = 0; u < PD; ++u) load_col<T, TWO>(Rw, W, max(npad - 1 - u, 0), lane, flo[u], fhi[u]);
     sl = (npad - 1) % W;
+    cplx<T> znext = zrow(npad - 64 - behind + lane);
     for (int c0 = npad - 64; c0 >= 0; c0 -= 64) {
         const cplx<T> zblk = znext;
-        const cplx<T> ynx = yb[max(c0 - 64, 0) + lane];
-        const cplx<T> dnx = Dv[max(c0 - 64, 0) + lane];
+        const int rn = c0 - 64 - behind + lane;
+        const cplx<T> ynx = yb[max(rn, 0)];
+        const cplx<T> dnx = Dv[max(rn, 0)];
+        if (TWO) {
+            inc[lane] = zblk;
+            correct(xlo, xhi, sl, c0, true);
+        }
 #pragma unroll
         for (int q = 0; q < 64; ++q) {
             const int t = 63 - q;
             const int u = q % PD;
             const int c = c0 + t;
-            cplx<T> p = cmul(flo[u], xlo);
-            if (TWO) p = cfma(p, fhi[u], xhi);
-            const cplx<T> sum = wave_sum(p);
-            const cplx<T> xc = csub(readlane(zblk, t), sum);
-            xlo = writelane(xlo, xc, sl);
-            if (TWO) xhi = writelane(xhi, xc, sl - 64);
-            stage[t] = xc;
-            load_col<T, TWO>(L, W, max(c - PD, 0), lane, flo[u], fhi[u]);
+            const cplx<T> piv = pivot(xlo, xhi, sl);                 // x_c
+            xlo = cfms(xlo, flo[u], piv);
+            if (TWO) xhi = cfms(xhi, fhi[u], piv);
+            if (!TWO) xlo = writelane(xlo, readlane(zblk, t), sl);   // row c - W enters
+            hist[c & 127] = piv;
+            load_col<T, TWO>(Rw, W, max(c - PD, 0), lane, flo[u], fhi[u]);
             sl = (sl == 0) ? W - 1 : sl - 1;
             __builtin_amdgcn_sched_barrier(0);
         }
-        znext = cmul(ynx, dnx);
+        znext = csel(rn >= 0, cmul(ynx, dnx), zero);
         __builtin_amdgcn_wave_barrier();
-        xo[c0 + lane] = stage[lane];
+        xo[c0 + lane] = hist[(c0 + lane) & 127];
         __builtin_amdgcn_wave_barrier();
     }
+}
+
+// One wave per SIMD by design (1024 subdomains on 1024 SIMDs at k = 640):
+// the whole register file is available to the prefetch ring.  A launch built
+// for W up to 128 still solves its subdomains with W <= 64 in the
+// one-register form (uniform branch per subdomain).
+template <typename T, bool TWO, int PD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_band_solve(
+    const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
+    const int *__restrict__ order, const int *__restrict__ active, const double2 *__restrict__ v,
+    const cplx<T> *__restrict__ F, cplx<T> *__restrict__ ybuf, cplx<T> *__restrict__ xout) {
+    __shared__ cplx<T> hist[128];               // outputs, by row mod 128
+    __shared__ cplx<T> inc[64];                 // right-hand side of the current block
+    const DevSub S = subs[order[blockIdx.x]];
+    if (active != nullptr && active[S.prob] == 0) return;
+    if (TWO && S.W > 64)
+        solve_subdomain<T, true, PD>(probs, S, v, F, ybuf, xout, hist, inc);
+    else
+        solve_subdomain<T, false, PD>(probs, S, v, F, ybuf, xout, hist, inc);
 }
 
 // z = sum over subdomains covering the node of chi_x * chi_y * x_local.

@@ -129,12 +129,17 @@ def test_factors(name, precision):
     for m, sd in enumerate(R.sds[:4]):
         W = sd.band + 1
         npad = (sd.n + 63) // 64 * 64
-        Lcols, Dinv = rp.ras_pml_export_factor(H, m, npad, W)
+        Lcols, Lrows, Dinv = rp.ras_pml_export_factor(H, m, npad, W)
         LU = R.batch.factors(m)
         b = sd.band
         n = sd.n
         # slot position c mod W of column c holds 0
         assert np.all(Lcols[np.arange(npad), np.arange(npad) % W] == 0)
+        # the row copy holds the same entries: L[r, c] at row r, position c mod W
+        for c in range(npad):
+            for r in range(c + 1, min(c + W, npad)):
+                assert Lrows[r, c % W] == Lcols[c, r % W]
+        assert np.all(Lrows[np.arange(npad), np.arange(npad) % W] == 0)
         D = LU[:, b]
         assert np.abs(1.0 / Dinv[:n] - D).max() <= tol * np.abs(D).max()
         assert np.allclose(Dinv[n:], 1.0)
