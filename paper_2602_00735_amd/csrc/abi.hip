@@ -320,9 +320,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_pw, sizeof(double) * pw.size()));
     RCHK(dalloc(H, &H->d_coef, sizeof(double2) * 4 * H->ntot));
     RCHK(dalloc(H, &H->d_lst, sizeof(double2) * 4 * H->nloc));
-    RCHK(dalloc(H, &H->d_F, H->csize * fac));
-    // rows of L are written scattered; positions before row 0 must read 0
-    HCHK(H, hipMemsetAsync(H->d_F, 0, H->csize * fac, st));
+    RCHK(dalloc(H, &H->d_F, H->csize * fac + kFactorSlack));
     RCHK(dalloc(H, &H->d_ybuf, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_xout, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_status, sizeof(int) * H->nsub));
@@ -914,6 +912,11 @@ int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_valu
         HCHK(H, hipMemcpy(tmp.data(), src, 8 * cnt, hipMemcpyDeviceToHost));
         for (long long i = 0; i < 2 * cnt; ++i) out[i] = tmp[i];
     }
+    // the device keeps the rows of L last row first; export them in row order
+    const long long rw = 2LL * s.W;                       // doubles per row
+    double *rows = out + 2LL * s.npad * s.W;
+    for (int i = 0, k = s.npad - 1; i < k; ++i, --k)
+        for (long long e = 0; e < rw; ++e) std::swap(rows[i * rw + e], rows[k * rw + e]);
     return RAS_OK;
 }
 

@@ -94,13 +94,19 @@ __device__ __forceinline__ double readlane(double v, int l) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) |
                                 static_cast<unsigned int>(lo));
 }
-// Replace lane l of `old` by the (wave-uniform) value v: a lane compare and
-// a select (v_cmp + v_cndmask).
+// Replace lane l of `old` by the (wave-uniform) value v: v_writelane_b32.
+// The compiler exposes the instruction only as an LLVM intrinsic.
+extern "C" __device__ int raspml_writelane_i32(int v, int lane, int old) __asm(
+    "llvm.amdgcn.writelane.i32");
 __device__ __forceinline__ float writelane(float old, float v, int l) {
-    return lane_id() == l ? v : old;
+    return __int_as_float(raspml_writelane_i32(__float_as_int(v), l, __float_as_int(old)));
 }
 __device__ __forceinline__ double writelane(double old, double v, int l) {
-    return lane_id() == l ? v : old;
+    const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+    const int lo = raspml_writelane_i32(static_cast<int>(b), l, static_cast<int>(o));
+    const int hi = raspml_writelane_i32(static_cast<int>(b >> 32), l, static_cast<int>(o >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<unsigned int>(lo));
 }
 template <typename T>
 __device__ __forceinline__ cplx<T> readlane(cplx<T> v, int l) {
@@ -108,8 +114,7 @@ __device__ __forceinline__ cplx<T> readlane(cplx<T> v, int l) {
 }
 template <typename T>
 __device__ __forceinline__ cplx<T> writelane(cplx<T> old, cplx<T> v, int l) {
-    const bool me = lane_id() == l;
-    return {me ? v.re : old.re, me ? v.im : old.im};
+    return {writelane(old.re, v.re, l), writelane(old.im, v.im, l)};
 }
 
 // ---- DPP wave64 sum; the total ends in lane 63.

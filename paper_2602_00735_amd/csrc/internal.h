@@ -17,6 +17,10 @@ constexpr int kMaxW = 128;
 constexpr int kMaxPou = 4;
 // Local vectors and factor columns are padded to a multiple of this.
 constexpr int kPad = 64;
+// The band solve reads each subdomain's factor as one stream and prefetches
+// up to 32 vectors (at most 32 KB) past its end; the factor allocation ends
+// with this much slack so that the last subdomain's over-read stays inside.
+constexpr int kFactorSlack = 65536;
 
 // Flags of a subdomain descriptor.
 enum : int {

@@ -3,7 +3,8 @@
 // The paper does not name its local solver; its setup/solve split (Table 4)
 // is read as one factorisation of every local operator, reused by every
 // preconditioner application.  A_j is complex symmetric (A_j = A_j^T), so its
-// no-pivot LU is U = D L^T and only L and D are stored.
+// no-pivot LU is U = D L^T: L (twice, by columns and by rows) and D^{-1}
+// are stored, never U.
 //
 // One workgroup factorises one subdomain.  The active (W x W) window of the
 // band, W = half-bandwidth + 1, lives in registers as a ring: band row r sits
@@ -16,7 +17,9 @@
 //   3. L[:, c] is written in slot order (row r at position r mod W, the
 //      pivot position holds 0), D^{-1}_c separately, and every entry L[r, c]
 //      also into row r of a second, row-ordered copy R (position c mod W) so
-//      that the backward sweep can run in column form too;
+//      that the backward sweep can run in column form too.  R holds its rows
+//      last row first: the backward sweep then reads it front to back, and the
+//      two sweeps together read one contiguous stream [L | R];
 //   4. the retired slot receives the band row/column c + W, whose only
 //      non-zeros are the 7-point stencil couplings (diagonal, fast -1,
 //      slow -n_fast, diagonal -n_fast-1), staged in LDS one block of 64 rows
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
     const int ty = tid / TX, tx = tid % TX;
     const double2 *lst = lst_all + 4 * S.loc_off;
     cplx<T> *L = F + S.fac_off;
-    cplx<T> *Rw = L + static_cast<long long>(npad) * W;        // rows of L
+    cplx<T> *Rw = L + static_cast<long long>(npad) * W;        // rows of L, last first
     cplx<T> *Dinv = Rw + static_cast<long long>(npad) * W;
 
     cplx<T> A[RY][RX];
@@ -110,6 +113,12 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
             A[a][b] = (rs < W && cs < W) ? initial_entry<T>(lst, n, nf, rs, cs) : cplx<T>{0, 0};
         }
     for (int i = tid; i < 2 * MW; i += NT) ubuf[i / MW][i % MW] = cplx<T>{0, 0};
+    // Row r < W of R has no columns before 0 at positions r+1 .. W-1; every
+    // other entry of L, R and D^{-1} is written by the column loop below.
+    for (int i = tid; i < W * W; i += NT) {
+        const int r = i / W, q = i % W;
+        if (q > r && r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + q] = cplx<T>{0, 0};
+    }
     for (int i = tid; i < W; i += NT) {
         cplx<T> d = initial_entry<T>(lst, n, nf, i, i);
         dorig[i] = sqrt(cabs2(d));
@@ -166,7 +175,7 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
             const cplx<T> lv = (p == sl) ? cplx<T>{0, 0} : cmul(ubuf[buf][p], dinv);
             L[static_cast<long long>(c) * W + p] = lv;
             const int r = c + (p >= sl ? p - sl : p - sl + W);
-            if (r < npad) Rw[static_cast<long long>(r) * W + sl] = lv;
+            if (r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + sl] = lv;
         }
         if (tid == 0) Dinv[c] = dinv;
         // 4. band row/column c + W enters slot sl

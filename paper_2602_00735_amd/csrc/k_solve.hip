@@ -6,18 +6,25 @@
 //   forward   L y = R_j v   and   backward   L^T x = D^{-1} y,
 // both in column form: once the pivot value of row c is final, every other
 // row of the band window takes -(factor entry) * pivot.  The forward reads
-// column c of L, the backward row c of L (the factorisation stores L both
-// ways), so both sweeps are the same short step: one v_readlane broadcast of
-// the pivot, one complex FMA per ring slot, one LDS write of the output.
+// column c of L, the backward row c of L; the factorisation stores the
+// columns, then the rows last row first, so the two sweeps read one
+// contiguous stream of W complex values per step, which a single pointer
+// walks PD vectors ahead of the arithmetic (prefetch into registers).  Each
+// step is one v_readlane broadcast of the pivot, one complex FMA per ring
+// slot and a v_writelane of the pivot into the block's output register.
 // The window rows live in registers as a ring spread over the lanes: row r
 // in slot r mod W, slot s in lane s mod 64 (a second register for slots
-// 64..127).  Factor vectors are stored in the same slot order, so a step
-// reads one contiguous, coalesced vector, prefetched PD steps ahead into
-// registers.  A slot whose row is finished is not reset: it keeps
+// 64..127).  A slot whose row is finished is not reset: it keeps
 // accumulating for the row W further on, and when that row's block of 64
 // steps starts the slot is corrected by (right-hand side - finished value),
 // read from an LDS history of the last 128 outputs (for W <= 64 the
 // right-hand side enters the slot at retirement instead).
+//
+// The stream pointer is not clamped at the ends: the prefetch runs up to PD
+// vectors past the last backward row (into D^{-1}, the next subdomain, or
+// the allocation's slack); those vectors are loaded and never used.  Lanes
+// past the vector end re-read its last entry (their ring registers hold no
+// slot).
 //
 // k_pou_sum: deterministic partition-of-unity weighted sum of the local
 // solutions into z (fixed summation order, complex128).
@@ -52,29 +59,7 @@ __device__ __forceinline__ cplx<T> to_T(double2 x, bool in) {
 template <typename T>
 __device__ __forceinline__ cplx<T> gather_rhs(const DevSub &S, int dof_off, int n1,
                                               const double2 *__restrict__ v, int r0) {
-    const int r = min(r0, S.n - 1);
-    int i, j;
-    if (S.xfast) {
-        i = S.ix0 + r % S.nf;
-        j = S.jy0 + r / S.nf;
-    } else {
-        j = S.jy0 + r % S.nf;
-        i = S.ix0 + r / S.nf;
-    }
-    const double2 x = v[static_cast<long long>(dof_off) + static_cast<long long>(j - 1) * n1 + (i - 1)];
-    const bool in = r0 < S.n;
-    return cplx<T>{in ? static_cast<T>(x.x) : T(0), in ? static_cast<T>(x.y) : T(0)};
-}
-
-// Column `col` of L in slot order.  Lanes past the column end re-read its
-// last entry (always in bounds, no branch): the ring registers of those
-// lanes hold no slot and are never read.
-template <typename T, bool TWO>
-__device__ __forceinline__ void load_col(const cplx<T> *__restrict__ L, int W, int col, int lane,
-                                         cplx<T> &lo, cplx<T> &hi) {
-    const cplx<T> *p = L + static_cast<long long>(col) * W;
-    lo = p[min(lane, W - 1)];
-    if (TWO) hi = p[min(lane + 64, W - 1)];
+    return to_T<T>(gather_raw(S, dof_off, n1, v, r0), r0 < S.n);
 }
 
 // Offset of slot s (held by this lane) from slot `sl` in the ring, in the
@@ -86,7 +71,7 @@ __device__ __forceinline__ int ring_offset(int s, int sl, int W, bool down) {
 
 // Both sweeps for one subdomain.  TWO: the ring has a second register
 // (W > 64, block correction); otherwise W <= 64 and incoming rows enter at
-// retirement.  PD: factor prefetch depth in vectors (divides 64).
+// retirement.  PD: prefetch depth in vectors (divides 64).
 template <typename T, bool TWO, int PD>
 __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ probs, const DevSub &S,
                                                 const double2 *__restrict__ v,
@@ -99,13 +84,13 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
     const int lane = threadIdx.x;
     const int W = S.W, npad = S.npad;
     const long long NW = static_cast<long long>(npad) * W;
-    const cplx<T> *L = F + S.fac_off;          // columns of L
-    const cplx<T> *Rw = L + NW;                 // rows of L
-    const cplx<T> *Dv = Rw + NW;                // D^{-1}
+    const cplx<T> *L = F + S.fac_off;          // [columns of L | rows of L, last first]
+    const cplx<T> *Dv = L + 2 * NW;             // D^{-1}
     cplx<T> *yb = ybuf + S.vec_off;
     cplx<T> *xo = xout + S.vec_off;
     const cplx<T> zero{0, 0};
     const bool hi_ok = lane + 64 < W;
+    const int olo = min(lane, W - 1), ohi = min(lane + 64, W - 1);
 
     auto pivot = [&](const cplx<T> &lo, const cplx<T> &hi, int q) {
         return readlane(csel(!TWO || q < 64, lo, hi), q & 63);
@@ -118,23 +103,31 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
         const int thi = ring_offset(lane + 64, sl, W, down);
         const int qlo = down ? 63 - tlo : tlo, qhi = down ? 63 - thi : thi;   // index into inc
         const int rlo = rfirst + qlo, rhi = rfirst + qhi;                     // rows
-        const int olo = down ? rlo + W : rlo - W, ohi = down ? rhi + W : rhi - W;
-        const cplx<T> dlo = csub(inc[min(max(qlo, 0), 63)], hist[olo & 127]);
-        const cplx<T> dhi = csub(inc[min(max(qhi, 0), 63)], hist[ohi & 127]);
+        const int plo = down ? rlo + W : rlo - W, phi = down ? rhi + W : rhi - W;
+        const cplx<T> dlo = csub(inc[min(max(qlo, 0), 63)], hist[plo & 127]);
+        const cplx<T> dhi = csub(inc[min(max(qhi, 0), 63)], hist[phi & 127]);
         lo = cadd(lo, csel(tlo < 64, dlo, zero));
         if (TWO) hi = cadd(hi, csel(hi_ok && thi < 64, dhi, zero));
         __builtin_amdgcn_wave_barrier();
     };
 
+    // one pointer runs through the whole stream: PD vectors ahead of the step
+    const cplx<T> *pf = L;
     cplx<T> flo[PD], fhi[PD];
-    hist[lane] = zero;
-    hist[lane + 64] = zero;
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+        flo[u] = pf[olo];
+        if (TWO) fhi[u] = pf[ohi];
+        pf += W;
+    }
+    if (TWO) {
+        hist[lane] = zero;
+        hist[lane + 64] = zero;
+    }
 
     // ------------------------------------------------------------ forward
     cplx<T> ylo = zero, yhi = zero;
     if (!TWO) ylo = csel(lane < W, gather_rhs<T>(S, dof_off, n1, v, lane), zero);
-#pragma unroll
-    for (int u = 0; u < PD; ++u) load_col<T, TWO>(L, W, min(u, npad - 1), lane, flo[u], fhi[u]);
     // rows of the next block: TWO -> rows whose pivot step is in it,
     // one register -> rows entering the window during it
     const int ahead = TWO ? 0 : W;
@@ -147,30 +140,34 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
             inc[lane] = rblk;
             correct(ylo, yhi, sl, c0, false);
         }
+        cplx<T> yout = zero;
 #pragma unroll
         for (int t = 0; t < 64; ++t) {
             const int u = t % PD;
-            const int c = c0 + t;
-            const cplx<T> piv = pivot(ylo, yhi, sl);                 // y_c
+            const cplx<T> piv = pivot(ylo, yhi, sl);                 // y_(c0+t)
             ylo = cfms(ylo, flo[u], piv);
             if (TWO) yhi = cfms(yhi, fhi[u], piv);
             if (!TWO) ylo = writelane(ylo, readlane(rblk, t), sl);   // row c + W enters
-            hist[c & 127] = piv;                                    // same value from every lane
-            load_col<T, TWO>(L, W, min(c + PD, npad - 1), lane, flo[u], fhi[u]);
+            yout = writelane(yout, piv, t);
+            flo[u] = pf[olo];
+            if (TWO) fhi[u] = pf[ohi];
+            pf += W;
             sl = (sl + 1 == W) ? 0 : sl + 1;
             __builtin_amdgcn_sched_barrier(0);   // keep each step's loads in place
         }
         rnext = to_T<T>(rraw, c0 + 64 + ahead + lane < S.n);
-        __builtin_amdgcn_wave_barrier();
-        yb[c0 + lane] = hist[(c0 + lane) & 127];
-        __builtin_amdgcn_wave_barrier();
+        yb[c0 + lane] = yout;
+        if (TWO) hist[(c0 + lane) & 127] = yout;
     }
 
     // ------------------------------------------------------------ backward
     // L^T x = z with z = D^{-1} y: after x_c is final, rows r < c in the
-    // window take -L[c, r] x_c, i.e. row c of L.
-    hist[lane] = zero;
-    hist[lane + 64] = zero;
+    // window take -L[c, r] x_c, i.e. row c of L (next in the stream).
+    if (TWO) {
+        __builtin_amdgcn_wave_barrier();
+        hist[lane] = zero;
+        hist[lane + 64] = zero;
+    }
     cplx<T> xlo = zero, xhi = zero;
     // z of the rows of the next block: TWO -> rows whose pivot step is in it
     // (c0 .. c0+63), one register -> rows entering the window (c0-W .. c0+63-W)
@@ -183,8 +180,6 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
         const int r0 = npad - 1 - ((npad - 1 - lane) % W + W) % W;   // row of slot `lane`
         xlo = csel(lane < W && r0 >= npad - W, zrow(r0), zero);
     }
-#pragma unroll
-    for (int u = 0; u < PD; ++u) load_col<T, TWO>(Rw, W, max(npad - 1 - u, 0), lane, flo[u], fhi[u]);
     sl = (npad - 1) % W;
     cplx<T> znext = zrow(npad - 64 - behind + lane);
     for (int c0 = npad - 64; c0 >= 0; c0 -= 64) {
@@ -196,24 +191,25 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
             inc[lane] = zblk;
             correct(xlo, xhi, sl, c0, true);
         }
+        cplx<T> xr = zero;
 #pragma unroll
         for (int q = 0; q < 64; ++q) {
             const int t = 63 - q;
             const int u = q % PD;
-            const int c = c0 + t;
-            const cplx<T> piv = pivot(xlo, xhi, sl);                 // x_c
+            const cplx<T> piv = pivot(xlo, xhi, sl);                 // x_(c0+t)
             xlo = cfms(xlo, flo[u], piv);
             if (TWO) xhi = cfms(xhi, fhi[u], piv);
             if (!TWO) xlo = writelane(xlo, readlane(zblk, t), sl);   // row c - W enters
-            hist[c & 127] = piv;
-            load_col<T, TWO>(Rw, W, max(c - PD, 0), lane, flo[u], fhi[u]);
+            xr = writelane(xr, piv, t);
+            flo[u] = pf[olo];
+            if (TWO) fhi[u] = pf[ohi];
+            pf += W;
             sl = (sl == 0) ? W - 1 : sl - 1;
             __builtin_amdgcn_sched_barrier(0);
         }
         znext = csel(rn >= 0, cmul(ynx, dnx), zero);
-        __builtin_amdgcn_wave_barrier();
-        xo[c0 + lane] = hist[(c0 + lane) & 127];
-        __builtin_amdgcn_wave_barrier();
+        xo[c0 + lane] = xr;
+        if (TWO) hist[(c0 + lane) & 127] = xr;
     }
 }
 
