@@ -61,3 +61,8 @@ def batch_draw(seed: int):
 def random_vector(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def batch_source(n_int: int, G: int, draw) -> np.ndarray:
+    """Nodal values of a ``batch_draw`` source on the given mesh."""
+    return gaussian(n_int, G, draw["centres"], draw["amps"], draw["width"])

@@ -429,3 +429,77 @@ def test_fused_and_unfused_arnoldi_agree(name):
     assert out[0][0] == out[1][0]
     assert relerr(out[0][1], out[1][1]) <= 1e-12
     assert np.allclose(out[0][2], out[1][2], rtol=1e-9, atol=1e-15)
+
+
+# ------------------------------------------------------------------ a8: 32-problem batch
+def config4_items():
+    """The 32 seeded multi-source problems (seeds 0..31): k from {40, 80, 160},
+    h = 1/(2k), G = overlap = PML = ceil(ln k / (k h)), P = ceil(Nc / 22)."""
+    items = []
+    for seed in range(32):
+        d = inputs.batch_draw(seed)
+        k = d["k"]
+        n = int(round(2 * k))
+        L = geometry.log_width(k, 1.0 / n)
+        P = -(-(n + 2 * L) // 22)
+        items.append((Problem(k=k, n_int=n, G=L, Px=P, Py=P, delta=L, kappa=L, sigma=10 * k), d))
+    return items
+
+
+def test_config4_batch_of_32_problems():
+    """All 32 problems (about 5 k subdomains, 2.2 M unknowns) in one handle and
+    one GMRES(100) call, mixed and FP64: every problem converges to a true
+    relative residual <= 1e-6; mixed and FP64 solutions agree within 1e-5;
+    for one problem of each k the right-hand side, the true residual (oracle
+    operator) and sampled local solves match the oracle."""
+    items = config4_items()
+    pbs = [p for p, _ in items]
+    f = np.concatenate([inputs.batch_source(p.n_int, p.G, d) for p, d in items])
+    v = inputs.random_vector(f.size, 44)
+    first_of_k = {}
+    for m, p in enumerate(pbs):
+        first_of_k.setdefault(p.k, m)
+    sample = sorted(first_of_k.values())
+    out = {}
+    for prec, tol in ((rp.RAS_MIXED, 1e-4), (rp.RAS_FP64, 1e-12)):
+        H = rp.ras_pml_setup_batch([p.k for p in pbs], [1.0 / p.n_int for p in pbs],
+                                   [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                                   [p.delta for p in pbs], [p.kappa for p in pbs],
+                                   rp.default_opts(precision=prec))
+        assert H.nprob == 32 and H.ndof == f.size
+        fd = dev(f)
+        b = torch.zeros_like(fd)
+        rp.ras_pml_rhs(H, fd, b)
+        x = torch.zeros_like(fd)
+        rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+        assert rc == rp.RAS_OK and rr <= 1e-6
+        for m in range(32):
+            itp, rrp, conv = rp.ras_pml_batch_result(H, m)
+            assert conv and rrp <= 1e-6, (m, itp, rrp)
+        xl = torch.zeros(H.nloc, dtype=torch.complex128, device="cuda")
+        rp.ras_pml_local_solve(H, dev(v), xl)
+        desc = H.desc()
+        out[prec] = (host(x), host(b), host(xl), desc, tol)
+        H.close()
+    xm, xd = out[rp.RAS_MIXED][0], out[rp.RAS_FP64][0]
+    sub_first = np.concatenate([[0], np.cumsum([p.Px * p.Py for p in pbs])])
+    for m, p in enumerate(pbs):
+        off, n = sum(q.ndof for q in pbs[:m]), p.ndof
+        assert relerr(xm[off:off + n], xd[off:off + n]) <= 1e-5, m
+    for m in sample:
+        p, d = items[m]
+        off, n = sum(q.ndof for q in pbs[:m]), p.ndof
+        ids = [0, p.Px - 1, (p.Py // 2) * p.Px + p.Px // 2, p.Px * p.Py - 1]
+        R = ras.RasPml(p, subset=ids)
+        fm = f[off:off + n]
+        bref = fem.rhs(R.M1, fm)
+        ref = R.local_solve(v[off:off + n])
+        for prec, (x, bh, xg, desc, tol) in out.items():
+            assert relerr(bh[off:off + n], bref) <= 1e-12, (m, prec)
+            r = bref - R.A @ x[off:off + n]
+            assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(bref) * (1 + 1e-9), (m, prec)
+            loc_off = np.concatenate([[0], np.cumsum([dd[0] for dd in desc])])
+            for q, s in enumerate(ids):
+                g = sub_first[m] + s
+                a = xg[loc_off[g]:loc_off[g + 1]]
+                assert relerr(a, R.local_part(ref, q)) <= tol, (m, s, prec)
