@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 32-problem batch (seeded multi-source problems, one handle)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC traffic calibration)")
     args = ap.parse_args()
@@ -215,10 +217,60 @@ def main():
         H.close()
     out["applies"] = applies
 
+    # ---------------------------------------------------------------- 32-problem batch
+    if not args.no_batch:
+        out["batch32"] = batch32(dev, args.no_fp64)
+
     # ---------------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(k, n_int, P, L, G, mixed["iters"], args.workload)
     print(json.dumps(out), flush=True)
+
+
+def batch32(dev, no_fp64):
+    """The 32 seeded multi-source problems (seeds 0..31: k from {40, 80, 160},
+    h = 1/(2k), G = overlap = PML = L, P = ceil(Nc / 22)) in one handle: setup,
+    right-hand sides and one GMRES(100) call to rtol 1e-6 for all of them,
+    timed end to end after one untimed run."""
+    import numpy as np
+    import torch
+    import paper_2602_00735_amd as rp
+    from paper_2602_00735_amd import inputs
+    ks, hs, grids, subs, ovs, fs = [], [], [], [], [], []
+    for seed in range(32):
+        d = inputs.batch_draw(seed)
+        k = d["k"]
+        n = int(round(2 * k))
+        L = log_width(k, 1.0 / n)
+        P = -(-(n + 2 * L) // 22)
+        ks.append(k); hs.append(1.0 / n); grids.append((n, n)); subs.append((P, P)); ovs.append(L)
+        fs.append(inputs.batch_source(n, L, d))
+    f = torch.from_numpy(np.concatenate(fs)).to(dev)
+    res = {"problems": 32, "unknowns": int(f.numel()),
+           "subdomains": int(sum(P * Q for P, Q in subs))}
+    for name, prec in (("mixed", rp.RAS_MIXED), ("fp64", rp.RAS_FP64)):
+        if name == "fp64" and no_fp64:
+            continue
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H = rp.ras_pml_setup_batch(ks, hs, grids, subs, ovs, ovs, rp.default_opts(precision=prec))
+            b = torch.empty_like(f)
+            x = torch.zeros_like(f)
+            rp.ras_pml_rhs(H, f, b)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            per = [rp.ras_pml_batch_result(H, m) for m in range(32)]
+            H.close()
+        res[name] = {"total_s": round(t2 - t0, 5), "setup_s": round(t1 - t0, 5),
+                     "solve_s": round(t2 - t1, 5), "status": rc,
+                     "iters_max": max(p[0] for p in per), "iters_min": min(p[0] for p in per),
+                     "all_converged": all(p[2] for p in per),
+                     "relres_max": max(p[1] for p in per)}
+    return res
 
 
 def cpu_baseline(k, n_int, P, L, G, iters, workload):

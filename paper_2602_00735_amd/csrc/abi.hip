@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +24,9 @@ void launch_local_stencil(const DevProb *, const DevSub *, int, int, double2 *, 
 void launch_rhs(const DevProb *, int, long long, const double2 *, double2 *, hipStream_t);
 void launch_band_ldlt(bool, int, const DevSub *, const int *, int, const double2 *, void *, int *,
                       hipStream_t);
+int ldlt_mfma_tiles(int W);
+void launch_band_ldlt_mfma(int, const DevSub *, const int *, int, const double2 *, void *, int *,
+                           hipStream_t);
 void launch_band_solve(bool, int, const DevProb *, const DevSub *, const int *, int, const int *,
                        const double2 *, const void *, void *, void *, hipStream_t);
 void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
@@ -68,6 +72,10 @@ struct ras_pml_handle {
     std::vector<DevProb> hprobs;
     std::vector<DevSub> hsubs;
     std::vector<int> order;
+    // complex64 factorisation: subdomains grouped by window size (tiles per
+    // side), largest first within a group; {tiles, first, count} per group
+    std::vector<int> lu_order;
+    std::vector<std::array<int, 3>> lu_groups;
     int nprob = 0, nsub = 0, maxW = 0, max_n = 0;
     long long ntot = 0, nloc = 0, nvec = 0, max_ndof = 0;
     bool fp64 = false;
@@ -77,7 +85,7 @@ struct ras_pml_handle {
 
     DevProb *d_probs = nullptr;
     DevSub *d_subs = nullptr;
-    int *d_order = nullptr;
+    int *d_order = nullptr, *d_lu_order = nullptr;
     int *d_pcnt = nullptr, *d_pchunk = nullptr;
     double *d_pw = nullptr;
     double2 *d_coef = nullptr;
@@ -216,7 +224,7 @@ void collect_events(ras_pml_handle *H) {
 }  // namespace
 
 ras_pml_handle::~ras_pml_handle() {
-    void *ptrs[] = {d_probs, d_subs,  d_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
+    void *ptrs[] = {d_probs, d_subs,  d_order, d_lu_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
                     d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err};
@@ -299,6 +307,18 @@ int build(ras_pml_handle *H, hipStream_t st) {
     std::iota(H->order.begin(), H->order.end(), 0);
     std::stable_sort(H->order.begin(), H->order.end(),
                      [&](int a, int b) { return H->hsubs[a].n > H->hsubs[b].n; });
+    if (!H->fp64) {
+        H->lu_order = H->order;
+        auto tiles = [&](int j) { return ldlt_mfma_tiles(H->hsubs[j].W); };
+        std::stable_sort(H->lu_order.begin(), H->lu_order.end(),
+                         [&](int a, int b) { return tiles(a) > tiles(b); });
+        for (int i = 0; i < H->nsub;) {
+            int e = i;
+            while (e < H->nsub && tiles(H->lu_order[e]) == tiles(H->lu_order[i])) ++e;
+            H->lu_groups.push_back({tiles(H->lu_order[i]), i, e - i});
+            i = e;
+        }
+    }
 
     // algorithmic bytes of one band-solve launch: L read by both sweeps,
     // D^{-1}, the gathered right-hand side (complex128), the forward result
@@ -315,6 +335,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_probs, sizeof(DevProb) * H->nprob));
     RCHK(dalloc(H, &H->d_subs, sizeof(DevSub) * H->nsub));
     RCHK(dalloc(H, &H->d_order, sizeof(int) * H->nsub));
+    if (!H->fp64) RCHK(dalloc(H, &H->d_lu_order, sizeof(int) * H->nsub));
     RCHK(dalloc(H, &H->d_pcnt, sizeof(int) * pcnt.size()));
     RCHK(dalloc(H, &H->d_pchunk, sizeof(int) * pchunk.size()));
     RCHK(dalloc(H, &H->d_pw, sizeof(double) * pw.size()));
@@ -330,6 +351,9 @@ int build(ras_pml_handle *H, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_order, H->order.data(), sizeof(int) * H->nsub,
                            hipMemcpyHostToDevice, st));
+    if (!H->fp64)
+        HCHK(H, hipMemcpyAsync(H->d_lu_order, H->lu_order.data(), sizeof(int) * H->nsub,
+                               hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_pcnt, pcnt.data(), sizeof(int) * pcnt.size(),
                            hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_pchunk, pchunk.data(), sizeof(int) * pchunk.size(),
@@ -350,9 +374,17 @@ int build(ras_pml_handle *H, hipStream_t st) {
     launch_local_stencil(H->d_probs, H->d_subs, H->nsub, H->max_n, H->d_lst, st);
     HCHK(H, hipGetLastError());
     if (timing) HCHK(H, hipEventRecord(e1, st));
-    launch_band_ldlt(H->fp64, H->maxW, H->d_subs, H->d_order, H->nsub, H->d_lst, H->d_F,
-                     H->d_status, st);
-    HCHK(H, hipGetLastError());
+    if (H->fp64) {
+        launch_band_ldlt(true, H->maxW, H->d_subs, H->d_order, H->nsub, H->d_lst, H->d_F,
+                         H->d_status, st);
+        HCHK(H, hipGetLastError());
+    } else {
+        for (const auto &g : H->lu_groups) {
+            launch_band_ldlt_mfma(g[0], H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst, H->d_F,
+                                  H->d_status, st);
+            HCHK(H, hipGetLastError());
+        }
+    }
     if (timing) HCHK(H, hipEventRecord(e2, st));
     std::vector<int> status(H->nsub);
     HCHK(H, hipMemcpyAsync(status.data(), H->d_status, sizeof(int) * H->nsub,

@@ -1,0 +1,307 @@
+// Blocked band factorisation A_j = L_j D_j L_j^T (complex64, no pivoting)
+// with the trailing update on the matrix cores (setup).
+//
+// Same factor as the one-column kernel (Section 2's local solves; A_j is
+// complex symmetric, U = D L^T), organised in panels of 16 columns:
+//   1. the panel (16 columns of the active window) is factorised in
+//      registers: for each column, the pivot is broadcast with v_readlane,
+//      the column is scaled, and the panel's later columns take the rank-1
+//      update;
+//   2. L, its row copy and D^{-1} of the 16 columns are written out;
+//   3. the rest of the window takes the rank-16 update C -= L W^T with
+//      W = L D, as complex 16x16 tiles: 16 v_mfma_f32_16x16x4f32 per tile
+//      (real and imaginary parts in four real products).  Only tiles on or
+//      below the diagonal are updated: the window stays symmetric.
+// The window covers M = 16 NT rows and columns, NT = ceil((W + 15) / 16),
+// enough to hold every row a panel column reaches (W - 1 below its
+// diagonal).  Its NT (NT + 1) / 2 tiles on and below the diagonal live in
+// the accumulator registers, spread over the four waves.  Tile (I, J) lies
+// on tile diagonal d = I - J; the tiles of one diagonal form a ring of
+// length NT - d, so when the window slides by one panel no tile moves: each
+// diagonal's ring index advances, and the tile that leaves (J = 0) becomes
+// that diagonal's new last tile (J = NT - 1 - d, in the new last tile row),
+// refilled from the stencil (those rows have not been touched by any earlier
+// panel).  Rows past the matrix end are identity rows, as in the one-column
+// kernel, and the factor layout is the same: columns of L in slot order,
+// then the rows last row first, then D^{-1}.
+//
+// The panel factorisation runs on all four waves: lanes 0..15 of every wave
+// hold the panel's first 16 rows (the same values, computed redundantly, so
+// no wave waits for another), lanes 16..63 of wave w hold rows
+// 16 + 48 w .. 16 + 48 w + 47.
+#include "device.h"
+
+namespace raspml {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kLdsStride = 17;   // complex values per LDS panel row (16 + 1 pad)
+
+// Workgroup barrier for the LDS panel buffers only: waits for this wave's
+// LDS accesses (lgkmcnt(0); vmcnt and expcnt left at their maximum), not for
+// its global stores and loads (a fence would drain those, costing a memory
+// round trip per barrier).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// A_j(r, q) from the local stencil: for r >= q the coupling is stored at
+// node q, entry 0 (d = r - q = 0), 1 (d = 1), 2 (d = n_fast) or 3
+// (d = n_fast + 1; entries 1 and 3 vanish when r starts a fast line).
+// Identity past the matrix end.  Branch-free: one clamped load, always
+// issued, so that its wait can sit at the first use of the value.
+__device__ __forceinline__ cplx<float> band_entry(const double2 *__restrict__ lst, int n, int nf,
+                                                  int r, int q) {
+    const int hi = max(r, q), lo = min(r, q), d = hi - lo;
+    const int e = d == 0 ? 0 : d == 1 ? 1 : d == nf ? 2 : 3;
+    const bool wrap = (hi % nf) == 0;
+    const bool in = hi < n;
+    const bool coupled = in && (d == 0 || d == nf || ((d == 1 || d == nf + 1) && !wrap));
+    const double2 v = lst[4LL * min(lo, n - 1) + e];
+    const float id = (!in && d == 0) ? 1.0f : 0.0f;
+    return cplx<float>{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
+}
+
+// Panel factorisation on the calling wave's rows (see above).  Before
+// column k is scaled, its entries below the diagonal are L[row, k] d_k, i.e.
+// W = L D, which is what the later panel columns need (as the values of
+// rows j < 16, broadcast with v_readlane) and what is stored in WB; L itself
+// goes to LP (rows 16.. only; the first 16 rows' L, zero on and above the
+// diagonal, goes to LT, because every wave reads those rows of LP first).
+// dg: lane k < 16 holds |A_j(c0 + k, c0 + k)| for the pivot test.  The
+// reciprocal of the pivot is v_rcp_f32 based (within 1 ulp; complex64
+// factors).
+template <int M>
+__device__ __forceinline__ int factor_panel(cplx<float> *LP, cplx<float> *LT, cplx<float> *WB,
+                                            float dg, int c0, cplx<float> *__restrict__ Dinv,
+                                            int bad, int wave) {
+    const int lane = threadIdx.x & 63;
+    const int row = lane < 16 ? lane : 16 + 48 * wave + (lane - 16);
+    const bool have = row < M;
+    cplx<float> x[16];
+    const cplx<float> *src = LP + min(row, M - 1) * kLdsStride;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = csel(have, src[k], cplx<float>{0.0f, 0.0f});
+    // every wave reads rows 0..15 of LP first: their L goes to LT (wave 0);
+    // lanes with nothing to store write the spare row M of LP / WB
+    cplx<float> *dl = lane < 16 ? (wave == 0 ? LT + row * kLdsStride : LP + M * kLdsStride)
+                                : LP + min(row, M) * kLdsStride;
+    cplx<float> *dw = WB + (lane < 16 ? M : min(row, M)) * kLdsStride;
+    float pa[16];        // |pivot|^2 per column, tested after the loop
+    cplx<float> dinv{0.0f, 0.0f};   // lane k: 1 / d_k
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const cplx<float> w = x[k];                      // W[row, k] for row > k
+        const cplx<float> d = readlane(w, k);
+        const float m2 = cabs2(d);
+        pa[k] = m2;
+        const float rm = __builtin_amdgcn_rcpf(m2);
+        const cplx<float> inv{d.re * rm, -d.im * rm};
+        dinv = writelane(dinv, inv, k);
+        const cplx<float> l = cmul(w, inv);
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) x[j] = cfms(x[j], l, readlane(w, j));
+        const bool below = row > k;
+        dl[k] = csel(below, l, cplx<float>{0.0f, 0.0f});
+        dw[k] = csel(below, w, cplx<float>{0.0f, 0.0f});
+    }
+    if (wave == 0 && lane < 16) Dinv[c0 + lane] = dinv;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float ad = sqrtf(pa[k]);
+        if (bad < 0 && !(ad > 1e-6f * readlane(dg, k) && ad < 1e30f)) bad = c0 + k;
+    }
+    return bad;
+}
+
+// Lower tile number u < NT (NT + 1) / 2 as (diagonal d, ring slot q); the
+// loop is bounded, so numbers past the last tile give d = NT (unused).
+template <int NT>
+__device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
+    d = 0;
+    int left = u;
+#pragma unroll
+    for (int dd = 0; dd < NT; ++dd) {
+        if (d == dd && left >= NT - dd) {
+            left -= NT - dd;
+            d = dd + 1;
+        }
+    }
+    q = left;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict__ subs,
+                                                        const int *__restrict__ order,
+                                                        const double2 *__restrict__ lst_all,
+                                                        cplx<float> *__restrict__ F,
+                                                        int *__restrict__ status) {
+    constexpr int M = 16 * NT;
+    constexpr int NL = NT * (NT + 1) / 2;   // tiles on and below the diagonal
+    constexpr int NS = (NL + 3) / 4;        // tile slots per wave
+    static_assert(M <= 16 + 4 * 48, "panel rows per wave");
+    // row M of LP and WB is a spare row for lanes with nothing to store
+    __shared__ cplx<float> LP[(M + 1) * kLdsStride];   // published panel, then L (rows 16..)
+    __shared__ cplx<float> LT[16 * kLdsStride];        // L of the panel's first 16 rows
+    __shared__ cplx<float> WB[(M + 1) * kLdsStride];   // W = L D (rows 16..)
+
+    const int sid = order[blockIdx.x];
+    const DevSub S = subs[sid];
+    const int W = S.W, nf = S.nf, n = S.n, npad = S.npad;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2 *lst = lst_all + 4 * S.loc_off;
+    cplx<float> *L = F + S.fac_off;
+    cplx<float> *Rw = L + static_cast<long long>(npad) * W;   // rows of L, last first
+    cplx<float> *Dinv = Rw + static_cast<long long>(npad) * W;
+    const int ti = 4 * (lane >> 4), tj = lane & 15;   // accumulator element (ti + r, tj)
+    const cplx<float> zero{0.0f, 0.0f};
+
+    // Row r < W of R has no columns before 0 at positions r+1 .. W-1.
+    for (int i = tid; i < W * W; i += 256) {
+        const int r = i / W, q = i % W;
+        if (q > r && r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + q] = zero;
+    }
+
+    // slot s of this wave holds lower tile u = 4 s + wave: diagonal d, ring
+    // slot q; at panel p its logical column is J = (q - p) mod (NT - d) and
+    // its row I = J + d.  Window at panel 0: rows 16 I.., columns 16 J..
+    v4f cre[NS], cim[NS];
+    int dg_[NS], jc_[NS];            // diagonal and current logical column of each slot
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int d, q;
+        lower_tile<NT>(4 * s + wave, d, q);
+        const bool valid = 4 * s + wave < NL;
+        dg_[s] = valid ? d : -1;
+        jc_[s] = q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const cplx<float> v =
+                valid ? band_entry(lst, n, nf, 16 * (q + d) + ti + r, 16 * q + tj) : zero;
+            cre[s][r] = v.re;
+            cim[s][r] = v.im;
+        }
+    }
+
+    int bad = -1;
+    // original diagonal magnitudes of the next panel's columns (pivot test),
+    // loaded one panel ahead
+    auto diag = [&](int c0) { return sqrtf(cabs2(band_entry(lst, n, nf, c0 + tj, c0 + tj))); };
+    float dg = diag(0);
+    for (int c0 = 0; c0 < npad; c0 += 16) {
+        const float dg_next = diag(c0 + 16);
+        // 1. publish logical tile column 0 (J == 0 on every diagonal)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (dg_[s] >= 0 && jc_[s] == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    LP[(16 * dg_[s] + ti + r) * kLdsStride + tj] = cplx<float>{cre[s][r], cim[s][r]};
+            }
+        }
+        lds_barrier();
+        // 2. panel factorisation
+        bad = factor_panel<M>(LP, LT, WB, dg, c0, Dinv, bad, wave);
+        dg = dg_next;
+        lds_barrier();
+        // 3. columns c0 .. c0+15 of L (slot order) and their entries in the
+        //    rows of L; row r's entry of column c sits at position c mod W
+        {
+            const int sl0 = c0 % W;
+            const int pos = tid & 127;
+#pragma unroll
+            for (int k = tid >> 7; k < 16; k += 2) {
+                const int c = c0 + k;
+                int sl = sl0 + k;
+                sl = sl >= W ? sl - W : sl;
+                if (pos < W) {
+                    const int r = c + (pos >= sl ? pos - sl : pos - sl + W);
+                    const int rr = r - c0;
+                    L[static_cast<long long>(c) * W + pos] =
+                        r == c ? zero : (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                }
+            }
+            const int k = tid & 15;
+            int slk = sl0 + k;
+            slk = slk >= W ? slk - W : slk;
+            for (int r = c0 + 1 + (tid >> 4); r < c0 + W + 15; r += 16) {
+                const int c = c0 + k;
+                if (r > c && r < c + W && r < npad) {
+                    const int rr = r - c0;
+                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] =
+                        (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                }
+            }
+        }
+        // 4. rank-16 update of the tiles with J >= 1; the tiles with J == 0
+        //    leave and come back as their diagonal's last tile
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int d = dg_[s], J = jc_[s];
+            if (d >= 0) {
+                // the window slides: column J becomes J - 1, column 0 comes
+                // back as the diagonal's last tile
+                jc_[s] = J == 0 ? NT - 1 - d : J - 1;
+                if (J >= 1) {
+                    const int I = J + d;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int col = 4 * kk + (lane >> 4);
+                        const cplx<float> l = LP[(16 * I + tj) * kLdsStride + col];
+                        const cplx<float> w = WB[(16 * J + tj) * kLdsStride + col];
+                        cre[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.re, w.re, cre[s], 0, 0, 0);
+                        cre[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(l.im, w.im, cre[s], 0, 0, 0);
+                        cim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.re, w.im, cim[s], 0, 0, 0);
+                        cim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.im, w.re, cim[s], 0, 0, 0);
+                    }
+                } else {
+                    // next window: row NT - 1, column NT - 1 - d
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const cplx<float> v = band_entry(lst, n, nf, c0 + M + ti + r,
+                                                         c0 + 16 + 16 * (NT - 1 - d) + tj);
+                        cre[s][r] = v.re;
+                        cim[s][r] = v.im;
+                    }
+                }
+            }
+        }
+        lds_barrier();
+    }
+    if (tid == 0) status[sid] = bad;
+}
+
+template <int NT>
+void launch_nt(const DevSub *subs, const int *order, int count, const double2 *lst, void *F,
+               int *status, hipStream_t st) {
+    hipLaunchKernelGGL(k_band_ldlt_mfma<NT>, dim3(count), dim3(256), 0, st, subs, order, lst,
+                       static_cast<cplx<float> *>(F), status);
+}
+
+}  // namespace
+
+// Window tiles per side for a factor column length W (at most 128).
+int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }
+
+// count subdomains order[0 .. count) that all have ldlt_mfma_tiles(W) == NT.
+void launch_band_ldlt_mfma(int NT, const DevSub *subs, const int *order, int count,
+                           const double2 *lst, void *F, int *status, hipStream_t st) {
+    switch (NT) {
+        case 2: launch_nt<2>(subs, order, count, lst, F, status, st); break;
+        case 3: launch_nt<3>(subs, order, count, lst, F, status, st); break;
+        case 4: launch_nt<4>(subs, order, count, lst, F, status, st); break;
+        case 5: launch_nt<5>(subs, order, count, lst, F, status, st); break;
+        case 6: launch_nt<6>(subs, order, count, lst, F, status, st); break;
+        case 7: launch_nt<7>(subs, order, count, lst, F, status, st); break;
+        case 8: launch_nt<8>(subs, order, count, lst, F, status, st); break;
+        default: launch_nt<9>(subs, order, count, lst, F, status, st); break;
+    }
+}
+
+}  // namespace raspml
