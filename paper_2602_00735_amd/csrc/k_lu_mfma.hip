@@ -25,10 +25,10 @@
 // kernel, and the factor layout is the same: columns of L in slot order,
 // then the rows last row first, then D^{-1}.
 //
-// The panel factorisation runs on all four waves: lanes 0..15 of every wave
-// hold the panel's first 16 rows (the same values, computed redundantly, so
-// no wave waits for another), lanes 16..63 of wave w hold rows
-// 16 + 48 w .. 16 + 48 w + 47.
+// The panel factorisation runs on as few waves as hold its rows (two at
+// M = 112): the column-by-column chain is serial, and every extra wave
+// repeats it for the panel's first 16 rows; the other waves' issue slots
+// stay free for the workgroups that share the CU.
 #include "device.h"
 
 namespace raspml {
@@ -67,39 +67,44 @@ __device__ __forceinline__ cplx<float> band_entry(const double2 *__restrict__ ls
     return cplx<float>{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
 }
 
-// Panel factorisation on the calling wave's rows (see above).  Before
-// column k is scaled, its entries below the diagonal are L[row, k] d_k, i.e.
-// W = L D, which is what the later panel columns need (as the values of
-// rows j < 16, broadcast with v_readlane) and what is stored in WB; L itself
-// goes to LP (rows 16.. only; the first 16 rows' L, zero on and above the
-// diagonal, goes to LT, because every wave reads those rows of LP first).
-// dg: lane k < 16 holds |A_j(c0 + k, c0 + k)| for the pivot test.  The
-// reciprocal of the pivot is v_rcp_f32 based (within 1 ulp; complex64
-// factors).
+// Rows of the panel factorisation: NW = 1 + ceil((M - 64) / 48) waves take
+// part.  Part v = 0 holds rows 0..63 (one per lane); part v >= 1 holds rows
+// 0..15 in lanes 0..15 (the same values as part 0, computed again so that no
+// wave waits for another) and rows 64 + 48 (v - 1) + lane - 16 in lanes 16..63.
+template <int M>
+constexpr int panel_waves() { return M <= 64 ? 1 : 1 + (M - 64 + 47) / 48; }
+
+// Panel factorisation on the calling wave's rows.  Before column k is
+// scaled, its entries below the diagonal are L[row, k] d_k, i.e. W = L D,
+// which is what the later panel columns need (the values of rows j < 16,
+// broadcast with v_readlane) and what is stored in WB; L goes to LP, except
+// for the first 16 rows, whose L goes to LT (every part reads those rows of
+// LP first).  Zero on and above the diagonal.  dg: lane k < 16 holds
+// |A_j(c0 + k, c0 + k)| for the pivot test.  The reciprocal of the pivot is
+// v_rcp_f32 based (within 1 ulp; complex64 factors).
 template <int M>
 __device__ __forceinline__ int factor_panel(cplx<float> *LP, cplx<float> *LT, cplx<float> *WB,
                                             float dg, int c0, cplx<float> *__restrict__ Dinv,
-                                            int bad, int wave) {
+                                            int bad, int part) {
     const int lane = threadIdx.x & 63;
-    const int row = lane < 16 ? lane : 16 + 48 * wave + (lane - 16);
+    const int row = part == 0 ? lane : lane < 16 ? lane : 64 + 48 * (part - 1) + lane - 16;
     const bool have = row < M;
     cplx<float> x[16];
     const cplx<float> *src = LP + min(row, M - 1) * kLdsStride;
 #pragma unroll
     for (int k = 0; k < 16; ++k) x[k] = csel(have, src[k], cplx<float>{0.0f, 0.0f});
-    // every wave reads rows 0..15 of LP first: their L goes to LT (wave 0);
     // lanes with nothing to store write the spare row M of LP / WB
-    cplx<float> *dl = lane < 16 ? (wave == 0 ? LT + row * kLdsStride : LP + M * kLdsStride)
+    cplx<float> *dl = lane < 16 ? (part == 0 ? LT + row * kLdsStride : LP + M * kLdsStride)
                                 : LP + min(row, M) * kLdsStride;
     cplx<float> *dw = WB + (lane < 16 ? M : min(row, M)) * kLdsStride;
-    float pa[16];        // |pivot|^2 per column, tested after the loop
+    float pa = 0.0f;                // lane k: |d_k|^2, tested after the loop
     cplx<float> dinv{0.0f, 0.0f};   // lane k: 1 / d_k
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const cplx<float> w = x[k];                      // W[row, k] for row > k
         const cplx<float> d = readlane(w, k);
         const float m2 = cabs2(d);
-        pa[k] = m2;
+        pa = writelane(pa, m2, k);
         const float rm = __builtin_amdgcn_rcpf(m2);
         const cplx<float> inv{d.re * rm, -d.im * rm};
         dinv = writelane(dinv, inv, k);
@@ -110,12 +115,11 @@ __device__ __forceinline__ int factor_panel(cplx<float> *LP, cplx<float> *LT, cp
         dl[k] = csel(below, l, cplx<float>{0.0f, 0.0f});
         dw[k] = csel(below, w, cplx<float>{0.0f, 0.0f});
     }
-    if (wave == 0 && lane < 16) Dinv[c0 + lane] = dinv;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const float ad = sqrtf(pa[k]);
-        if (bad < 0 && !(ad > 1e-6f * readlane(dg, k) && ad < 1e30f)) bad = c0 + k;
-    }
+    if (part == 0 && lane < 16) Dinv[c0 + lane] = dinv;
+    const float ad = sqrtf(pa);
+    const bool fail = lane < 16 && !(ad > 1e-6f * dg && ad < 1e30f);
+    const unsigned long long fm = __ballot(fail);
+    if (bad < 0 && fm != 0) bad = c0 + __builtin_ctzll(fm);
     return bad;
 }
 
@@ -135,8 +139,12 @@ __device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
     q = left;
 }
 
+// Up to NT = 7 (W <= 97) the kernel is held to 128 registers, so that
+// four workgroups (one subdomain each) share a CU: at k = 640 all 1024
+// subdomains are then resident at once.  Larger windows need more.
 template <int NT>
-__global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict__ subs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 7 ? 4 : 1))) void
+k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                                                         const int *__restrict__ order,
                                                         const double2 *__restrict__ lst_all,
                                                         cplx<float> *__restrict__ F,
@@ -144,7 +152,7 @@ __global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict
     constexpr int M = 16 * NT;
     constexpr int NL = NT * (NT + 1) / 2;   // tiles on and below the diagonal
     constexpr int NS = (NL + 3) / 4;        // tile slots per wave
-    static_assert(M <= 16 + 4 * 48, "panel rows per wave");
+    static_assert(panel_waves<M>() <= 4, "panel rows per wave");
     // row M of LP and WB is a spare row for lanes with nothing to store
     __shared__ cplx<float> LP[(M + 1) * kLdsStride];   // published panel, then L (rows 16..)
     __shared__ cplx<float> LT[16 * kLdsStride];        // L of the panel's first 16 rows
@@ -155,6 +163,8 @@ __global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict
     const int W = S.W, nf = S.nf, n = S.n, npad = S.npad;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int fwave = blockIdx.x & 3;
+    const int part = (wave - fwave) & 3;   // panel part of this wave
     const double2 *lst = lst_all + 4 * S.loc_off;
     cplx<float> *L = F + S.fac_off;
     cplx<float> *Rw = L + static_cast<long long>(npad) * W;   // rows of L, last first
@@ -207,7 +217,10 @@ __global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict
         }
         lds_barrier();
         // 2. panel factorisation
-        bad = factor_panel<M>(LP, LT, WB, dg, c0, Dinv, bad, wave);
+        // parts 0 .. NW-1 on waves fwave, fwave+1, ... (mod 4): the choice
+        // rotates with the workgroup so that the workgroups sharing a CU
+        // tend to factorise on different SIMDs
+        if (part < panel_waves<M>()) bad = factor_panel<M>(LP, LT, WB, dg, c0, Dinv, bad, part);
         dg = dg_next;
         lds_barrier();
         // 3. columns c0 .. c0+15 of L (slot order) and their entries in the
@@ -274,7 +287,7 @@ __global__ __launch_bounds__(256) void k_band_ldlt_mfma(const DevSub *__restrict
         }
         lds_barrier();
     }
-    if (tid == 0) status[sid] = bad;
+    if (part == 0 && lane == 0) status[sid] = bad;
 }
 
 template <int NT>
