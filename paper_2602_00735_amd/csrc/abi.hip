@@ -43,7 +43,7 @@ void launch_normalize(const DevProb *, int, long long, const KState *, double2 *
 void launch_start_cycle(const DevProb *, int, long long, const KState *, const double2 *,
                         double2 *, hipStream_t);
 void launch_givens(KState *, int, int, int, double2 *, double *, double2 *, double2 *, double *,
-                   hipStream_t);
+                   int *, hipStream_t);
 void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, double2 *,
                     hipStream_t);
 void launch_update_x(const DevProb *, int, long long, const KState *, const int *, int,
@@ -52,7 +52,7 @@ int arnoldi_block_capacity(int E, int *blocks_per_cu);
 hipError_t launch_arnoldi(int E, int nblocks, const DevProb *, const KState *, const ArnoldiBlock *,
                           const double2 *, long long, const double2 *, double2 *, int, int,
                           double2 *, double2 *, unsigned long long *, unsigned long long, int *,
-                          hipStream_t);
+                          int, hipStream_t);
 
 constexpr int kRedBlocksHost = 512;
 
@@ -480,7 +480,7 @@ int ensure_krylov(ras_pml_handle *H, int m) {
     RCHK(dalloc(H, &H->d_sn, sizeof(double2) * static_cast<size_t>(P) * m));
     RCHK(dalloc(H, &H->d_y, sizeof(double2) * static_cast<size_t>(P) * m));
     RCHK(dalloc(H, &H->d_cs, sizeof(double) * static_cast<size_t>(P) * m));
-    RCHK(dalloc(H, &H->d_hist, sizeof(double) * static_cast<size_t>(P)));
+    RCHK(dalloc(H, &H->d_hist, sizeof(double) * static_cast<size_t>(P) * (m + 1)));
     if (!H->d_ks) {
         RCHK(dalloc(H, &H->d_ks, sizeof(KState) * P));
         RCHK(dalloc(H, &H->d_active, sizeof(int) * P));
@@ -589,8 +589,13 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
                                st));
         launch_start_cycle(H->d_probs, P, H->max_ndof, H->d_ks, H->d_r, H->d_V, st);
         HCHK(H, hipGetLastError());
-        // active-in-cycle flags for the apply/SpMV: mirror of need at start
-        std::vector<int> act(need);
+        // Steps are enqueued without waiting: the Givens kernel clears a
+        // problem's in-cycle flag (and its active flag, read by the next
+        // step's launches) on convergence, breakdown or the cycle's end, and
+        // every later launch of the cycle skips that problem (the Arnoldi
+        // launch as a whole once no problem is left).  The host looks at the
+        // flags every kSyncSteps steps and stops enqueueing when none is set.
+        constexpr int kSyncSteps = 8;
         for (int j = 0; j < mc; ++j) {
             const long long n = H->ntot;
             double2 *Vj = H->d_V + static_cast<long long>(j) * n;
@@ -601,7 +606,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
                 Timer t(H, C_MGS, st);
                 hipError_t e = launch_arnoldi(H->arn_E, H->arn_nblocks, H->d_probs, H->d_ks,
                                               H->d_ablocks, H->d_coef, n, Zj, H->d_V, j, m, H->d_H,
-                                              H->d_part2, H->d_bar, H->bar_base, H->d_err, st);
+                                              H->d_part2, H->d_bar, H->bar_base, H->d_err, P, st);
                 if (e != hipSuccess) {
                     H->last_error = std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e);
                     return RAS_EHIP;
@@ -625,9 +630,11 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
             HCHK(H, hipGetLastError());
             {
                 Timer t(H, C_GIVENS, st);
-                launch_givens(H->d_ks, P, j, m, H->d_H, H->d_cs, H->d_sn, H->d_g, nullptr, st);
+                launch_givens(H->d_ks, P, j, m, H->d_H, H->d_cs, H->d_sn, H->d_g, H->d_hist,
+                              H->d_active, st);
             }
             HCHK(H, hipGetLastError());
+            if ((j + 1) % kSyncSteps != 0 && j + 1 != mc) continue;
             HCHK(H, hipMemcpyAsync(H->h_ks, H->d_ks, sizeof(KState) * P, hipMemcpyDeviceToHost, st));
             if (H->arn_E > 0)
                 HCHK(H, hipMemcpyAsync(H->h_err, H->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -636,21 +643,30 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
                 H->last_error = "grid barrier of the fused Arnoldi step timed out";
                 return RAS_EHIP;
             }
-            ++total;
             int still = 0;
-            double worst = 0.0;
-            for (int p = 0; p < P; ++p) {
-                if (act[p]) {
-                    worst = std::max(worst, H->h_ks[p].est / bnorm[p]);
-                    H->res_iters[p] += 1;
-                }
-                act[p] = H->h_ks[p].in_cycle;
-                still += act[p];
-            }
-            if (hist) hist[hist_n++] = worst;
+            for (int p = 0; p < P; ++p) still += H->h_ks[p].in_cycle;
             if (still == 0) break;
-            HCHK(H, hipMemcpyAsync(H->d_active, act.data(), sizeof(int) * P, hipMemcpyHostToDevice,
-                                   st));
+        }
+        // steps taken in this cycle (per problem: kp) and the estimate history
+        {
+            std::vector<double> eh(static_cast<size_t>(P) * (m + 1));
+            HCHK(H, hipMemcpyAsync(eh.data(), H->d_hist, sizeof(double) * eh.size(),
+                                   hipMemcpyDeviceToHost, st));
+            HCHK(H, hipStreamSynchronize(st));
+            int steps = 0;
+            for (int p = 0; p < P; ++p)
+                if (need[p]) {
+                    H->res_iters[p] += H->h_ks[p].kp;
+                    steps = std::max(steps, H->h_ks[p].kp);
+                }
+            for (int t = 0; t < steps; ++t) {
+                double worst = 0.0;
+                for (int p = 0; p < P; ++p)
+                    if (need[p] && t < H->h_ks[p].kp)
+                        worst = std::max(worst, eh[static_cast<size_t>(p) * (m + 1) + t]);
+                if (hist) hist[hist_n++] = worst;
+            }
+            total += steps;
         }
         // x += Z y for every problem that took steps
         launch_solve_y(H->d_ks, P, m, H->d_H, H->d_g, H->d_y, st);

@@ -204,9 +204,13 @@ __global__ void k_start_cycle(const DevProb *__restrict__ probs, const KState *_
 
 // One thread per problem.  Rotation [[c, s], [-conj(s), c]] with c real
 // zeroes h_{j+1,j}; g_{j+1} = -conj(s) g_j, g_j = c g_j.
+// hist (optional): est / ||b|| of step j at hist[p (m + 1) + j]; active
+// (optional): the problem's in-cycle flag after this step, for the next
+// step's launches.
 __global__ void k_givens(KState *__restrict__ ks, int nprob, int j, int m, double2 *__restrict__ H,
                          double *__restrict__ cs, double2 *__restrict__ sn,
-                         double2 *__restrict__ gv, double *__restrict__ hist) {
+                         double2 *__restrict__ gv, double *__restrict__ hist,
+                         int *__restrict__ active) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob || ks[p].in_cycle == 0) return;
     double2 *Hc = H + static_cast<long long>(p) * (m + 1) * m + static_cast<long long>(j) * (m + 1);
@@ -253,10 +257,11 @@ __global__ void k_givens(KState *__restrict__ ks, int nprob, int j, int m, doubl
     KState &K = ks[p];
     K.est = est;
     K.kp = j + 1;
-    if (hist != nullptr) hist[p] = est / K.bnorm;
+    if (hist != nullptr) hist[static_cast<long long>(p) * (m + 1) + j] = est / K.bnorm;
     const bool brk = hn <= 1e-14 * sqrt(colnorm2);
     if (brk) K.breakdown = 1;
     if (est <= K.rtol * K.bnorm || brk || j + 1 == m) K.in_cycle = 0;
+    if (active != nullptr) active[p] = K.in_cycle;
 }
 
 // Back substitution R y = g (one thread per problem, kp <= m).
@@ -387,8 +392,27 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
     const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef, long long ntot,
     const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,
     double2 *__restrict__ H, double2 *__restrict__ part2, unsigned long long *bar,
-    unsigned long long epoch0, int *err) {
+    unsigned long long epoch0, int *err, int nprob) {
     __shared__ cplx<double> sh[kRedThreads];
+    // No problem left in the cycle (the host enqueues steps ahead of the
+    // convergence test): every block sees the same flags, so the whole grid
+    // skips the step and only advances the barrier counters by the step's
+    // j + 2 barriers, as if it had taken them.
+    bool any = false;
+    for (int q = 0; q < nprob; ++q) any = any || ks[q].in_cycle != 0;
+    if (!any) {
+        if (threadIdx.x == 0) {
+            const unsigned long long nbar = static_cast<unsigned long long>(j) + 2;
+            unsigned long long *garr = bar + kBarStride * (blockIdx.x / kBarGroup + 1);
+            atomicAdd(garr, nbar);
+            if (blockIdx.x % kBarGroup == 0) {
+                atomicAdd(bar, nbar);
+                __hip_atomic_store(garr + 16, epoch0 + nbar, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        return;
+    }
     const ArnoldiBlock B = blocks[blockIdx.x];
     const int nblocks = gridDim.x;
     const int p = B.prob;
@@ -497,9 +521,9 @@ void launch_start_cycle(const DevProb *probs, int nprob, long long max_ndof, con
 }
 
 void launch_givens(KState *ks, int nprob, int j, int m, double2 *H, double *cs, double2 *sn,
-                   double2 *g, double *hist, hipStream_t s) {
+                   double2 *g, double *hist, int *active, hipStream_t s) {
     hipLaunchKernelGGL(k_givens, dim3((nprob + 63) / 64), dim3(64), 0, s, ks, nprob, j, m, H, cs,
-                       sn, g, hist);
+                       sn, g, hist, active);
 }
 
 void launch_solve_y(const KState *ks, int nprob, int m, const double2 *H, const double2 *g,
@@ -530,11 +554,11 @@ int arnoldi_block_capacity(int E, int *blocks_per_cu) {
 hipError_t launch_arnoldi(int E, int nblocks, const DevProb *probs, const KState *ks,
                           const ArnoldiBlock *blocks, const double2 *coef, long long ntot,
                           const double2 *zj, double2 *V, int j, int m, double2 *H, double2 *part2,
-                          unsigned long long *bar, unsigned long long epoch0, int *err,
+                          unsigned long long *bar, unsigned long long epoch0, int *err, int nprob,
                           hipStream_t s) {
     void *args[] = {(void *)&probs, (void *)&ks, (void *)&blocks, (void *)&coef, (void *)&ntot,
                     (void *)&zj, (void *)&V, (void *)&j, (void *)&m, (void *)&H, (void *)&part2,
-                    (void *)&bar, (void *)&epoch0, (void *)&err};
+                    (void *)&bar, (void *)&epoch0, (void *)&err, (void *)&nprob};
     const void *fn = E <= 8 ? reinterpret_cast<const void *>(k_arnoldi<8>)
                             : reinterpret_cast<const void *>(k_arnoldi<16>);
     return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kRedThreads), args, 0, s);
