@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--applies", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (default: tune once before the warmup, outside the "
+                         "timed region, and set every timed handle up from its cache)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batch (seeded multi-source problems, one handle)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -113,9 +116,24 @@ def main():
     ndof = f.numel()
     stream = torch.cuda.current_stream()
 
+    import tempfile
+    cache = None if args.no_tune else os.path.join(
+        tempfile.gettempdir(), "ras_pml_tune_%s_%d.json" % (args.workload, os.getpid()))
+    tuning = {}
+    if cache is not None:
+        for name, prec in (("mixed", rp.RAS_MIXED), ("fp64", rp.RAS_FP64)):
+            if name == "fp64" and args.no_fp64:
+                continue
+            Ht = rp.ras_pml_setup(k, h, grid, subs, L, L, rp.default_opts(global_pml=G, precision=prec))
+            rp.ras_pml_autotune(Ht, cache)
+            tuning[name] = rp.ras_pml_tuning(Ht)
+            Ht.close()
+
     def one_solve(precision, timing=False):
         opts = rp.default_opts(global_pml=G, precision=precision,
                                flags=rp.RAS_FLAG_TIMING if timing else 0)
+        if cache is not None:
+            opts.tune_cache = os.fsencode(cache)
         t0 = time.perf_counter()
         H = rp.ras_pml_setup(k, h, grid, subs, L, L, opts)
         b = torch.empty_like(f)
@@ -175,6 +193,10 @@ def main():
                       "givens": round(st["givens_ms"], 3)},
                   "setup_assemble_ms": round(st["setup_assemble_ms"], 3),
                   "setup_factor_ms": round(st["setup_factor_ms"], 3)},
+        "tuning": {name: {"band_solve_deep_prefetch": t["solve_deep"],
+                          "factor_classes": [{"tiles": g[0], "subdomains": g[1],
+                                              "128_register_variant": g[2]} for g in t["ldlt"]]}
+                   for name, t in tuning.items()},
         "roofline": {"kernel": "k_band_solve (batched forward/backward band sweeps)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -202,7 +224,10 @@ def main():
     for name, prec in (("mixed", rp.RAS_MIXED), ("fp64", rp.RAS_FP64)):
         if name == "fp64" and args.no_fp64:
             continue
-        H = rp.ras_pml_setup(k, h, grid, subs, L, L, rp.default_opts(global_pml=G, precision=prec))
+        o = rp.default_opts(global_pml=G, precision=prec)
+        if cache is not None:
+            o.tune_cache = os.fsencode(cache)
+        H = rp.ras_pml_setup(k, h, grid, subs, L, L, o)
         v = torch.from_numpy(inputs.random_vector(ndof, 1)).to(dev)
         z = torch.empty_like(v)
         rp.ras_pml_apply(H, v, z)
@@ -224,6 +249,8 @@ def main():
     # ---------------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(k, n_int, P, L, G, mixed["iters"], args.workload)
+    if cache is not None and os.path.exists(cache):
+        os.remove(cache)
     print(json.dumps(out), flush=True)
 
 

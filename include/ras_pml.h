@@ -70,13 +70,17 @@ typedef struct {
                           global vectors, SpMV and Krylov work complex128;
                           RAS_FP64: complex128 everywhere                     */
     int flags;         /* bitwise OR of RAS_FLAG_*                            */
+    const char *tune_cache; /* path of a tuning cache written by
+                          ras_pml_autotune, or NULL: setup then uses the
+                          cached kernel variants for the configurations the
+                          file knows (a missing file is an empty cache)       */
 } ras_pml_opts;
 
 /* Number of int32 fields in one subdomain descriptor (ras_pml_plan). */
 #define RAS_DESC_INTS 24
 
 /* Fill *o with the defaults (sigma = 10 k, global PML = pml_width,
- * impedance, linear PoU, mixed precision, no flags). */
+ * impedance, linear PoU, mixed precision, no flags, no tuning cache). */
 void ras_pml_default_opts(ras_pml_opts *o);
 
 /* Host-only planning: validates the parameters exactly as ras_pml_setup
@@ -194,8 +198,34 @@ typedef struct {
     double solve_bytes;    /* algorithmic bytes of one band-solve launch      */
     double factor_bytes;   /* bytes of all stored factors                     */
 } ras_pml_stats;
+/* Launch counts cover the GMRES steps that ran: steps enqueued after every
+ * problem had stopped (gmres_solve enqueues up to eight ahead of its
+ * convergence test) return at once and are not counted; their few
+ * microseconds remain in the times. */
 int ras_pml_get_stats(ras_pml_t H, ras_pml_stats *out);
 int ras_pml_reset_stats(ras_pml_t H);
+
+/* Autotuner (performance only: every variant computes the same values).
+ * Times, on this handle's own factors and subdomain tables, the kernel
+ * variants whose best choice depends on the band width and the number of
+ * subdomains, and keeps the faster for the handle's later calls:
+ *   - per complex64 factorisation window class (tiles per side): the
+ *     128-register variant (four workgroups per CU) or the unconstrained
+ *     one (re-runs that class's factorisation; the factor is unchanged);
+ *   - the band-solve prefetch depth (32 or 16 vectors in complex64, 16 or 8
+ *     in complex128).
+ * cache_path (nullable): the choices are merged into this flat JSON file,
+ * keyed "arch/precision/kernel/class/count" (counts rounded up to a power
+ * of two), for ras_pml_opts.tune_cache.  Allocates one temporary vector;
+ * synchronises `stream`.  Errors: RAS_EINVAL (no handle, or the cache file
+ * cannot be written), RAS_ENOMEM, RAS_EHIP.                                */
+int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream);
+
+/* Current variant choices: *solve_deep (1: deep prefetch); *n_groups window
+ * classes of the complex64 factorisation (0 in the FP64 path), the first
+ * cap_groups of them as (tiles per side, subdomains, 128-register variant
+ * 0/1) triples in groups.  Errors: RAS_EINVAL.                             */
+int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, int *n_groups);
 
 const char *ras_pml_strerror(int status);
 const char *ras_pml_last_error(ras_pml_t H);

@@ -36,7 +36,8 @@ _STATUS = {0: "RAS_OK", 1: "RAS_EINVAL", 2: "RAS_ENOMEM", 3: "RAS_EHIP", 4: "RAS
 
 class Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("global_pml", ctypes.c_int), ("bc", ctypes.c_int),
-                ("pou", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("pou", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class Stats(ctypes.Structure):
@@ -86,6 +87,8 @@ SYMBOLS = [
     ("ras_pml_export_factor", _I, [_P, _I, _P, _LL]),
     ("ras_pml_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
     ("ras_pml_reset_stats", _I, [_P]),
+    ("ras_pml_autotune", _I, [_P, ctypes.c_char_p, _P]),
+    ("ras_pml_tuning", _I, [_P, _IP, _IP, _I, _IP]),
     ("ras_pml_strerror", ctypes.c_char_p, [_I]),
     ("ras_pml_last_error", ctypes.c_char_p, [_P]),
 ]
@@ -121,6 +124,8 @@ def default_opts(**kw) -> Opts:
     o = Opts()
     lib().ras_pml_default_opts(ctypes.byref(o))
     for k, v in kw.items():
+        if k == "tune_cache" and isinstance(v, (str, os.PathLike)):
+            v = os.fsencode(v)
         setattr(o, k, v)
     return o
 
@@ -343,6 +348,25 @@ def ras_pml_reset_stats(H: Handle):
     rc = lib().ras_pml_reset_stats(H.ptr)
     if rc:
         H._raise(rc)
+
+
+def ras_pml_autotune(H: Handle, cache_path=None, stream=None):
+    path = None if cache_path is None else os.fsencode(cache_path)
+    rc = lib().ras_pml_autotune(H.ptr, path, _stream(stream))
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_tuning(H: Handle) -> dict:
+    """{"solve_deep": bool, "ldlt": [(tiles, subdomains, occupancy_variant), ...]}"""
+    deep, ng = ctypes.c_int(0), ctypes.c_int(0)
+    cap = 16
+    buf = (ctypes.c_int * (3 * cap))()
+    rc = lib().ras_pml_tuning(H.ptr, ctypes.byref(deep), buf, cap, ctypes.byref(ng))
+    if rc:
+        H._raise(rc)
+    groups = [(buf[3 * i], buf[3 * i + 1], bool(buf[3 * i + 2])) for i in range(min(cap, ng.value))]
+    return {"solve_deep": bool(deep.value), "ldlt": groups}
 
 
 def ras_pml_strerror(status: int) -> str:

@@ -5,6 +5,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <memory>
@@ -25,9 +26,11 @@ void launch_rhs(const DevProb *, int, long long, const double2 *, double2 *, hip
 void launch_band_ldlt(bool, int, const DevSub *, const int *, int, const double2 *, void *, int *,
                       hipStream_t);
 int ldlt_mfma_tiles(int W);
-void launch_band_ldlt_mfma(int, const DevSub *, const int *, int, const double2 *, void *, int *,
-                           hipStream_t);
-void launch_band_solve(bool, int, const DevProb *, const DevSub *, const int *, int, const int *,
+bool ldlt_mfma_default_occ(int NT);
+void launch_band_ldlt_mfma(int, bool, const DevSub *, const int *, int, const double2 *, void *,
+                           int *, hipStream_t);
+void launch_band_solve(bool, bool, int, const DevProb *, const DevSub *, const int *, int,
+                       const int *,
                        const double2 *, const void *, void *, void *, hipStream_t);
 void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
                     const int *, const int *, const double *, const void *, double2 *, hipStream_t);
@@ -73,9 +76,14 @@ struct ras_pml_handle {
     std::vector<DevSub> hsubs;
     std::vector<int> order;
     // complex64 factorisation: subdomains grouped by window size (tiles per
-    // side), largest first within a group; {tiles, first, count} per group
+    // side), largest first within a group; {tiles, first, count, occupancy
+    // variant} per group
     std::vector<int> lu_order;
-    std::vector<std::array<int, 3>> lu_groups;
+    std::vector<std::array<int, 4>> lu_groups;
+    bool solve_deep = true;    // band-solve prefetch depth variant
+    std::string arch;          // gfx name of the device (tuning cache keys)
+    std::string tune_cache;    // opts.tune_cache (empty: none)
+    long long skipped_steps = 0;   // GMRES steps enqueued after every problem had stopped
     int nprob = 0, nsub = 0, maxW = 0, max_n = 0;
     long long ntot = 0, nloc = 0, nvec = 0, max_ndof = 0;
     bool fp64 = false;
@@ -242,6 +250,8 @@ ras_pml_handle::~ras_pml_handle() {
 
 namespace {
 
+void apply_cache(ras_pml_handle *H, const char *path);
+
 int build(ras_pml_handle *H, hipStream_t st) {
     // ---- concatenate problems
     H->nprob = static_cast<int>(H->plans.size());
@@ -315,10 +325,12 @@ int build(ras_pml_handle *H, hipStream_t st) {
         for (int i = 0; i < H->nsub;) {
             int e = i;
             while (e < H->nsub && tiles(H->lu_order[e]) == tiles(H->lu_order[i])) ++e;
-            H->lu_groups.push_back({tiles(H->lu_order[i]), i, e - i});
+            const int nt = tiles(H->lu_order[i]);
+            H->lu_groups.push_back({nt, i, e - i, ldlt_mfma_default_occ(nt) ? 1 : 0});
             i = e;
         }
     }
+    if (!H->tune_cache.empty()) apply_cache(H, H->tune_cache.c_str());
 
     // algorithmic bytes of one band-solve launch: L read by both sweeps,
     // D^{-1}, the gathered right-hand side (complex128), the forward result
@@ -380,8 +392,8 @@ int build(ras_pml_handle *H, hipStream_t st) {
         HCHK(H, hipGetLastError());
     } else {
         for (const auto &g : H->lu_groups) {
-            launch_band_ldlt_mfma(g[0], H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst, H->d_F,
-                                  H->d_status, st);
+            launch_band_ldlt_mfma(g[0], g[3] != 0, H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
+                                  H->d_F, H->d_status, st);
             HCHK(H, hipGetLastError());
         }
     }
@@ -503,7 +515,8 @@ int check_handle(ras_pml_handle *H) { return H ? RAS_OK : RAS_EINVAL; }
 int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st) {
     {
         Timer t(H, C_SOLVE, st);
-        launch_band_solve(H->fp64, H->maxW, H->d_probs, H->d_subs, H->d_order, H->nsub, active, v,
+        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
+                          H->nsub, active, v,
                           H->d_F, H->d_ybuf, H->d_xout, st);
     }
     HCHK(H, hipGetLastError());
@@ -596,7 +609,9 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
         // launch as a whole once no problem is left).  The host looks at the
         // flags every kSyncSteps steps and stops enqueueing when none is set.
         constexpr int kSyncSteps = 8;
+        int enqueued = 0;
         for (int j = 0; j < mc; ++j) {
+            ++enqueued;
             const long long n = H->ntot;
             double2 *Vj = H->d_V + static_cast<long long>(j) * n;
             double2 *Vj1 = H->d_V + static_cast<long long>(j + 1) * n;
@@ -667,6 +682,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
                 if (hist) hist[hist_n++] = worst;
             }
             total += steps;
+            H->skipped_steps += enqueued - steps;
         }
         // x += Z y for every problem that took steps
         launch_solve_y(H->d_ks, P, m, H->d_H, H->d_g, H->d_y, st);
@@ -739,6 +755,7 @@ int setup_common(int nprob, const double *k, const double *h, const int *grid, c
     }
     H->fp64 = o.precision == RAS_FP64;
     H->flags = o.flags;
+    if (o.tune_cache) H->tune_cache = o.tune_cache;
     int rc = build(H.get(), as_stream(stream));
     if (rc != RAS_OK) {
         g_plan_error = H->last_error;
@@ -746,6 +763,99 @@ int setup_common(int nprob, const double *k, const double *h, const int *grid, c
     }
     *out = H.release();
     return RAS_OK;
+}
+
+// ---- tuning cache: a flat JSON object {"key": 0 | 1, ...}
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+int pow2_bucket(int n) {
+    int b = 1;
+    while (b < n) b <<= 1;
+    return b;
+}
+
+std::string lu_key(const ras_pml_handle *H, const std::array<int, 4> &g) {
+    return H->arch + "/c64/ldlt/tiles=" + std::to_string(g[0]) + "/count=" +
+           std::to_string(pow2_bucket(g[2]));
+}
+
+std::string solve_key(const ras_pml_handle *H) {
+    return H->arch + (H->fp64 ? "/c128" : "/c64") + "/solve/maxW=" + std::to_string(H->maxW) +
+           "/nsub=" + std::to_string(pow2_bucket(H->nsub));
+}
+
+// Reads "key": integer pairs; a missing or unreadable file is an empty cache.
+std::vector<std::pair<std::string, int>> read_cache(const char *path) {
+    std::vector<std::pair<std::string, int>> out;
+    FILE *f = path ? std::fopen(path, "rb") : nullptr;
+    if (!f) return out;
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        std::string key = txt.substr(i + 1, j - i - 1);
+        size_t k = txt.find(':', j);
+        if (k == std::string::npos) break;
+        char *end = nullptr;
+        const long v = std::strtol(txt.c_str() + k + 1, &end, 10);
+        if (end != txt.c_str() + k + 1) out.emplace_back(key, static_cast<int>(v));
+        i = end ? static_cast<size_t>(end - txt.c_str()) : k + 1;
+    }
+    return out;
+}
+
+int cache_lookup(const std::vector<std::pair<std::string, int>> &c, const std::string &key,
+                 int fallback) {
+    for (const auto &kv : c)
+        if (kv.first == key) return kv.second;
+    return fallback;
+}
+
+bool write_cache(const char *path, std::vector<std::pair<std::string, int>> c) {
+    std::sort(c.begin(), c.end());
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < c.size(); ++i)
+        std::fprintf(f, "  \"%s\": %d%s\n", c[i].first.c_str(), c[i].second,
+                     i + 1 < c.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+void cache_set(std::vector<std::pair<std::string, int>> &c, const std::string &key, int v) {
+    for (auto &kv : c)
+        if (kv.first == key) {
+            kv.second = v;
+            return;
+        }
+    c.emplace_back(key, v);
+}
+
+// Choices from the cache (setup): classes and configurations it does not
+// know keep their defaults.
+void apply_cache(ras_pml_handle *H, const char *path) {
+    if (!path) return;
+    const auto c = read_cache(path);
+    if (c.empty()) return;
+    if (H->arch.empty()) H->arch = device_arch();
+    for (auto &g : H->lu_groups) g[3] = cache_lookup(c, lu_key(H, g), g[3]) != 0;
+    H->solve_deep = cache_lookup(c, solve_key(H), H->solve_deep) != 0;
 }
 
 }  // namespace
@@ -761,6 +871,7 @@ void ras_pml_default_opts(ras_pml_opts *o) {
     o->pou = RAS_POU_LINEAR;
     o->precision = RAS_MIXED;
     o->flags = 0;
+    o->tune_cache = nullptr;
 }
 
 const char *ras_pml_plan_error(void) { return g_plan_error.c_str(); }
@@ -892,7 +1003,8 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
     hipStream_t st = as_stream(stream);
     {
         Timer t(H, C_SOLVE, st);
-        launch_band_solve(H->fp64, H->maxW, H->d_probs, H->d_subs, H->d_order, H->nsub, nullptr,
+        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
+                          H->nsub, nullptr,
                           static_cast<const double2 *>(v), H->d_F, H->d_ybuf, H->d_xout, st);
     }
     HCHK(H, hipGetLastError());
@@ -968,10 +1080,104 @@ int ras_pml_export_factor(ras_pml_t H, int j, void *host_out, long long cap_valu
     return RAS_OK;
 }
 
+int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
+    if (!H) return RAS_EINVAL;
+    hipStream_t st = as_stream(stream);
+    if (H->arch.empty()) H->arch = device_arch();
+    hipEvent_t e0{}, e1{};
+    HCHK(H, hipEventCreate(&e0));
+    HCHK(H, hipEventCreate(&e1));
+    // best of `reps` timed runs of fn (ms)
+    auto timeit = [&](auto fn, int reps) -> float {
+        float best = 1e30f;
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(e0, st) != hipSuccess) return best;
+            fn();
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return best;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = std::min(best, ms);
+        }
+        return best;
+    };
+    int rc = RAS_OK;
+    // factorisation classes (complex64): both register budgets; the factor
+    // they write is the same
+    if (!H->fp64)
+        for (auto &g : H->lu_groups) {
+            float t[2];
+            for (int occ = 0; occ < 2; ++occ)
+                t[occ] = timeit([&] {
+                    launch_band_ldlt_mfma(g[0], occ != 0, H->d_subs, H->d_lu_order + g[1], g[2],
+                                          H->d_lst, H->d_F, H->d_status, st);
+                }, 2);
+            g[3] = t[1] <= t[0] ? 1 : 0;
+        }
+    // band solve: both prefetch depths on a zero right-hand side (the kernel
+    // has no data-dependent control flow)
+    double2 *v = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&v), sizeof(double2) * H->ntot) != hipSuccess) {
+        H->last_error = "autotune: no memory for the test vector";
+        rc = RAS_ENOMEM;
+    } else {
+        float t[2];
+        if (hipMemsetAsync(v, 0, sizeof(double2) * H->ntot, st) == hipSuccess) {
+            for (int deep = 0; deep < 2; ++deep)
+                t[deep] = timeit([&] {
+                    launch_band_solve(H->fp64, deep != 0, H->maxW, H->d_probs, H->d_subs,
+                                      H->d_order, H->nsub, nullptr, v, H->d_F, H->d_ybuf,
+                                      H->d_xout, st);
+                }, 3);
+            H->solve_deep = t[1] <= t[0];
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(v);
+    }
+    const hipError_t e = hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        H->last_error = std::string("autotune: ") + hipGetErrorString(e);
+        return RAS_EHIP;
+    }
+    if (rc != RAS_OK) return rc;
+    if (cache_path) {
+        auto c = read_cache(cache_path);
+        if (!H->fp64)
+            for (const auto &g : H->lu_groups) cache_set(c, lu_key(H, g), g[3]);
+        cache_set(c, solve_key(H), H->solve_deep ? 1 : 0);
+        if (!write_cache(cache_path, c)) {
+            H->last_error = std::string("autotune: cannot write ") + cache_path;
+            return RAS_EINVAL;
+        }
+    }
+    return RAS_OK;
+}
+
+int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, int *n_groups) {
+    if (!H || !solve_deep || !n_groups || (cap_groups > 0 && !groups)) return RAS_EINVAL;
+    *solve_deep = H->solve_deep ? 1 : 0;
+    *n_groups = static_cast<int>(H->lu_groups.size());
+    for (int i = 0; i < std::min(cap_groups, *n_groups); ++i) {
+        groups[3 * i + 0] = H->lu_groups[i][0];
+        groups[3 * i + 1] = H->lu_groups[i][2];
+        groups[3 * i + 2] = H->lu_groups[i][3];
+    }
+    return RAS_OK;
+}
+
 int ras_pml_get_stats(ras_pml_t H, ras_pml_stats *out) {
     if (!H || !out) return RAS_EINVAL;
     collect_events(H);
     *out = H->stats;
+    // launches of steps enqueued after convergence returned at once: count
+    // only the steps that ran (their few microseconds stay in the times)
+    const long long sk = H->skipped_steps;
+    out->n_solve = std::max(0LL, out->n_solve - sk);
+    out->n_sum = std::max(0LL, out->n_sum - sk);
+    out->n_givens = std::max(0LL, out->n_givens - sk);
+    out->n_mgs = std::max(0LL, out->n_mgs - sk);
+    if (H->arn_E <= 0) out->n_spmv = std::max(0LL, out->n_spmv - sk);
     return RAS_OK;
 }
 
@@ -981,6 +1187,7 @@ int ras_pml_reset_stats(ras_pml_t H) {
     const double sb = H->stats.solve_bytes, fb = H->stats.factor_bytes;
     const double a = H->stats.setup_assemble_ms, f = H->stats.setup_factor_ms;
     std::memset(&H->stats, 0, sizeof(H->stats));
+    H->skipped_steps = 0;
     H->stats.solve_bytes = sb;
     H->stats.factor_bytes = fb;
     H->stats.setup_assemble_ms = a;

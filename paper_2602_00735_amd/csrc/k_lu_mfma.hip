@@ -139,11 +139,14 @@ __device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
     q = left;
 }
 
-// Up to NT = 7 (W <= 97) the kernel is held to 128 registers, so that
-// four workgroups (one subdomain each) share a CU: at k = 640 all 1024
-// subdomains are then resident at once.  Larger windows need more.
-template <int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 7 ? 4 : 1))) void
+// OCC: the kernel is held to 128 registers, so that four workgroups (one
+// subdomain each) share a CU (at k = 640 all 1024 subdomains are then
+// resident at once; the largest windows spill a little to fit).  Without
+// it the compiler's own budget applies (two workgroups per CU, no spills).
+// Which is faster depends on the window and the number of subdomains; the
+// default is OCC up to NT = 7 and the autotuner measures both.
+template <int NT, bool OCC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 4 : 1))) void
 k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                                                         const int *__restrict__ order,
                                                         const double2 *__restrict__ lst_all,
@@ -291,10 +294,14 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
 }
 
 template <int NT>
-void launch_nt(const DevSub *subs, const int *order, int count, const double2 *lst, void *F,
-               int *status, hipStream_t st) {
-    hipLaunchKernelGGL(k_band_ldlt_mfma<NT>, dim3(count), dim3(256), 0, st, subs, order, lst,
-                       static_cast<cplx<float> *>(F), status);
+void launch_nt(bool occ, const DevSub *subs, const int *order, int count, const double2 *lst,
+               void *F, int *status, hipStream_t st) {
+    if (occ)
+        hipLaunchKernelGGL((k_band_ldlt_mfma<NT, true>), dim3(count), dim3(256), 0, st, subs, order,
+                           lst, static_cast<cplx<float> *>(F), status);
+    else
+        hipLaunchKernelGGL((k_band_ldlt_mfma<NT, false>), dim3(count), dim3(256), 0, st, subs,
+                           order, lst, static_cast<cplx<float> *>(F), status);
 }
 
 }  // namespace
@@ -302,18 +309,21 @@ void launch_nt(const DevSub *subs, const int *order, int count, const double2 *l
 // Window tiles per side for a factor column length W (at most 128).
 int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }
 
+// Default register budget of a window class (see k_band_ldlt_mfma).
+bool ldlt_mfma_default_occ(int NT) { return NT <= 7; }
+
 // count subdomains order[0 .. count) that all have ldlt_mfma_tiles(W) == NT.
-void launch_band_ldlt_mfma(int NT, const DevSub *subs, const int *order, int count,
+void launch_band_ldlt_mfma(int NT, bool occ, const DevSub *subs, const int *order, int count,
                            const double2 *lst, void *F, int *status, hipStream_t st) {
     switch (NT) {
-        case 2: launch_nt<2>(subs, order, count, lst, F, status, st); break;
-        case 3: launch_nt<3>(subs, order, count, lst, F, status, st); break;
-        case 4: launch_nt<4>(subs, order, count, lst, F, status, st); break;
-        case 5: launch_nt<5>(subs, order, count, lst, F, status, st); break;
-        case 6: launch_nt<6>(subs, order, count, lst, F, status, st); break;
-        case 7: launch_nt<7>(subs, order, count, lst, F, status, st); break;
-        case 8: launch_nt<8>(subs, order, count, lst, F, status, st); break;
-        default: launch_nt<9>(subs, order, count, lst, F, status, st); break;
+        case 2: launch_nt<2>(occ, subs, order, count, lst, F, status, st); break;
+        case 3: launch_nt<3>(occ, subs, order, count, lst, F, status, st); break;
+        case 4: launch_nt<4>(occ, subs, order, count, lst, F, status, st); break;
+        case 5: launch_nt<5>(occ, subs, order, count, lst, F, status, st); break;
+        case 6: launch_nt<6>(occ, subs, order, count, lst, F, status, st); break;
+        case 7: launch_nt<7>(occ, subs, order, count, lst, F, status, st); break;
+        case 8: launch_nt<8>(occ, subs, order, count, lst, F, status, st); break;
+        default: launch_nt<9>(occ, subs, order, count, lst, F, status, st); break;
     }
 }
 

@@ -284,22 +284,30 @@ void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order
 
 }  // namespace
 
-// One wave per subdomain; the prefetch depth keeps ~32 (complex64) or ~16
-// (complex128) factor columns in flight per wave.
-void launch_band_solve(bool fp64, int maxW, const DevProb *probs, const DevSub *subs,
+// One wave per subdomain.  deep: prefetch depth 32 (complex64) / 16
+// (complex128) vectors, else half of that; the default is deep, the
+// autotuner measures both.  F must carry 64 KB of slack past the last
+// factor (the prefetch runs past each stream's end).
+void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, const DevSub *subs,
                        const int *order, int nsub, const int *active, const double2 *v,
                        const void *F, void *ybuf, void *xout, hipStream_t st) {
+    const bool two = maxW > 64;
+#define RAS_SOLVE(T, TWO, PD) \
+    launch_solve_cfg<T, TWO, PD>(probs, subs, order, nsub, active, v, F, ybuf, xout, st)
     if (fp64) {
-        if (maxW <= 64)
-            launch_solve_cfg<double, false, 16>(probs, subs, order, nsub, active, v, F, ybuf, xout, st);
-        else
-            launch_solve_cfg<double, true, 16>(probs, subs, order, nsub, active, v, F, ybuf, xout, st);
+        if (two) {
+            if (deep) RAS_SOLVE(double, true, 16); else RAS_SOLVE(double, true, 8);
+        } else {
+            if (deep) RAS_SOLVE(double, false, 16); else RAS_SOLVE(double, false, 8);
+        }
     } else {
-        if (maxW <= 64)
-            launch_solve_cfg<float, false, 32>(probs, subs, order, nsub, active, v, F, ybuf, xout, st);
-        else
-            launch_solve_cfg<float, true, 32>(probs, subs, order, nsub, active, v, F, ybuf, xout, st);
+        if (two) {
+            if (deep) RAS_SOLVE(float, true, 32); else RAS_SOLVE(float, true, 16);
+        } else {
+            if (deep) RAS_SOLVE(float, false, 32); else RAS_SOLVE(float, false, 16);
+        }
     }
+#undef RAS_SOLVE
 }
 
 void launch_pou_sum(bool fp64, const DevProb *probs, int nprob, long long max_ndof,

@@ -503,3 +503,48 @@ def test_config4_batch_of_32_problems():
                 g = sub_first[m] + s
                 a = xg[loc_off[g]:loc_off[g + 1]]
                 assert relerr(a, R.local_part(ref, q)) <= tol, (m, s, prec)
+
+
+# ------------------------------------------------------------------ a8: autotuner
+@pytest.mark.parametrize("precision", [rp.RAS_MIXED, rp.RAS_FP64])
+def test_autotune_cache_round_trip(tmp_path, precision):
+    """The autotuner picks among variants that compute the same values: applies
+    before and after tuning, and with the opposite choices read back from the
+    cache by a new handle, agree bit for bit; the cache holds the choices."""
+    import json
+    pb = PROBLEMS["k40_two_slot"]
+    v = dev(inputs.random_vector(pb.ndof, 31))
+    H = setup_gpu(pb, precision)
+    z0 = torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, z0)
+    path = tmp_path / "tune.json"
+    rp.ras_pml_autotune(H, path)
+    t = rp.ras_pml_tuning(H)
+    z1 = torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, z1)
+    assert torch.equal(z0, z1)
+    cache = json.loads(path.read_text())
+    solve_keys = [k for k in cache if "/solve/" in k]
+    assert len(solve_keys) == 1 and cache[solve_keys[0]] == int(t["solve_deep"])
+    ldlt_keys = sorted(k for k in cache if "/ldlt/" in k)
+    if precision == rp.RAS_MIXED:
+        assert len(ldlt_keys) == len(t["ldlt"]) >= 1
+        for tiles, count, occ in t["ldlt"]:
+            key = [k for k in ldlt_keys if "/tiles=%d/" % tiles in k]
+            assert len(key) == 1 and cache[key[0]] == int(occ)
+    else:
+        assert ldlt_keys == [] and t["ldlt"] == []
+    H.close()
+    # the opposite of every choice, read back at setup
+    flipped = {k: 1 - val for k, val in cache.items()}
+    path.write_text(json.dumps(flipped))
+    o = rp.default_opts(sigma=pb.sigma, global_pml=pb.G, bc=pb.bc, pou=pb.pou,
+                        precision=precision, tune_cache=str(path))
+    H2 = rp.ras_pml_setup(pb.k, 1.0 / pb.n_int, (pb.n_int, pb.n_int), (pb.Px, pb.Py), pb.delta,
+                          pb.kappa, o)
+    t2 = rp.ras_pml_tuning(H2)
+    assert t2["solve_deep"] != t["solve_deep"]
+    assert [g[2] for g in t2["ldlt"]] == [not g[2] for g in t["ldlt"]]
+    z2 = torch.zeros_like(v)
+    rp.ras_pml_apply(H2, v, z2)
+    assert torch.equal(z0, z2)
