@@ -238,7 +238,21 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.applies
-        applies[name] = {"applies_per_s": round(1000.0 / ms, 2), "ms_per_apply": round(ms, 4)}
+        # the same applies replayed from a captured graph
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            rp.ras_pml_apply(H, v, z)
+        g.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.applies):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / args.applies
+        applies[name] = {"applies_per_s": round(1000.0 / ms, 2), "ms_per_apply": round(ms, 4),
+                         "graph_replayed_applies_per_s": round(1000.0 / gms, 2)}
+        del g
         H.close()
     out["applies"] = applies
 

@@ -146,7 +146,11 @@ int ras_pml_rhs(ras_pml_t H, const void *f, void *b, void *stream);
 int ras_pml_spmv(ras_pml_t H, const void *x, void *y, void *stream);
 
 /* z = B^{-1} v = sum_j R~_j^T A_j^{-1} R_j v (Section 2).  v and z must not
- * alias.  Deterministic: the same input gives bitwise the same output.     */
+ * alias.  Deterministic: the same input gives bitwise the same output.
+ * Enqueues two kernels on `stream` and nothing else (no allocation, memset
+ * or synchronisation), so it can be recorded into a HIP graph by stream
+ * capture (with RAS_FLAG_TIMING off: it records events).  Calls on one
+ * handle share its local work vectors: they must not overlap in time.     */
 int ras_pml_apply(ras_pml_t H, const void *v, void *z, void *stream);
 
 /* Local solutions x_j = A_j^{-1} R_j v of every subdomain, back to back in

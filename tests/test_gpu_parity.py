@@ -548,3 +548,37 @@ def test_autotune_cache_round_trip(tmp_path, precision):
     z2 = torch.zeros_like(v)
     rp.ras_pml_apply(H2, v, z2)
     assert torch.equal(z0, z2)
+
+
+# ------------------------------------------------------------------ a8: graph replay
+@pytest.mark.parametrize("precision", [rp.RAS_MIXED, rp.RAS_FP64])
+def test_apply_captured_in_graph(precision):
+    """The apply recorded into a graph (stream capture) and replayed several
+    times, with eager applies of another vector between the replays: every
+    replay equals the eager result bit for bit, and so does the eager work."""
+    pb = PROBLEMS["k40_two_slot"]
+    H = setup_gpu(pb, precision)
+    v = dev(inputs.random_vector(pb.ndof, 41))
+    v2 = dev(inputs.random_vector(pb.ndof, 42))
+    ref, ref2 = torch.zeros_like(v), torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, ref)
+    rp.ras_pml_apply(H, v2, ref2)
+    zg = torch.zeros_like(v)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rp.ras_pml_apply(H, v, zg)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rp.ras_pml_apply(H, v, zg)
+    for _ in range(4):
+        zg.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(zg, ref)
+        z2 = torch.zeros_like(v)
+        rp.ras_pml_apply(H, v2, z2)
+        torch.cuda.synchronize()
+        assert torch.equal(z2, ref2)
