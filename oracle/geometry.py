@@ -86,6 +86,13 @@ class Problem:
         return (np.asarray(i, dtype=np.float64) - self.G) * self.h
 
 
+def paper_width_cells(k: float, h: float, C: float, k0: float = 150.0) -> int:
+    """Section 3 (iii): a width of C l(k) wavelengths, l(k) = k/(k - k0) log2(k/k0)
+    (its limit 1/ln 2 at k = k0), in mesh cells of width h (rounded down)."""
+    lk = 1.0 / math.log(2.0) if k == k0 else k / (k - k0) * math.log2(k / k0)
+    return int(math.floor(C * lk * (2.0 * math.pi / k) / h + 1e-9))
+
+
 def log_width(k: float, h: float) -> int:
     """Overlap / PML width ceil(ln k / (k h)) in mesh layers (natural log)."""
     return int(math.ceil(math.log(k) / (k * h) - 1e-12))

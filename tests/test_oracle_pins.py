@@ -432,3 +432,62 @@ def test_p13_local_pml_impedance_stretched_plane_wave():
         errs.append(np.linalg.norm(uh - u) / np.linalg.norm(u))
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.5, errs
     assert errs[2] < 0.03, errs
+
+
+# ---------------------------------------------------------------- width rule (Section 3 (iii))
+def _width_table():
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(__file__), "golden", "width_rule_tables.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            rows.append(tuple(int(t) for t in line.split()))
+    return rows
+
+
+def test_width_rule_matches_the_paper_tables():
+    """Tables 3/4: the PML column is C_kappa l(k) wavelengths on the listed grid
+    (h = 1/grid); the overlap column is C_delta l(k) wavelengths at 12 points
+    per wavelength (the Section 4 text), not on the listed grid -- the
+    paper's own inconsistency, recorded as a reading."""
+    rows = _width_table()
+    assert len(rows) == 6
+    for k, n, pml, ovlp in rows:
+        assert geometry.paper_width_cells(k, 1.0 / n, 0.5) == pml
+        lam = 2 * np.pi / k
+        assert geometry.paper_width_cells(k, lam / 12, 1.0 / 6.0) == ovlp
+    # continuous at k = k0 and monotone in C
+    assert geometry.paper_width_cells(150.0, 1 / 300, 1.0) == int(np.floor(2 * np.pi / 150 / np.log(2) * 300 + 1e-9))
+    assert geometry.paper_width_cells(600.0, 1 / 1200, 0.25) <= geometry.paper_width_cells(600.0, 1 / 1200, 0.5)
+
+
+# ---------------------------------------------------------------- Richardson (Algorithm 1)
+def test_richardson_one_subdomain_is_one_step():
+    """P = 1: B^{-1} = A^{-1}, so the fixed-point iteration lands on the
+    solution in one step (as GMRES does, P6)."""
+    from oracle import richardson
+    pb = small(k=8.0, n=24, G=3, P=1, L=3)
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    out = richardson.ras_richardson(lambda x: R.A @ x, R.apply, b, rtol=1e-10, maxit=5)
+    assert out.converged and out.iters == 1 and out.relres <= 1e-12
+
+
+def test_richardson_converges_to_the_direct_solution():
+    """Several subdomains: the iteration reaches rtol, its history is the true
+    relative residual of each iterate, and the iterate is the direct solution
+    to within the conditioning of A times rtol."""
+    import scipy.sparse.linalg as spla
+    from oracle import richardson
+    pb = small(k=10.0, n=40, G=4, P=3, L=4)
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    out = richardson.ras_richardson(lambda x: R.A @ x, R.apply, b, rtol=1e-8, maxit=200)
+    assert out.converged and 1 < out.iters < 200
+    assert abs(np.linalg.norm(b - R.A @ out.x) / np.linalg.norm(b) - out.relres) <= 1e-12
+    xs = spla.spsolve(R.A.tocsc(), b)
+    assert np.linalg.norm(out.x - xs) <= 1e-5 * np.linalg.norm(xs)
+    # a plain fixed point: one more step from the converged iterate moves it
+    # by about the residual's size only
+    x2 = out.x + R.apply(b - R.A @ out.x)
+    assert np.linalg.norm(x2 - out.x) <= 1e-6 * np.linalg.norm(out.x)
