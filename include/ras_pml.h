@@ -106,6 +106,16 @@ int ras_pml_plan(double k, double h, const int grid[2], const int subdomains[2],
                  int overlap, int pml_width, const ras_pml_opts *opts,
                  int *nsub, int *desc, int desc_cap);
 
+/* Section 3 (iii), eq. (igg_width): overlap and PML widths of C l(k)
+ * wavelengths, l(k) = k/(k - k0) log2(k/k0) (limit 1/ln 2 at k = k0); the
+ * paper takes k0 = 150, C = 1/6 for the overlap delta and C = 1/2 (Tables
+ * 3/4) for the PML width kappa.  Host only, touches no GPU.
+ *   k, h   wavenumber and mesh width (> 0)
+ *   C      width constant (>= 0), k0 reference wavenumber (> 0)
+ *   cells  out: floor(C l(k) (2 pi / k) / h), the width in mesh cells
+ * Returns RAS_EINVAL (message via ras_pml_plan_error) on a bad argument.    */
+int ras_pml_width_rule(double k, double h, double C, double k0, int *cells);
+
 /* Message of the last failed ras_pml_plan / setup call on this thread. */
 const char *ras_pml_plan_error(void);
 
@@ -172,7 +182,22 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream);
 int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, int maxit,
                 int *iters, double *relres, double *hist, void *stream);
 
-/* Per-problem outcome of the last gmres_solve on a batch handle. */
+/* Algorithm 1 (Section 2) as a solver: the fixed-point iteration
+ * x <- x + B^{-1} (b - A x), every step one batched local solve and the
+ * PoU-weighted sum added into x, the residual in complex128.  x holds x0 on
+ * entry and the iterate on return.  Stops when ||b - A x|| <= rtol ||b||
+ * (checked after every step) or after maxit steps.  iters/relres
+ * (nullable) get the step count and the final relative residual; hist
+ * (nullable, maxit+1 doubles, host) gets the relative residual of x0 and
+ * of every iterate.  Batch handles: as gmres_solve (each problem stops on
+ * its own; hist and relres give the worst problem; per problem through
+ * ras_pml_batch_result).  Synchronises `stream` after every step.
+ * Errors: RAS_EINVAL, RAS_ENONFINITE, RAS_ENOTCONV, RAS_ENOMEM, RAS_EHIP.  */
+int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int maxit, int *iters,
+                       double *relres, double *hist, void *stream);
+
+/* Per-problem outcome of the last gmres_solve or ras_pml_richardson on a
+ * batch handle. */
 int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged);
 
 /* Inspection (tests).  All outputs are HOST memory, complex128.

@@ -18,6 +18,8 @@ frequency Helmholtz equation" (Xie, Gong, Graham, Spence, Zhang):
                    (Section 2, discrete RAS, eq. (local-ras-discrete)/(update1)).
 * ``gmres``     -- restarted right-preconditioned GMRES(m) with modified
                    Gram-Schmidt and complex Givens rotations (Section 4.1).
+* ``richardson``-- the preconditioner used as a fixed-point iteration
+                   (Algorithm 1).
 
 Everything is complex128 / float64 and deliberately unoptimised.
 """

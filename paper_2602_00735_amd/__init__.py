@@ -81,6 +81,8 @@ SYMBOLS = [
     ("ras_pml_apply", _I, [_P, _P, _P, _P]),
     ("ras_pml_local_solve", _I, [_P, _P, _P, _P]),
     ("gmres_solve", _I, [_P, _P, _P, _D, _I, _I, _IP, _DP, _DP, _P]),
+    ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
+    ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
     ("ras_pml_export_stencil", _I, [_P, _P]),
     ("ras_pml_export_local", _I, [_P, _I, _P]),
@@ -295,6 +297,31 @@ def gmres_solve(H: Handle, b, x, rtol=1e-6, restart=100, maxit=500, stream=None,
     if check and rc not in (RAS_OK, RAS_ENOTCONV, RAS_EBREAKDOWN):
         H._raise(rc)
     return rc, it.value, rr.value, hist[:it.value + 1]
+
+
+def ras_pml_richardson(H: Handle, b, x, rtol=1e-6, maxit=500, stream=None, check=True):
+    """Algorithm 1 iteration.  Returns (status, iters, relres, hist).  Raises
+    on errors other than RAS_ENOTCONV unless check=False."""
+    import numpy as np
+    _check_vec(b, H.ndof, "b")
+    _check_vec(x, H.ndof, "x")
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    rc = lib().ras_pml_richardson(H.ptr, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(it),
+                                  ctypes.byref(rr), hist.ctypes.data_as(_DP), _stream(stream))
+    if check and rc not in (RAS_OK, RAS_ENOTCONV):
+        H._raise(rc)
+    return rc, it.value, rr.value, hist[:it.value + 1]
+
+
+def ras_pml_width_rule(k, h, C, k0=150.0):
+    """Section 3 (iii) width in mesh cells (host only)."""
+    cells = ctypes.c_int(0)
+    rc = lib().ras_pml_width_rule(float(k), float(h), float(C), float(k0), ctypes.byref(cells))
+    if rc:
+        raise ValueError(lib().ras_pml_plan_error().decode())
+    return cells.value
 
 
 def ras_pml_batch_result(H: Handle, p):

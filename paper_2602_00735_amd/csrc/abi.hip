@@ -33,7 +33,8 @@ void launch_band_solve(bool, bool, int, const DevProb *, const DevSub *, const i
                        const int *,
                        const double2 *, const void *, void *, void *, hipStream_t);
 void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
-                    const int *, const int *, const double *, const void *, double2 *, hipStream_t);
+                    const int *, const int *, const double *, const void *, double2 *, bool,
+                    hipStream_t);
 void launch_export_local(bool, const DevSub *, int, int, const void *, double2 *, hipStream_t);
 void launch_spmv(const DevProb *, int, long long, const int *, const double2 *, long long,
                  const double2 *, const double2 *, double2 *, hipStream_t);
@@ -512,7 +513,8 @@ int ensure_krylov(ras_pml_handle *H, int m) {
 
 int check_handle(ras_pml_handle *H) { return H ? RAS_OK : RAS_EINVAL; }
 
-int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st) {
+int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st,
+             bool acc = false) {
     {
         Timer t(H, C_SOLVE, st);
         launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
@@ -523,7 +525,7 @@ int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active,
     {
         Timer t(H, C_SUM, st);
         launch_pou_sum(H->fp64, H->d_probs, H->nprob, H->max_ndof, H->d_subs, active, H->d_pcnt,
-                       H->d_pchunk, H->d_pw, H->d_xout, z, st);
+                       H->d_pchunk, H->d_pw, H->d_xout, z, acc, st);
     }
     HCHK(H, hipGetLastError());
     return RAS_OK;
@@ -726,6 +728,76 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
     return RAS_OK;
 }
 
+// Algorithm 1 as an iteration: x <- x + B^{-1} (b - A x) for every problem
+// not yet converged.  The correction is summed straight into x (the PoU sum
+// in accumulate mode), so a step is one batched solve, one sum, one
+// residual and one reduction.  The host reads the norms after every step.
+int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int maxit,
+                    int *iters, double *relres, double *hist, hipStream_t st) {
+    const int P = H->nprob;
+    RCHK(ensure_krylov(H, 1));
+    H->res_iters.assign(P, 0);
+    H->res_relres.assign(P, 0.0);
+    H->res_conv.assign(P, 0);
+    std::vector<double> bnorm(P);
+    std::vector<int> need(P, 0);
+    RCHK(reduce_sync(H, b, nullptr, 0, st));
+    for (int p = 0; p < P; ++p) {
+        bnorm[p] = std::sqrt(H->h_red[p].x);
+        if (!std::isfinite(bnorm[p])) {
+            H->last_error = "right-hand side is not finite";
+            return RAS_ENONFINITE;
+        }
+        if (bnorm[p] == 0.0) {
+            const DevProb &D = H->hprobs[p];
+            HCHK(H, hipMemsetAsync(x + D.dof_off, 0, sizeof(double2) * D.ndof, st));
+        }
+    }
+    // residual r = b - A x of the problems in `act` (nullptr: all), its norms
+    // into relres and the stopping test into need
+    auto residual = [&](const int *act) -> int {
+        launch_spmv(H->d_probs, P, H->max_ndof, act, H->d_coef, H->ntot, x, b, H->d_r, st);
+        HCHK(H, hipGetLastError());
+        RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
+        for (int p = 0; p < P; ++p) {
+            if (act != nullptr && !need[p]) continue;
+            const double beta = std::sqrt(H->h_red[p].x);
+            if (!std::isfinite(beta)) {
+                H->last_error = "iterate is not finite";
+                return RAS_ENONFINITE;
+            }
+            H->res_relres[p] = bnorm[p] > 0.0 ? beta / bnorm[p] : 0.0;
+            need[p] = (bnorm[p] > 0.0 && beta > rtol * bnorm[p]) ? 1 : 0;
+            H->res_conv[p] = need[p] ? 0 : 1;
+        }
+        return RAS_OK;
+    };
+    RCHK(residual(nullptr));
+    int it = 0;
+    if (hist) hist[0] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    int nneed = 0;
+    for (int p = 0; p < P; ++p) nneed += need[p];
+    while (nneed > 0 && it < maxit) {
+        HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+        RCHK(do_apply(H, H->d_r, x, H->d_active, st, true));
+        for (int p = 0; p < P; ++p) H->res_iters[p] += need[p];
+        ++it;
+        // the residual of the stepped problems only; r of the others is kept
+        RCHK(residual(H->d_active));
+        if (hist) hist[it] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+        nneed = 0;
+        for (int p = 0; p < P; ++p) nneed += need[p];
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    for (int p = 0; p < P; ++p)
+        if (!H->res_conv[p]) {
+            H->last_error = "maximum number of iterations reached";
+            return RAS_ENOTCONV;
+        }
+    return RAS_OK;
+}
+
 int setup_common(int nprob, const double *k, const double *h, const int *grid, const int *subs,
                  const int *overlap, const int *pml, const ras_pml_opts *opts, void *stream,
                  ras_pml_t *out) {
@@ -876,6 +948,14 @@ void ras_pml_default_opts(ras_pml_opts *o) {
 
 const char *ras_pml_plan_error(void) { return g_plan_error.c_str(); }
 
+int ras_pml_width_rule(double k, double h, double C, double k0, int *cells) {
+    if (cells == nullptr) {
+        g_plan_error = "cells is NULL";
+        return RAS_EINVAL;
+    }
+    return width_rule_cells(k, h, C, k0, *cells, g_plan_error);
+}
+
 int ras_pml_plan(double k, double h, const int grid[2], const int subdomains[2], int overlap,
                  int pml_width, const ras_pml_opts *opts, int *nsub, int *desc, int desc_cap) {
     try {
@@ -1024,6 +1104,22 @@ int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, i
     try {
         return gmres_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
                           restart, maxit, iters, relres, hist, as_stream(stream));
+    } catch (const std::exception &e) {
+        H->last_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int maxit, int *iters,
+                       double *relres, double *hist, void *stream) {
+    if (!H) return RAS_EINVAL;
+    if (!b || !x || b == x || !(rtol > 0.0) || maxit < 0) {
+        H->last_error = "invalid richardson arguments";
+        return RAS_EINVAL;
+    }
+    try {
+        return richardson_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
+                               maxit, iters, relres, hist, as_stream(stream));
     } catch (const std::exception &e) {
         H->last_error = e.what();
         return RAS_ENOMEM;

@@ -98,6 +98,7 @@ struct PlanProblem {
 
 // Validate one problem and compute its subdomains and PoU tables.
 // Returns RAS_OK or an error status with a message in `err`.
+int width_rule_cells(double k, double h, double C, double k0, int &cells, std::string &err);
 int plan_problem(double k, double h, const int grid[2], const int subdomains[2],
                  int overlap, int pml_width, const ras_pml_opts &opts,
                  PlanProblem &out, std::string &err);

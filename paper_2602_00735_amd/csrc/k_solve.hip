@@ -232,12 +232,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         solve_subdomain<T, false, PD>(probs, S, v, F, ybuf, xout, hist, inc);
 }
 
-// z = sum over subdomains covering the node of chi_x * chi_y * x_local.
+// z = sum over subdomains covering the node of chi_x * chi_y * x_local
+// (acc != 0: z += that sum, the fixed-point update of Algorithm 1).
 template <typename T>
 __global__ void k_pou_sum(const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
                           const int *__restrict__ active, const int *__restrict__ pcnt,
                           const int *__restrict__ pchunk, const double *__restrict__ pw,
-                          const cplx<T> *__restrict__ xout, double2 *__restrict__ z) {
+                          const cplx<T> *__restrict__ xout, double2 *__restrict__ z, int acc) {
     const DevProb P = probs[blockIdx.y];
     if (active != nullptr && active[blockIdx.y] == 0) return;
     const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -259,6 +260,11 @@ __global__ void k_pou_sum(const DevProb *__restrict__ probs, const DevSub *__res
             zr = fma(w, static_cast<double>(x.re), zr);
             zi = fma(w, static_cast<double>(x.im), zi);
         }
+    }
+    if (acc) {
+        const double2 z0 = z[P.dof_off + idx];
+        zr += z0.x;
+        zi += z0.y;
     }
     z[P.dof_off + idx] = make_double2(zr, zi);
 }
@@ -312,14 +318,14 @@ void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, con
 
 void launch_pou_sum(bool fp64, const DevProb *probs, int nprob, long long max_ndof,
                     const DevSub *subs, const int *active, const int *pcnt, const int *pchunk,
-                    const double *pw, const void *xout, double2 *z, hipStream_t st) {
+                    const double *pw, const void *xout, double2 *z, bool acc, hipStream_t st) {
     dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
     if (fp64)
         hipLaunchKernelGGL(k_pou_sum<double>, grid, dim3(256), 0, st, probs, subs, active, pcnt,
-                           pchunk, pw, static_cast<const cplx<double> *>(xout), z);
+                           pchunk, pw, static_cast<const cplx<double> *>(xout), z, acc ? 1 : 0);
     else
         hipLaunchKernelGGL(k_pou_sum<float>, grid, dim3(256), 0, st, probs, subs, active, pcnt,
-                           pchunk, pw, static_cast<const cplx<float> *>(xout), z);
+                           pchunk, pw, static_cast<const cplx<float> *>(xout), z, acc ? 1 : 0);
 }
 
 void launch_export_local(bool fp64, const DevSub *subs, int nsub, int max_n, const void *xout,

@@ -255,4 +255,26 @@ void desc_ints(const DevSub &s, const PlanProblem &pb, int *o) {
     o[19] = s.prob;
 }
 
+// Section 3 (iii): a layer of C l(k) wavelengths, with the slowly growing
+// factor l(k) = k/(k - k0) log2(k/k0), which tends to 1/ln 2 as k -> k0 (the
+// removable singularity is evaluated through log1p of (k - k0)/k0 near it),
+// converted to whole mesh cells by rounding down.  A relative slack of 1e-9
+// keeps a width that is an exact multiple of h from dropping a cell.
+int width_rule_cells(double k, double h, double C, double k0, int &cells, std::string &err) {
+    if (bad(k) || k <= 0.0 || bad(h) || h <= 0.0 || bad(k0) || k0 <= 0.0 || bad(C) || C < 0.0) {
+        err = "width rule needs finite k, h, k0 > 0 and C >= 0";
+        return RAS_EINVAL;
+    }
+    const double t = (k - k0) / k0;              // k/k0 = 1 + t
+    double ell;
+    if (std::fabs(t) < 1e-6)                     // series of log1p(t)/t about t = 0
+        ell = (1.0 + t) * (1.0 - t / 2.0 + t * t / 3.0) / std::log(2.0);
+    else
+        ell = (1.0 + t) / t * std::log1p(t) / std::log(2.0);
+    const double cells_real = C * ell * (2.0 * M_PI / k) / h;
+    if (!(cells_real < 1e9)) { err = "width rule: width exceeds 1e9 cells"; return RAS_EINVAL; }
+    cells = static_cast<int>(std::floor(cells_real * (1.0 + 1e-9)));
+    return RAS_OK;
+}
+
 }  // namespace raspml

@@ -136,3 +136,38 @@ def test_config_sizes_from_the_plan(L):
     sides = sorted(set(d[15] - d[14] for d in desc))
     assert sides[-1] in (92, 93) and 92 in sides
     assert max(d[2] for d in desc) <= 128
+
+
+def _width_rows():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "width_rule_tables.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append(tuple(int(t) for t in line.split()))
+    return rows
+
+
+def test_width_rule_reproduces_the_paper_tables(L):
+    """Section 3 (iii) widths through the C ABI against the printed Table 3/4
+    columns (PML on the listed grid with C = 1/2, overlap at 12 points per
+    wavelength with C = 1/6)."""
+    for k, n, pml, ovlp in _width_rows():
+        assert rp.ras_pml_width_rule(k, 1.0 / n, 0.5) == pml
+        assert rp.ras_pml_width_rule(k, 2 * np.pi / k / 12, 1.0 / 6.0) == ovlp
+
+
+def test_width_rule_matches_the_oracle_and_its_limit(L):
+    rng = np.random.default_rng(5)
+    for _ in range(400):
+        k = float(rng.uniform(20.0, 20000.0))
+        h = 1.0 / float(rng.integers(64, 40000))
+        C = float(rng.choice([1 / 6, 1 / 4, 3 / 8, 1 / 2, 1.0]))
+        assert rp.ras_pml_width_rule(k, h, C) == geometry.paper_width_cells(k, h, C)
+    # k -> k0: l(k) -> 1/ln 2 from both sides, no 0/0
+    for k in (150.0, 150.0 * (1 + 1e-9), 150.0 * (1 - 1e-9), 150.0 * (1 + 1e-4)):
+        h = 1.0 / 3000
+        want = geometry.paper_width_cells(150.0, h, 1.0)
+        assert rp.ras_pml_width_rule(k, h, 1.0) == want
+    for bad in ((0.0, 0.01, 0.5), (100.0, -1.0, 0.5), (100.0, 0.01, -0.5),
+                (float("nan"), 0.01, 0.5), (100.0, 0.01, float("inf"))):
+        with pytest.raises(ValueError):
+            rp.ras_pml_width_rule(*bad)

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2602_00735_amd as rp
 from paper_2602_00735_amd import inputs
-from oracle import fem, geometry, gmres, ras
+from oracle import fem, geometry, gmres, ras, richardson
 from oracle.geometry import BC_DRCH, BC_IMP, POU_BOOLEAN, POU_LINEAR, Problem
 
 
@@ -278,6 +278,137 @@ def test_gmres_edge_cases():
     bad[5] = complex(float("nan"), 0.0)
     rc, *_ = rp.gmres_solve(H, bad, torch.zeros_like(zero), rtol=1e-6, check=False)
     assert rc == rp.RAS_ENONFINITE
+
+
+# ------------------------------------------------------------------ f2 Richardson
+def oracle_richardson(R, b, rtol=1e-6, maxit=100):
+    return richardson.ras_richardson(lambda y: R.A @ y, R.apply, b, rtol=rtol, maxit=maxit)
+
+
+# converging (wide layers, Boolean PoU), stagnating (3-cell layers) and
+# diverging (Dirichlet transmission) cases of the fixed-point iteration
+@pytest.mark.parametrize("name,maxit", [("k20", 100), ("k40_two_slot", 100), ("boolean", 100),
+                                        ("ragged", 40), ("clip_drch", 25)])
+def test_richardson_fp64_matches_oracle(name, maxit):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    ref = oracle_richardson(R, b, maxit=maxit)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(b), x, rtol=1e-6, maxit=maxit)
+    assert rc == (rp.RAS_OK if ref.converged else rp.RAS_ENOTCONV)
+    assert it == ref.iters
+    # every iterate's true relative residual, step by step
+    assert np.allclose(hist, ref.history, rtol=1e-8, atol=1e-15)
+    assert abs(rr - ref.relres) <= 1e-8 * ref.relres
+    assert relerr(host(x), ref.x) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["k20", "k40_two_slot", "boolean"])
+def test_richardson_mixed_matches_fp64_oracle(name):
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    ref = oracle_richardson(R, b)
+    tight = oracle_richardson(R, b, rtol=1e-12, maxit=300)
+    assert tight.converged
+    H = setup_gpu(pb, rp.RAS_MIXED)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(b), x, rtol=1e-6, maxit=100)
+    assert rc == rp.RAS_OK and abs(it - ref.iters) <= 1
+    xs = host(x)
+    # the residual is formed in complex128: the stopping test is exact
+    assert np.linalg.norm(b - R.A @ xs) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)
+    assert relerr(xs, tight.x) <= 1e-5
+    k = min(len(hist), len(ref.history))
+    assert np.allclose(hist[:k], ref.history[:k], rtol=1e-2, atol=1e-6)
+
+
+def test_richardson_edge_cases():
+    pb = PROBLEMS["k20"]
+    R = oracle_for("k20")
+    H = setup_gpu(pb, rp.RAS_FP64)
+    zero = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    x = torch.ones_like(zero)
+    rc, it, rr, hist = rp.ras_pml_richardson(H, zero, x, rtol=1e-6)
+    assert rc == rp.RAS_OK and it == 0 and torch.count_nonzero(x) == 0 and list(hist) == [0.0]
+    bh = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    b = dev(bh)
+    x = torch.zeros_like(zero)
+    rc, it, rr, hist = rp.ras_pml_richardson(H, b, x, rtol=1e-6, maxit=0)
+    assert rc == rp.RAS_ENOTCONV and it == 0 and abs(hist[0] - 1.0) <= 1e-14
+    rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-6, maxit=2)
+    assert rc == rp.RAS_ENOTCONV and it == 2
+    # resume: two more steps from the iterate equal steps 3..4 of one run
+    ref = oracle_richardson(R, bh, rtol=1e-12, maxit=4)
+    rc, it, rr, hist = rp.ras_pml_richardson(H, b, x, rtol=1e-12, maxit=2)
+    assert it == 2 and np.allclose(hist, ref.history[2:5], rtol=1e-8)
+    assert relerr(host(x), ref.x) <= 1e-9
+    bad = b.clone()
+    bad[7] = complex(float("nan"), 0.0)
+    rc, *_ = rp.ras_pml_richardson(H, bad, torch.zeros_like(zero), rtol=1e-6, check=False)
+    assert rc == rp.RAS_ENONFINITE
+    one = Problem(k=8.0, n_int=24, G=3, Px=1, Py=1, delta=3, kappa=3, sigma=80.0)
+    R1 = ras.RasPml(one)
+    b1 = fem.rhs(R1.M1, inputs.centre_gaussian(one.n_int, one.G, 0.1))
+    H1 = setup_gpu(one, rp.RAS_FP64)
+    x1 = torch.zeros(one.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, _ = rp.ras_pml_richardson(H1, dev(b1), x1, rtol=1e-10, maxit=5)
+    assert rc == rp.RAS_OK and it == 1 and rr <= 1e-12
+
+
+def test_richardson_batch_matches_separate_oracles():
+    """Three problems on one handle, one of them stagnating: each stops on its
+    own test, converged problems are left untouched."""
+    base = [PROBLEMS["k20"], PROBLEMS["ragged"], PROBLEMS["k40_two_slot"]]
+    pbs = [Problem(k=p.k, n_int=p.n_int, G=p.kappa, Px=p.Px, Py=p.Py, delta=p.delta,
+                   kappa=p.kappa, sigma=10 * p.k) for p in base]
+    o = rp.default_opts(precision=rp.RAS_FP64)
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs], o)
+    Rs = [ras.RasPml(p) for p in pbs]
+    bs = [fem.rhs(R.M1, inputs.centre_gaussian(p.n_int, p.G, 0.1)) for p, R in zip(pbs, Rs)]
+    refs = [oracle_richardson(R, b, maxit=30) for R, b in zip(Rs, bs)]
+    x = torch.zeros(H.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(np.concatenate(bs)), x, rtol=1e-6, maxit=30)
+    assert rc == (rp.RAS_OK if all(r.converged for r in refs) else rp.RAS_ENOTCONV)
+    assert it == max(r.iters for r in refs)
+    worst = [max(r.history[min(t, r.iters)] for r in refs) for t in range(it + 1)]
+    assert np.allclose(hist, worst, rtol=1e-8)
+    xs = host(x)
+    for p, ref in enumerate(refs):
+        off, m = H.problem_offset(p)
+        itp, rrp, conv = rp.ras_pml_batch_result(H, p)
+        assert itp == ref.iters and conv == ref.converged
+        assert abs(rrp - ref.relres) <= 1e-8 * ref.relres
+        assert relerr(xs[off:off + m], ref.x) <= 1e-9
+
+
+def test_k160_richardson_fp64_against_full_oracle():
+    """k = 160, h = 1/320, 16 x 16 subdomains: the whole fixed-point run,
+    every iterate's residual and the final iterate."""
+    pb = geometry.config_problem("k160")
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.05))
+    ref = oracle_richardson(R, b, maxit=200)
+    assert ref.converged
+    for prec in (rp.RAS_FP64, rp.RAS_MIXED):
+        H = setup_gpu(pb, prec)
+        x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+        rc, it, rr, hist = rp.ras_pml_richardson(H, dev(b), x, rtol=1e-6, maxit=200)
+        assert rc == rp.RAS_OK
+        xs = host(x)
+        if prec == rp.RAS_FP64:
+            assert it == ref.iters
+            assert np.allclose(hist, ref.history, rtol=1e-8, atol=1e-15)
+            assert relerr(xs, ref.x) <= 1e-9
+        else:
+            assert abs(it - ref.iters) <= 1
+            assert np.linalg.norm(b - R.A @ xs) <= 1e-6 * np.linalg.norm(b) * (1 + 1e-9)
+            assert relerr(xs, ref.x) <= 1e-5
+        H.close()
 
 
 # ------------------------------------------------------------------ batch
