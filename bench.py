@@ -75,6 +75,11 @@ def main():
                          "timed region, and set every timed handle up from its cache)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batch (seeded multi-source problems, one handle)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the k-sweep at kh = 1/2 with the Section 3 (iii) widths: "
+                         "subdomain boundary conditions (Tables 1/2 set-up) and the growth of "
+                         "iterations and time with k (Tables 3/4 set-up); one JSON line per run")
+    ap.add_argument("--sweep-max-k", type=float, default=1280.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC traffic calibration)")
     args = ap.parse_args()
@@ -99,6 +104,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "device copy", "bytes_read": 8 * n, "bytes_written": 8 * n,
                           "dispatches": 3}))
+        return
+
+    if args.sweep:
+        sweep(args.sweep_max_k)
         return
 
     k, n_int, P = WORKLOADS[args.workload]
@@ -219,6 +228,28 @@ def main():
         out["mixed_vs_fp64_solution_rel_l2"] = d
         out["speedup_mixed_over_fp64_time_to_solution"] = round(r64["total_s"] / mixed["total_s"], 3)
 
+    # ---------------------------------------------------------------- Richardson
+    # the preconditioner as a fixed-point iteration (Algorithm 1), mixed
+    # precision, same problem and stopping test; solve time only
+    o = rp.default_opts(global_pml=G, precision=rp.RAS_MIXED)
+    if cache is not None:
+        o.tune_cache = os.fsencode(cache)
+    H = rp.ras_pml_setup(k, h, grid, subs, L, L, o)
+    b = torch.empty_like(f)
+    rp.ras_pml_rhs(H, f, b)
+    x = torch.zeros_like(f)
+    rp.ras_pml_richardson(H, b, x, rtol=1e-6, maxit=2)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-6, maxit=500)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["richardson"] = {"iters": it, "relres": rr, "converged": rc == rp.RAS_OK,
+                         "solve_s": round(ts, 5), "ms_per_iteration": round(1000 * ts / max(1, it), 4),
+                         "fgmres_iters_same_problem": mixed["iters"]}
+    H.close()
+
     # ---------------------------------------------------------------- applies/s
     applies = {}
     for name, prec in (("mixed", rp.RAS_MIXED), ("fp64", rp.RAS_FP64)):
@@ -266,6 +297,68 @@ def main():
     if cache is not None and os.path.exists(cache):
         os.remove(cache)
     print(json.dumps(out), flush=True)
+
+
+def sweep(max_k):
+    """k = 80 ... max_k at kh = 1/2 (about 12.6 points per wavelength), k/20
+    subdomains per side (40-cell cores, N proportional to k^2), the Section 4
+    source (smoothed point source at the centre), a global PML of three
+    wavelengths, rtol 1e-10, at most 500 iterations, mixed precision.
+      - "bc": overlap and PML from the width rule with C_delta = 1/6,
+        C_kappa = 3/8 (the Tables 1/2 constants); RAS-PML-Imp, RAS-PML-Drch
+        and RAS-Imp (no subdomain PML); Richardson and GMRES(100).
+      - "growth": C_delta = 1/6, C_kappa = 1/2 (Tables 3/4); RAS-PML-Imp
+        Richardson; setup and solve seconds."""
+    import torch
+    import paper_2602_00735_amd as rp
+    from paper_2602_00735_amd import inputs
+    torch.cuda.set_device(0)
+    ks = [k for k in (80.0, 160.0, 320.0, 640.0, 1280.0) if k <= max_k]
+
+    def run(k, bc, pml, c_kappa, solver):
+        n = int(round(2 * k))
+        h = 1.0 / n
+        P = int(round(k / 20))
+        G = int(math.floor(3 * 2 * math.pi / k / h + 1e-9))
+        o = rp.default_opts(global_pml=G, bc=bc, precision=rp.RAS_MIXED, width_c_kappa=c_kappa)
+        t0 = time.perf_counter()
+        H = rp.ras_pml_setup(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, pml, o)
+        f = torch.from_numpy(inputs.paper(k, n, G)).to("cuda")
+        b = torch.empty_like(f)
+        x = torch.zeros_like(f)
+        rp.ras_pml_rhs(H, f, b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if solver == "richardson":
+            rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-10, maxit=500, check=False)
+        else:
+            rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-10, restart=100, maxit=500,
+                                           check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        d = H.desc()[0]
+        H.close()
+        return {"k": k, "grid": n, "subdomains": P * P, "ovlp": d[20], "pml": d[21],
+                "global_pml": G, "solver": solver, "iters": it,
+                "relres": rr if math.isfinite(rr) else None,
+                "converged": rc == rp.RAS_OK, "status": rc,
+                "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4)}
+
+    variants = (("RAS-PML-Imp", rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE),
+                ("RAS-PML-Drch", rp.RAS_BC_DRCH, rp.RAS_WIDTH_RULE),
+                ("RAS-Imp", rp.RAS_BC_IMP, 0))
+    run(80.0, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")        # warm-up
+    for k in ks:
+        for name, bc, pml in variants:
+            for solver in ("richardson", "gmres"):
+                r = run(k, bc, pml, 3.0 / 8.0, solver)
+                r.update(sweep="bc", variant=name)
+                print(json.dumps(r), flush=True)
+    for k in ks:
+        r = run(k, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")
+        r.update(sweep="growth", variant="RAS-PML-Imp",
+                 total_per_k=round((r["setup_s"] + r["solve_s"]) / k, 6))
+        print(json.dumps(r), flush=True)
 
 
 def batch32(dev, no_fp64):

@@ -74,13 +74,22 @@ typedef struct {
                           ras_pml_autotune, or NULL: setup then uses the
                           cached kernel variants for the configurations the
                           file knows (a missing file is an empty cache)       */
+    double width_c_delta; /* Section 3 (iii) width rule (eq. igg_width) used  */
+    double width_c_kappa; /* for an overlap / pml_width of RAS_WIDTH_RULE:     */
+    double width_k0;      /* C_delta, C_kappa and k0; defaults 1/6, 1/2, 150
+                             (the constants of Tables 3 and 4)               */
 } ras_pml_opts;
+
+/* Pass as overlap and/or pml_width to take the width from the Section 3
+ * (iii) rule with the constants in ras_pml_opts (see ras_pml_width_rule). */
+#define RAS_WIDTH_RULE (-1)
 
 /* Number of int32 fields in one subdomain descriptor (ras_pml_plan). */
 #define RAS_DESC_INTS 24
 
 /* Fill *o with the defaults (sigma = 10 k, global PML = pml_width,
- * impedance, linear PoU, mixed precision, no flags, no tuning cache). */
+ * impedance, linear PoU, mixed precision, no flags, no tuning cache, width
+ * rule constants C_delta = 1/6, C_kappa = 1/2, k0 = 150). */
 void ras_pml_default_opts(ras_pml_opts *o);
 
 /* Host-only planning: validates the parameters exactly as ras_pml_setup
@@ -89,7 +98,8 @@ void ras_pml_default_opts(ras_pml_opts *o);
  *   h          mesh width; grid[0] * h == 1 and grid[1] == grid[0] required
  *   grid       cells of the interior box (0,1)^2 per side
  *   subdomains number of subdomains per side (Section 2 Cartesian covering)
- *   overlap    delta in cells (>= 0), pml_width kappa in cells (>= 0)
+ *   overlap    delta in cells (>= 0), pml_width kappa in cells (>= 0);
+ *              either may be RAS_WIDTH_RULE
  *   nsub       out: number of subdomains
  *   desc       nullable; if given, nsub * RAS_DESC_INTS int32 (host memory):
  *              [0] n_local  [1] n_fast  [2] W = n_fast + 2 (factor column
@@ -99,7 +109,9 @@ void ras_pml_default_opts(ras_pml_opts *o);
  *              [14..17] Omega_j box x lo, x hi, y lo, y hi (node indices)
  *              [18] flags: bit0/1 PML added below/above in x, bit2/3 in y,
  *              bit4..7 impedance on the x-lo, x-hi, y-lo, y-hi side
- *              [19] problem index  [20..23] reserved (0)
+ *              [19] problem index  [20] overlap delta  [21] PML width kappa
+ *              [22] global PML width (cells; as resolved from the
+ *              arguments, RAS_WIDTH_RULE and global_pml)  [23] reserved (0)
  *   desc_cap   capacity of desc in subdomains (ignored when desc is NULL)
  * Returns RAS_EINVAL (message via ras_pml_strerror) or RAS_ENOTSUP.        */
 int ras_pml_plan(double k, double h, const int grid[2], const int subdomains[2],
@@ -192,7 +204,9 @@ int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, i
  * of every iterate.  Batch handles: as gmres_solve (each problem stops on
  * its own; hist and relres give the worst problem; per problem through
  * ras_pml_batch_result).  Synchronises `stream` after every step.
- * Errors: RAS_EINVAL, RAS_ENONFINITE, RAS_ENOTCONV, RAS_ENOMEM, RAS_EHIP.  */
+ * Errors: RAS_EINVAL, RAS_ENONFINITE (also when a diverging iteration
+ * overflows: *iters then holds the steps taken, *relres = HUGE_VAL),
+ * RAS_ENOTCONV, RAS_ENOMEM, RAS_EHIP.                                       */
 int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int maxit, int *iters,
                        double *relres, double *hist, void *stream);
 

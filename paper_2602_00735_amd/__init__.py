@@ -22,6 +22,7 @@ RAS_MIXED, RAS_FP64 = 0, 1
 RAS_FLAG_TIMING = 1
 RAS_FLAG_UNFUSED_ARNOLDI = 2
 RAS_DESC_INTS = 24
+RAS_WIDTH_RULE = -1
 
 
 class RasPmlError(RuntimeError):
@@ -37,7 +38,8 @@ _STATUS = {0: "RAS_OK", 1: "RAS_EINVAL", 2: "RAS_ENOMEM", 3: "RAS_EHIP", 4: "RAS
 class Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("global_pml", ctypes.c_int), ("bc", ctypes.c_int),
                 ("pou", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("width_c_delta", ctypes.c_double),
+                ("width_c_kappa", ctypes.c_double), ("width_k0", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

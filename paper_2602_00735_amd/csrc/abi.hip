@@ -783,7 +783,12 @@ int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol
         for (int p = 0; p < P; ++p) H->res_iters[p] += need[p];
         ++it;
         // the residual of the stepped problems only; r of the others is kept
-        RCHK(residual(H->d_active));
+        const int rc = residual(H->d_active);
+        if (rc != RAS_OK) {       // a diverging iteration overflows: report how far it got
+            if (iters) *iters = it;
+            if (relres) *relres = HUGE_VAL;
+            return rc;
+        }
         if (hist) hist[it] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
         nneed = 0;
         for (int p = 0; p < P; ++p) nneed += need[p];
@@ -944,6 +949,9 @@ void ras_pml_default_opts(ras_pml_opts *o) {
     o->precision = RAS_MIXED;
     o->flags = 0;
     o->tune_cache = nullptr;
+    o->width_c_delta = 1.0 / 6.0;
+    o->width_c_kappa = 0.5;
+    o->width_k0 = 150.0;
 }
 
 const char *ras_pml_plan_error(void) { return g_plan_error.c_str(); }

@@ -126,7 +126,19 @@ int plan_problem(double k, double h, const int grid[2], const int subdomains[2],
         err = buf;
         return RAS_EINVAL;
     }
-    if (overlap < 0 || pml_width < 0) { err = "overlap and pml_width must be >= 0"; return RAS_EINVAL; }
+    // Section 3 (iii): a width argument of RAS_WIDTH_RULE takes the rule's value
+    if (overlap == RAS_WIDTH_RULE) {
+        const int rc = width_rule_cells(k, h, opts.width_c_delta, opts.width_k0, overlap, err);
+        if (rc != RAS_OK) return rc;
+    }
+    if (pml_width == RAS_WIDTH_RULE) {
+        const int rc = width_rule_cells(k, h, opts.width_c_kappa, opts.width_k0, pml_width, err);
+        if (rc != RAS_OK) return rc;
+    }
+    if (overlap < 0 || pml_width < 0) {
+        err = "overlap and pml_width must be >= 0 (or RAS_WIDTH_RULE)";
+        return RAS_EINVAL;
+    }
     if (opts.bc != RAS_BC_IMP && opts.bc != RAS_BC_DRCH) { err = "unknown bc"; return RAS_EINVAL; }
     if (opts.pou != RAS_POU_LINEAR && opts.pou != RAS_POU_BOOLEAN) { err = "unknown pou"; return RAS_EINVAL; }
     if (opts.precision != RAS_MIXED && opts.precision != RAS_FP64) { err = "unknown precision"; return RAS_EINVAL; }
@@ -240,7 +252,6 @@ void desc_ints(const DevSub &s, const PlanProblem &pb, int *o) {
     o[5] = s.nx;
     o[6] = s.jy0;
     o[7] = s.ny;
-    (void)pb;
     o[8] = s.cp;
     o[9] = s.cq;
     o[10] = s.ix_int0;
@@ -253,6 +264,9 @@ void desc_ints(const DevSub &s, const PlanProblem &pb, int *o) {
     o[17] = s.by1;
     o[18] = s.flags;
     o[19] = s.prob;
+    o[20] = pb.delta;
+    o[21] = pb.kappa;
+    o[22] = pb.G;
 }
 
 // Section 3 (iii): a layer of C l(k) wavelengths, with the slowly growing

@@ -60,7 +60,8 @@ def test_strerror(L):
     (dict(h=1.0 / 41), rp.RAS_EINVAL),            # grid * h != 1
     (dict(grid=(40, 39)), rp.RAS_EINVAL),
     (dict(subdomains=(0, 2)), rp.RAS_EINVAL),
-    (dict(overlap=-1), rp.RAS_EINVAL),
+    (dict(overlap=-2), rp.RAS_EINVAL),            # -1 is RAS_WIDTH_RULE
+    (dict(pml_width=-3), rp.RAS_EINVAL),
     (dict(subdomains=(1, 1), grid=(400, 400), h=1 / 400), rp.RAS_ENOTSUP),   # band too wide
 ])
 def test_plan_rejects_bad_parameters(L, args, status):
@@ -171,3 +172,28 @@ def test_width_rule_matches_the_oracle_and_its_limit(L):
                 (float("nan"), 0.01, 0.5), (100.0, 0.01, float("inf"))):
         with pytest.raises(ValueError):
             rp.ras_pml_width_rule(*bad)
+
+
+def test_width_rule_as_a_setup_option(L):
+    """RAS_WIDTH_RULE for overlap / pml_width plans exactly the subdomains of
+    the explicit widths the rule gives (descriptor fields 20..22 carry the
+    resolved delta, kappa and global PML)."""
+    for k, n, P in ((80.0, 160, 4), (300.0, 600, 8), (640.0, 1280, 32)):
+        h = 1.0 / n
+        d = rp.ras_pml_width_rule(k, h, 1.0 / 6.0)
+        kap = rp.ras_pml_width_rule(k, h, 0.5)
+        o = rp.default_opts()
+        a = rp.ras_pml_plan(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, rp.RAS_WIDTH_RULE, o)
+        b = rp.ras_pml_plan(k, h, (n, n), (P, P), d, kap, o)
+        assert a == b
+        assert all(row[20] == d and row[21] == kap and row[22] == kap for row in a)
+        # other constants, explicit global PML
+        o2 = rp.default_opts(width_c_kappa=3.0 / 8.0, width_k0=100.0, global_pml=7)
+        c = rp.ras_pml_plan(k, h, (n, n), (P, P), 3, rp.RAS_WIDTH_RULE, o2)
+        kap2 = rp.ras_pml_width_rule(k, h, 3.0 / 8.0, 100.0)
+        assert all(row[20] == 3 and row[21] == kap2 and row[22] == 7 for row in c)
+    o = rp.default_opts(width_c_delta=-1.0)
+    with pytest.raises(Exception):
+        rp.ras_pml_plan(80.0, 1 / 160, (160, 160), (4, 4), rp.RAS_WIDTH_RULE, 3, o)
+    with pytest.raises(Exception):
+        rp.ras_pml_plan(80.0, 1 / 160, (160, 160), (4, 4), -2, 3, rp.default_opts())

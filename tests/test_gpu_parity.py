@@ -49,6 +49,8 @@ PROBLEMS = {
     "boolean": Problem(k=12.0, n_int=40, G=4, Px=3, Py=3, delta=3, kappa=4, sigma=120.0,
                        pou=POU_BOOLEAN),
     "max_band": Problem(k=30.0, n_int=115, G=6, Px=1, Py=1, delta=0, kappa=0, sigma=300.0),
+    # RAS-Imp (Section 4.1): no subdomain PML, impedance on the subdomain boundary
+    "no_pml": Problem(k=12.0, n_int=40, G=4, Px=3, Py=3, delta=3, kappa=0, sigma=120.0),
 }
 
 _oracles = {}
@@ -208,6 +210,7 @@ def test_spmv_and_rhs(name):
 
 # ------------------------------------------------------------------ a7
 @pytest.mark.parametrize("name,restart", [("k20", 50), ("ragged", 50), ("k40_two_slot", 100),
+                                          ("no_pml", 50),
                                           ("ragged", 4), ("clip_drch", 50), ("boolean", 50)])
 def test_gmres_fp64_matches_oracle(name, restart):
     pb = PROBLEMS[name]
@@ -288,7 +291,7 @@ def oracle_richardson(R, b, rtol=1e-6, maxit=100):
 # converging (wide layers, Boolean PoU), stagnating (3-cell layers) and
 # diverging (Dirichlet transmission) cases of the fixed-point iteration
 @pytest.mark.parametrize("name,maxit", [("k20", 100), ("k40_two_slot", 100), ("boolean", 100),
-                                        ("ragged", 40), ("clip_drch", 25)])
+                                        ("ragged", 40), ("clip_drch", 25), ("no_pml", 100)])
 def test_richardson_fp64_matches_oracle(name, maxit):
     pb = PROBLEMS[name]
     R = oracle_for(name)
@@ -356,6 +359,62 @@ def test_richardson_edge_cases():
     x1 = torch.zeros(one.ndof, dtype=torch.complex128, device="cuda")
     rc, it, rr, _ = rp.ras_pml_richardson(H1, dev(b1), x1, rtol=1e-10, maxit=5)
     assert rc == rp.RAS_OK and it == 1 and rr <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [(rp.RAS_FP64, 1e-12), (rp.RAS_MIXED, 1e-5)])
+@pytest.mark.parametrize("name", ["k40_two_slot", "ragged", "no_pml"])
+def test_richardson_step_annihilates_the_residual_away_from_overlaps(name, precision, tol):
+    """Section 3 (i) on the GPU: one step from a random iterate leaves a
+    residual that vanishes (to the local solves' precision) wherever the
+    stencil lies in one subdomain's PoU-one region, and not elsewhere."""
+    from residual_mask import annihilation_set
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    mask = annihilation_set(R, check_rows=False)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    u = inputs.random_vector(pb.ndof, 3)
+    H = setup_gpu(pb, precision)
+    x = dev(u)
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(b), x, rtol=1e-14, maxit=1)
+    assert rc == rp.RAS_ENOTCONV and it == 1
+    r0 = b - R.A @ u
+    r1 = b - R.A @ host(x)
+    sc = np.abs(r0).max()
+    assert np.abs(r1[mask]).max() <= tol * sc
+    assert np.abs(r1[~mask]).max() >= 1e-4 * sc
+    assert abs(hist[1] - np.linalg.norm(r1) / np.linalg.norm(b)) <= 1e-10 * hist[1]
+
+
+@pytest.mark.parametrize("bc,kappa", [(BC_IMP, None), (BC_DRCH, None), (BC_IMP, 0)])
+def test_width_rule_setup_richardson_and_gmres_match_oracle(bc, kappa):
+    """k = 80, h = 1/160, 4 x 4 subdomains, overlap and PML from the
+    Section 3 (iii) rule (C_delta = 1/6, C_kappa = 1/2, k0 = 150), rtol 1e-10
+    as in Section 4: RAS-PML-Imp, RAS-PML-Drch and RAS-Imp (kappa = 0),
+    Richardson and GMRES, FP64 against the oracle."""
+    k, n, P = 80.0, 160, 4
+    d = geometry.paper_width_cells(k, 1.0 / n, 1.0 / 6.0)
+    kap = geometry.paper_width_cells(k, 1.0 / n, 0.5)
+    G = kap
+    o = rp.default_opts(precision=rp.RAS_FP64, bc=bc, global_pml=G)
+    H = rp.ras_pml_setup(k, 1.0 / n, (n, n), (P, P), rp.RAS_WIDTH_RULE,
+                         rp.RAS_WIDTH_RULE if kappa is None else kappa, o)
+    desc = H.desc()
+    pk = kap if kappa is None else kappa
+    assert all(row[20] == d and row[21] == pk and row[22] == G for row in desc)
+    pb = Problem(k=k, n_int=n, G=G, Px=P, Py=P, delta=d, kappa=pk, sigma=10 * k, bc=bc)
+    R = ras.RasPml(pb)
+    b = fem.rhs(R.M1, inputs.centre_gaussian(n, G, 0.1))
+    ref = oracle_richardson(R, b, rtol=1e-10, maxit=200)
+    x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(b), x, rtol=1e-10, maxit=200)
+    assert rc == rp.RAS_OK and it == ref.iters
+    assert np.allclose(hist, ref.history, rtol=1e-6, atol=1e-15)
+    assert relerr(host(x), ref.x) <= 1e-8
+    gref = gmres.gmres(lambda y: R.A @ y, R.apply, b, rtol=1e-10, restart=100, maxit=300)
+    x = torch.zeros_like(x)
+    rc, git, rr, _ = rp.gmres_solve(H, dev(b), x, rtol=1e-10, restart=100, maxit=300)
+    assert rc == rp.RAS_OK and abs(git - gref.iters) <= 1
+    assert np.linalg.norm(b - R.A @ host(x)) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
 
 
 def test_richardson_batch_matches_separate_oracles():

@@ -491,3 +491,35 @@ def test_richardson_converges_to_the_direct_solution():
     # by about the residual's size only
     x2 = out.x + R.apply(b - R.A @ out.x)
     assert np.linalg.norm(x2 - out.x) <= 1e-6 * np.linalg.norm(out.x)
+
+
+@pytest.mark.parametrize("case", ["wide", "ragged", "drch", "no_pml"])
+def test_one_step_annihilates_the_residual_away_from_overlaps(case):
+    """Section 3 (i): after one step of the iteration from any iterate the
+    residual is non-zero only near the overlaps.  On the unknowns whose
+    stencil lies where one PoU weight is 1 (where, as the test also checks,
+    the local rows equal the global ones) it vanishes to rounding; elsewhere
+    it does not."""
+    from residual_mask import annihilation_set
+    pbs = {
+        "wide": small(k=20.0, n=60, G=6, P=2, L=6),
+        "ragged": Problem(k=12.0, n_int=45, G=3, Px=3, Py=4, delta=3, kappa=3, sigma=120.0),
+        "drch": Problem(k=9.0, n_int=40, G=2, Px=3, Py=3, delta=3, kappa=4, sigma=90.0,
+                        bc=BC_DRCH),
+        "no_pml": Problem(k=12.0, n_int=40, G=4, Px=3, Py=3, delta=3, kappa=0, sigma=120.0),
+    }
+    pb = pbs[case]
+    R = ras.RasPml(pb)
+    mask = annihilation_set(R)
+    assert (mask == annihilation_set(R, check_rows=False)).all()
+    assert mask.mean() > 0.1
+    b = fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1))
+    u = inputs.random_vector(pb.ndof, 3)
+    r = b - R.A @ u
+    r1 = b - R.A @ (u + R.apply(r))
+    sc = np.abs(r).max()
+    assert np.abs(r1[mask]).max() <= 1e-13 * sc
+    assert np.abs(r1[~mask]).max() >= 1e-4 * sc
+    # the plain (unweighted) additive sum has no such property
+    r2 = b - R.A @ (u + R.apply(r, weighted=False))
+    assert np.abs(r2[mask]).max() >= 1e-4 * sc
