@@ -292,6 +292,10 @@ int build(ras_pml_handle *H, hipStream_t st) {
             s.fac_off = static_cast<long long>(fac);
             s.vec_off = vec;
             s.loc_off = loc;
+            if (s.W & 1) {            // the pair-layout solve relies on even W
+                H->last_error = "internal: odd factor column length";
+                return RAS_EINVAL;
+            }
             fac += static_cast<size_t>(s.npad) * (2 * s.W + 1);   // L, rows of L, D^{-1}
             vec += s.npad;
             loc += s.n;
@@ -333,12 +337,15 @@ int build(ras_pml_handle *H, hipStream_t st) {
     }
     if (!H->tune_cache.empty()) apply_cache(H, H->tune_cache.c_str());
 
-    // algorithmic bytes of one band-solve launch: L read by both sweeps,
-    // D^{-1}, the gathered right-hand side (complex128), the forward result
-    // written and read back, the local solution written.
+    // algorithmic bytes of one band-solve launch: the nf + 1 band entries of
+    // every column of L, read by both sweeps, D^{-1}, the gathered
+    // right-hand side (complex128), the forward result written and read
+    // back, the local solution written -- over the n rows of the matrix
+    // (the stored zeros of the padding rows, the diagonal slot and the slot
+    // that makes W even are not counted).
     double sb = 0.0, fb = 0.0;
     for (const DevSub &s : H->hsubs) {
-        sb += (2.0 * s.npad * s.W + s.npad + 3.0 * s.npad) * H->csize + 16.0 * s.n;
+        sb += (2.0 * s.n * (s.nf + 1) + s.n + 3.0 * s.n) * H->csize + 16.0 * s.n;
         fb += static_cast<double>(s.npad) * (2 * s.W + 1) * H->csize;
     }
     H->stats.solve_bytes = sb;

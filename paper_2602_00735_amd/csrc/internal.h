@@ -33,7 +33,8 @@ struct DevSub {
     int n;          // local unknowns
     int npad;       // n rounded up to kPad
     int nf;         // unknowns along the fast axis
-    int W;          // factor column length nf + 2 (= half-bandwidth + 1)
+    int W;          // factor column length: half-bandwidth + 1 = nf + 2, rounded
+                    // up to even (the extra slot holds zeros)
     int xfast;      // 1: x is the fast axis
     int ix0, nx;    // first unknown node index and count along x
     int jy0, ny;    // same along y

@@ -23,7 +23,8 @@
 //   4. the retired slot receives the band row/column c + W, whose only
 //      non-zeros are the 7-point stencil couplings (diagonal, fast -1,
 //      slow -n_fast, diagonal -n_fast-1), staged in LDS one block of 64 rows
-//      ahead.
+//      ahead.  (W may exceed the band by one slot: it is rounded up to even
+//      for the solve; that slot stays zero.)
 // One barrier per column (the column buffer is double buffered).  Rows past
 // the matrix end (padding to a multiple of 64) are identity rows.
 #include "device.h"
@@ -181,15 +182,18 @@ __global__ __launch_bounds__(TY *TX) void k_band_ldlt(const DevSub *__restrict__
         // 4. band row/column c + W enters slot sl
         const cplx<T> *nr = newrow[(c >> 6) & 1][c & 63];
         const cplx<T> eC = nr[0], eE = nr[1], eN = nr[2], eNE = nr[3];
+        // slots of rows c+W-1, c+W-nf and c+W-nf-1 (W - nf is 2, or 3 when W
+        // was rounded up to even)
         const int sm1 = sl == 0 ? W - 1 : sl - 1;
         const int sp1 = sl + 1 == W ? 0 : sl + 1;
-        const int sp2 = sp1 + 1 == W ? 0 : sp1 + 1;
+        const int sN = sl + (W - nf) >= W ? sl + (W - nf) - W : sl + (W - nf);
+        const int sNE = sN == 0 ? W - 1 : sN - 1;
         auto value = [&](int q) {
             cplx<T> v{0, 0};
             if (q == sl) v = cadd(v, eC);
             if (q == sm1) v = cadd(v, eE);
-            if (q == sp2) v = cadd(v, eN);
-            if (q == sp1) v = cadd(v, eNE);
+            if (q == sN) v = cadd(v, eN);
+            if (q == sNE) v = cadd(v, eNE);
             return v;
         };
         if (ty == sl % TY) {

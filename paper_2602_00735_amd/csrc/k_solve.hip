@@ -13,12 +13,23 @@
 // step is one v_readlane broadcast of the pivot, one complex FMA per ring
 // slot and a v_writelane of the pivot into the block's output register.
 // The window rows live in registers as a ring spread over the lanes: row r
-// in slot r mod W, slot s in lane s mod 64 (a second register for slots
-// 64..127).  A slot whose row is finished is not reset: it keeps
-// accumulating for the row W further on, and when that row's block of 64
-// steps starts the slot is corrected by (right-hand side - finished value),
-// read from an LDS history of the last 128 outputs (for W <= 64 the
-// right-hand side enters the slot at retirement instead).
+// in slot r mod W.  Three layouts of the slots over the lanes:
+//   ONE   (W <= 64): slot s in lane s;
+//   SPLIT (W > 64, complex128): slot s in lane s mod 64, a second register
+//         for slots 64..127;
+//   PAIR  (W > 64, complex64): slots 2l and 2l+1 in lane l, so that a lane
+//         takes its two entries of a factor vector with one 16-byte load.
+//         W is even (the planner rounds it up), so slot sl of step c has the
+//         parity of c and the register holding the pivot is known at
+//         compile time in the unrolled 64-step blocks.
+// A slot whose row is finished is not reset: it keeps accumulating for the
+// row W further on, and when that row's block of 64 steps starts the slot
+// is corrected by (right-hand side - finished value), read from an LDS
+// history of the last 128 outputs (ONE: the right-hand side enters the slot
+// at retirement instead).
+//
+// The factor stream is read once per application: its loads are
+// non-temporal, so they do not displace the gathered vectors in the caches.
 //
 // The stream pointer is not clamped at the ends: the prefetch runs up to PD
 // vectors past the last backward row (into D^{-1}, the next subdomain, or
@@ -62,6 +73,23 @@ __device__ __forceinline__ cplx<T> gather_rhs(const DevSub &S, int dof_off, int 
     return to_T<T>(gather_raw(S, dof_off, n1, v, r0), r0 < S.n);
 }
 
+// Non-temporal loads of one complex value / of two adjacent complex64 values.
+template <typename T>
+__device__ __forceinline__ cplx<T> nt_load(const cplx<T> *p) {
+    using v2 = T __attribute__((ext_vector_type(2)));
+    const v2 q = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+    return cplx<T>{q.x, q.y};
+}
+__device__ __forceinline__ void nt_load_pair(const cplx<float> *p, cplx<float> &a,
+                                             cplx<float> &b) {
+    using v4 = float __attribute__((ext_vector_type(4)));
+    const v4 q = __builtin_nontemporal_load(reinterpret_cast<const v4 *>(p));
+    a = cplx<float>{q.x, q.y};
+    b = cplx<float>{q.z, q.w};
+}
+
+enum RingLayout { RING_ONE = 0, RING_SPLIT = 1, RING_PAIR = 2 };
+
 // Offset of slot s (held by this lane) from slot `sl` in the ring, in the
 // direction of the sweep: the slot holds row (pivot row) +/- that offset.
 __device__ __forceinline__ int ring_offset(int s, int sl, int W, bool down) {
@@ -69,10 +97,10 @@ __device__ __forceinline__ int ring_offset(int s, int sl, int W, bool down) {
     return t < 0 ? t + W : t;
 }
 
-// Both sweeps for one subdomain.  TWO: the ring has a second register
-// (W > 64, block correction); otherwise W <= 64 and incoming rows enter at
-// retirement.  PD: prefetch depth in vectors (divides 64).
-template <typename T, bool TWO, int PD>
+// Both sweeps for one subdomain.  RING: slot layout (above); SPLIT and PAIR
+// have a second register and the block correction, ONE takes incoming rows
+// at retirement.  PD: prefetch depth in vectors (divides 64).
+template <typename T, int RING, int PD>
 __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ probs, const DevSub &S,
                                                 const double2 *__restrict__ v,
                                                 const cplx<T> *__restrict__ F,
@@ -88,26 +116,44 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
     const cplx<T> *Dv = L + 2 * NW;             // D^{-1}
     cplx<T> *yb = ybuf + S.vec_off;
     cplx<T> *xo = xout + S.vec_off;
+    constexpr bool TWO = RING != RING_ONE;
+    constexpr bool PAIR = RING == RING_PAIR;
+    static_assert(!PAIR || sizeof(T) == 4, "the pair layout is for complex64");
     const cplx<T> zero{0, 0};
-    const bool hi_ok = lane + 64 < W;
-    const int olo = min(lane, W - 1), ohi = min(lane + 64, W - 1);
+    // slots of this lane's two registers, and whether they exist
+    const int slo = PAIR ? 2 * lane : lane, shi = PAIR ? 2 * lane + 1 : lane + 64;
+    const bool lo_ok = slo < W, hi_ok = shi < W;
+    // stream offsets: lanes past the vector end re-read its last entries
+    const int olo = PAIR ? 2 * min(lane, W / 2 - 1) : min(lane, W - 1);
+    const int ohi = min(lane + 64, W - 1);
 
-    auto pivot = [&](const cplx<T> &lo, const cplx<T> &hi, int q) {
-        return readlane(csel(!TWO || q < 64, lo, hi), q & 63);
+    // pivot of step t (row c0 + t) in slot q; PAIR: the parity of q is that
+    // of t (W and c0 even), a compile-time constant in the unrolled loops
+    auto pivot = [&](const cplx<T> &lo, const cplx<T> &hi, int q, int t) {
+        if constexpr (PAIR) return readlane((t & 1) ? hi : lo, q >> 1);
+        else return readlane(csel(!TWO || q < 64, lo, hi), q & 63);
+    };
+    auto load = [&](const cplx<T> *p, cplx<T> &a, cplx<T> &b) {
+        if constexpr (PAIR) {
+            nt_load_pair(p + olo, a, b);
+        } else {
+            a = nt_load(p + olo);
+            if (TWO) b = nt_load(p + ohi);
+        }
     };
     // block correction (W > 64): the slot of every row r of the block gets
     // rhs_r - (finished value of the row W before it)
     auto correct = [&](cplx<T> &lo, cplx<T> &hi, int sl, int rfirst, bool down) {
         __builtin_amdgcn_wave_barrier();
-        const int tlo = ring_offset(lane, sl, W, down);
-        const int thi = ring_offset(lane + 64, sl, W, down);
+        const int tlo = ring_offset(slo, sl, W, down);
+        const int thi = ring_offset(shi, sl, W, down);
         const int qlo = down ? 63 - tlo : tlo, qhi = down ? 63 - thi : thi;   // index into inc
         const int rlo = rfirst + qlo, rhi = rfirst + qhi;                     // rows
         const int plo = down ? rlo + W : rlo - W, phi = down ? rhi + W : rhi - W;
         const cplx<T> dlo = csub(inc[min(max(qlo, 0), 63)], hist[plo & 127]);
         const cplx<T> dhi = csub(inc[min(max(qhi, 0), 63)], hist[phi & 127]);
-        lo = cadd(lo, csel(tlo < 64, dlo, zero));
-        if (TWO) hi = cadd(hi, csel(hi_ok && thi < 64, dhi, zero));
+        lo = cadd(lo, csel(lo_ok && tlo < 64, dlo, zero));
+        hi = cadd(hi, csel(hi_ok && thi < 64, dhi, zero));
         __builtin_amdgcn_wave_barrier();
     };
 
@@ -116,8 +162,7 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
     cplx<T> flo[PD], fhi[PD];
 #pragma unroll
     for (int u = 0; u < PD; ++u) {
-        flo[u] = pf[olo];
-        if (TWO) fhi[u] = pf[ohi];
+        load(pf, flo[u], fhi[u]);
         pf += W;
     }
     if (TWO) {
@@ -144,13 +189,12 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
 #pragma unroll
         for (int t = 0; t < 64; ++t) {
             const int u = t % PD;
-            const cplx<T> piv = pivot(ylo, yhi, sl);                 // y_(c0+t)
+            const cplx<T> piv = pivot(ylo, yhi, sl, t);              // y_(c0+t)
             ylo = cfms(ylo, flo[u], piv);
             if (TWO) yhi = cfms(yhi, fhi[u], piv);
             if (!TWO) ylo = writelane(ylo, readlane(rblk, t), sl);   // row c + W enters
             yout = writelane(yout, piv, t);
-            flo[u] = pf[olo];
-            if (TWO) fhi[u] = pf[ohi];
+            load(pf, flo[u], fhi[u]);
             pf += W;
             sl = (sl + 1 == W) ? 0 : sl + 1;
             __builtin_amdgcn_sched_barrier(0);   // keep each step's loads in place
@@ -196,13 +240,12 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
         for (int q = 0; q < 64; ++q) {
             const int t = 63 - q;
             const int u = q % PD;
-            const cplx<T> piv = pivot(xlo, xhi, sl);                 // x_(c0+t)
+            const cplx<T> piv = pivot(xlo, xhi, sl, t);              // x_(c0+t)
             xlo = cfms(xlo, flo[u], piv);
             if (TWO) xhi = cfms(xhi, fhi[u], piv);
             if (!TWO) xlo = writelane(xlo, readlane(zblk, t), sl);   // row c - W enters
             xr = writelane(xr, piv, t);
-            flo[u] = pf[olo];
-            if (TWO) fhi[u] = pf[ohi];
+            load(pf, flo[u], fhi[u]);
             pf += W;
             sl = (sl == 0) ? W - 1 : sl - 1;
             __builtin_amdgcn_sched_barrier(0);
@@ -216,7 +259,8 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
 // One wave per SIMD by design (1024 subdomains on 1024 SIMDs at k = 640):
 // the whole register file is available to the prefetch ring.  A launch built
 // for W up to 128 still solves its subdomains with W <= 64 in the
-// one-register form (uniform branch per subdomain).
+// one-register form (uniform branch per subdomain).  W > 64 takes the pair
+// layout in complex64 (W is even) and the split layout in complex128.
 template <typename T, bool TWO, int PD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_band_solve(
     const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
@@ -226,10 +270,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __shared__ cplx<T> inc[64];                 // right-hand side of the current block
     const DevSub S = subs[order[blockIdx.x]];
     if (active != nullptr && active[S.prob] == 0) return;
+    constexpr int WIDE = sizeof(T) == 4 ? RING_PAIR : RING_SPLIT;
     if (TWO && S.W > 64)
-        solve_subdomain<T, true, PD>(probs, S, v, F, ybuf, xout, hist, inc);
+        solve_subdomain<T, WIDE, PD>(probs, S, v, F, ybuf, xout, hist, inc);
     else
-        solve_subdomain<T, false, PD>(probs, S, v, F, ybuf, xout, hist, inc);
+        solve_subdomain<T, RING_ONE, PD>(probs, S, v, F, ybuf, xout, hist, inc);
 }
 
 // z = sum over subdomains covering the node of chi_x * chi_y * x_local

@@ -207,7 +207,7 @@ int plan_problem(double k, double h, const int grid[2], const int subdomains[2],
             s.jy0 = b.u_lo;
             s.xfast = s.nx <= s.ny ? 1 : 0;
             s.nf = s.xfast ? s.nx : s.ny;
-            s.W = s.nf + 2;
+            s.W = (s.nf + 3) & ~1;    // nf + 2, rounded up to even (one zero slot)
             if (s.W > kMaxW) {
                 std::snprintf(buf, sizeof buf,
                               "subdomain band %d exceeds the supported maximum %d; use more subdomains",

@@ -113,7 +113,8 @@ def test_host_plan_matches_oracle_geometry(L, name, pb):
     assert len(desc) == len(sds)
     for d, sd in zip(desc, sds):
         assert d[0] == sd.n
-        assert d[1] == sd.n_fast and d[2] == sd.band + 1
+        # factor column length: half-bandwidth + 1, rounded up to even
+        assert d[1] == sd.n_fast and d[2] == sd.band + 1 + (sd.band + 1) % 2
         assert d[3] == int(sd.x_fast)
         assert (d[4], d[5], d[6], d[7]) == (sd.px.u_lo, sd.nx, sd.py.u_lo, sd.ny)
         assert (d[8], d[9]) == (sd.px.p, sd.py.p)

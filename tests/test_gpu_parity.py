@@ -128,13 +128,19 @@ def test_factors(name, precision):
     R = oracle_for(name)
     H = setup_gpu(pb, precision)
     tol = 1e-12 if precision == rp.RAS_FP64 else 2e-5
+    desc = H.desc()
     for m, sd in enumerate(R.sds[:4]):
-        W = sd.band + 1
+        W = desc[m][2]                       # band + 1, rounded up to even
+        assert W in (sd.band + 1, sd.band + 2) and W % 2 == 0
         npad = (sd.n + 63) // 64 * 64
         Lcols, Lrows, Dinv = rp.ras_pml_export_factor(H, m, npad, W)
         LU = R.batch.factors(m)
         b = sd.band
         n = sd.n
+        # entries past the band (the slot that makes W even) are zero
+        if W == b + 2:
+            c = np.arange(npad)
+            assert np.all(Lcols[c, (c + b + 1) % W] == 0)
         # slot position c mod W of column c holds 0
         assert np.all(Lcols[np.arange(npad), np.arange(npad) % W] == 0)
         # the row copy holds the same entries: L[r, c] at row r, position c mod W
@@ -146,7 +152,7 @@ def test_factors(name, precision):
         assert np.abs(1.0 / Dinv[:n] - D).max() <= tol * np.abs(D).max()
         assert np.allclose(Dinv[n:], 1.0)
         for c in range(0, n, max(1, n // 97)):
-            for r in range(c + 1, min(c + W, n)):
+            for r in range(c + 1, min(c + b + 1, n)):
                 ref = LU[r, b + c - r]
                 assert abs(Lcols[c, r % W] - ref) <= tol * max(1.0, abs(ref)), (m, r, c)
 
