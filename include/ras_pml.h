@@ -177,7 +177,10 @@ int ras_pml_spmv(ras_pml_t H, const void *x, void *y, void *stream);
 int ras_pml_apply(ras_pml_t H, const void *v, void *z, void *stream);
 
 /* Local solutions x_j = A_j^{-1} R_j v of every subdomain, back to back in
- * subdomain order (n_local each), complex128, before the PoU-weighted sum. */
+ * subdomain order (n_local each), complex128, before the PoU-weighted sum.
+ * xloc may be NULL: then only the batched band solve runs (the first of
+ * the two kernels of ras_pml_apply, one launch) and its result stays in the
+ * handle's work vector -- for timing that kernel alone.                   */
 int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream);
 
 /* Flexible GMRES(restart), right preconditioned by B^{-1} (Section 4.1),
@@ -256,8 +259,8 @@ int ras_pml_reset_stats(ras_pml_t H);
  *   - per complex64 factorisation window class (tiles per side): the
  *     128-register variant (four workgroups per CU) or the unconstrained
  *     one (re-runs that class's factorisation; the factor is unchanged);
- *   - the band-solve prefetch depth (32 or 16 vectors in complex64, 16 or 8
- *     in complex128).
+ *   - the band-solve prefetch depth (16 or 8 vectors; 32 or 16 for a
+ *     complex64 handle whose bands all have W <= 64).
  * cache_path (nullable): the choices are merged into this flat JSON file,
  * keyed "arch/precision/kernel/class/count" (counts rounded up to a power
  * of two), for ras_pml_opts.tune_cache.  Allocates one temporary vector;

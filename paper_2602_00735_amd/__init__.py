@@ -278,9 +278,12 @@ def ras_pml_apply(H: Handle, v, z, stream=None):
 
 
 def ras_pml_local_solve(H: Handle, v, xloc, stream=None):
+    """xloc=None: the batched band solve alone (result kept in the handle)."""
     _check_vec(v, H.ndof, "v")
-    _check_vec(xloc, H.nloc, "xloc")
-    rc = lib().ras_pml_local_solve(H.ptr, _ptr(v), _ptr(xloc), _stream(stream))
+    if xloc is not None:
+        _check_vec(xloc, H.nloc, "xloc")
+    rc = lib().ras_pml_local_solve(H.ptr, _ptr(v), None if xloc is None else _ptr(xloc),
+                                   _stream(stream))
     if rc:
         H._raise(rc)
 

@@ -184,9 +184,12 @@ ras_pml_handle::EvPair take_pair(ras_pml_handle *H) {
         H->pool.pop_back();
         return p;
     }
+    // timing only: no system-scope fence at the record (a default event
+    // writes back and invalidates the caches there, which slows the kernel
+    // it brackets); the stats are read after a stream synchronisation
     ras_pml_handle::EvPair p{};
-    (void)hipEventCreate(&p.a);
-    (void)hipEventCreate(&p.b);
+    (void)hipEventCreateWithFlags(&p.a, hipEventDisableSystemFence);
+    (void)hipEventCreateWithFlags(&p.b, hipEventDisableSystemFence);
     return p;
 }
 
@@ -384,9 +387,9 @@ int build(ras_pml_handle *H, hipStream_t st) {
     hipEvent_t e0{}, e1{}, e2{};
     const bool timing = (H->flags & RAS_FLAG_TIMING) != 0;
     if (timing) {
-        HCHK(H, hipEventCreate(&e0));
-        HCHK(H, hipEventCreate(&e1));
-        HCHK(H, hipEventCreate(&e2));
+        HCHK(H, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+        HCHK(H, hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+        HCHK(H, hipEventCreateWithFlags(&e2, hipEventDisableSystemFence));
         HCHK(H, hipEventRecord(e0, st));
     }
     launch_global_stencil(H->d_probs, H->nprob, H->max_ndof, H->d_coef, H->ntot, st);
@@ -1094,7 +1097,7 @@ int ras_pml_apply(ras_pml_t H, const void *v, void *z, void *stream) {
 }
 
 int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
-    if (!H || !v || !xloc) return RAS_EINVAL;
+    if (!H || !v) return RAS_EINVAL;
     hipStream_t st = as_stream(stream);
     {
         Timer t(H, C_SOLVE, st);
@@ -1103,6 +1106,7 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
                           static_cast<const double2 *>(v), H->d_F, H->d_ybuf, H->d_xout, st);
     }
     HCHK(H, hipGetLastError());
+    if (xloc == nullptr) return RAS_OK;        // the solves alone (timing)
     launch_export_local(H->fp64, H->d_subs, H->nsub, H->max_n, H->d_xout,
                         static_cast<double2 *>(xloc), st);
     HCHK(H, hipGetLastError());
@@ -1196,8 +1200,8 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
     hipStream_t st = as_stream(stream);
     if (H->arch.empty()) H->arch = device_arch();
     hipEvent_t e0{}, e1{};
-    HCHK(H, hipEventCreate(&e0));
-    HCHK(H, hipEventCreate(&e1));
+    HCHK(H, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    HCHK(H, hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     // best of `reps` timed runs of fn (ms)
     auto timeit = [&](auto fn, int reps) -> float {
         float best = 1e30f;

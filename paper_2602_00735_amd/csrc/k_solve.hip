@@ -335,9 +335,10 @@ void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order
 
 }  // namespace
 
-// One wave per subdomain.  deep: prefetch depth 32 (complex64) / 16
-// (complex128) vectors, else half of that; the default is deep, the
-// autotuner measures both.  F must carry 64 KB of slack past the last
+// One wave per subdomain.  deep: prefetch depth 16 vectors (32 for a
+// complex64 batch with W <= 64, whose lanes hold one slot each), else half
+// of that; the default is deep, the autotuner measures both.  (In the pair
+// layout a vector takes four registers per lane: 32 would not fit.)  F must carry 64 KB of slack past the last
 // factor (the prefetch runs past each stream's end).
 void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, const DevSub *subs,
                        const int *order, int nsub, const int *active, const double2 *v,
@@ -353,7 +354,7 @@ void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, con
         }
     } else {
         if (two) {
-            if (deep) RAS_SOLVE(float, true, 32); else RAS_SOLVE(float, true, 16);
+            if (deep) RAS_SOLVE(float, true, 16); else RAS_SOLVE(float, true, 8);
         } else {
             if (deep) RAS_SOLVE(float, false, 32); else RAS_SOLVE(float, false, 16);
         }
