@@ -20,6 +20,8 @@ frequency Helmholtz equation" (Xie, Gong, Graham, Spence, Zhang):
                    Gram-Schmidt and complex Givens rotations (Section 4.1).
 * ``richardson``-- the preconditioner used as a fixed-point iteration
                    (Algorithm 1).
+* ``warmstart`` -- the learned warm start's convolutional encoder-decoder,
+                   its hand-derived gradient and Adam (float64).
 
 Everything is complex128 / float64 and deliberately unoptimised.
 """
