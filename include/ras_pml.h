@@ -218,6 +218,64 @@ int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int max
  * batch handle. */
 int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (the north-star's learned initial guess; not part of
+ * the paper's method).  A convolutional encoder-decoder maps the source,
+ * sampled on the grid x grid nodes of the interior box (node (G + gx,
+ * G + gy) for gx, gy in [0, grid), x_i = (i - G) h), to k^2 times a guess
+ * of the solution on the same nodes; the guess is zero elsewhere.  Five
+ * levels (grid divisible by 16), level widths c0..c4 (each 1..64, c3 == c4):
+ *   e0 = relu(conv(x)), e_l = relu(conv(pool(e_{l-1}))) for l = 1..4,
+ *   d3 = relu(conv(up(e4) + e3)), d2 = relu(conv(up(d3) + e2)),
+ *   d1 = relu(conv(up(d2) + e1)), d0 = relu(conv(up(d1) + e0)),
+ *   y = conv(d0) (2 channels);
+ * conv: 3 x 3, zero padding, no bias; pool: 2 x 2 mean; up: nearest.
+ * bfloat16 weights and activations, fp32 accumulation (matrix cores), fp32
+ * master weights and Adam (beta 0.9 / 0.999, eps 1e-8).  Weights, in this
+ * order: e0 e1 e2 e3 e4 d3 d2 d1 d0 head, each W[ky][kx][cin][cout] fp32.
+ * Grids (x, y, target) are device fp32 arrays (batch, grid, grid, 2), real
+ * and imaginary parts interleaved.  A network object is used by one stream
+ * at a time.                                                               */
+typedef struct ras_pml_wsnet *ras_pml_wsnet_t;
+
+/* Allocates every buffer for batches up to batch_max (weights zero until
+ * ras_pml_wsnet_set_weights).  Errors: RAS_EINVAL, RAS_ENOMEM.            */
+int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml_wsnet_t *out);
+void ras_pml_wsnet_destroy(ras_pml_wsnet_t N);
+int ras_pml_wsnet_num_weights(ras_pml_wsnet_t N, long long *n);
+/* Host fp32 weights in, out (n = ras_pml_wsnet_num_weights); setting them
+ * resets Adam's moments and step count.  Synchronises the device.        */
+int ras_pml_wsnet_set_weights(ras_pml_wsnet_t N, const float *host, long long n);
+int ras_pml_wsnet_get_weights(ras_pml_wsnet_t N, float *host, long long n);
+/* y = network(x) for `batch` grids (device pointers).                    */
+int ras_pml_wsnet_forward(ras_pml_wsnet_t N, const float *x, int batch, float *y, void *stream);
+/* Forward, mean squared error against target, backward.  loss (host,
+ * nullable: then no synchronisation) gets the mean squared error;
+ * grad_host (host, nullable, ras_pml_wsnet_num_weights floats) the weight
+ * gradient in the order of the weights.  The gradient stays in the object
+ * for ras_pml_wsnet_adam.                                                 */
+int ras_pml_wsnet_gradient(ras_pml_wsnet_t N, const float *x, const float *target, int batch,
+                           double *loss, float *grad_host, void *stream);
+/* One Adam step with the last gradient (learning rate lr > 0).            */
+int ras_pml_wsnet_adam(ras_pml_wsnet_t N, float lr, void *stream);
+/* ras_pml_wsnet_gradient followed by ras_pml_wsnet_adam.                 */
+int ras_pml_wsnet_train_step(ras_pml_wsnet_t N, const float *x, const float *target, int batch,
+                             float lr, double *loss, void *stream);
+const char *ras_pml_wsnet_last_error(ras_pml_wsnet_t N);
+
+/* Samples a complex128 vector over the unknowns of a single-problem handle
+ * on the grid of the interior box (grid = 1/h nodes per side, as above),
+ * times `scale`, into grid_out (device fp32, grid x grid x 2).            */
+int ras_pml_grid_sample(ras_pml_t H, const void *vec, double scale, float *grid_out, void *stream);
+
+/* Initial guess for gmres_solve / ras_pml_richardson: x0 = network(f on
+ * the grid) / k^2 on the grid nodes, 0 elsewhere; kept only if
+ * ||b - A x0|| <= ||b||, else x0 = 0.  *used (nullable) = 1 when kept.
+ * Single-problem handles whose grid equals the network's.  f, b, x0:
+ * device complex128 over the unknowns.  Synchronises `stream`.           */
+int ras_pml_warm_start(ras_pml_t H, ras_pml_wsnet_t N, const void *f, const void *b, void *x0,
+                       int *used, void *stream);
+
 /* Inspection (tests).  All outputs are HOST memory, complex128.
  *   export_stencil: 4 * n_dofs values: the C, E, N and NE couplings of every
  *     unknown (E = to (i+1,j), N = to (i,j+1), NE = to (i+1,j+1); zero where

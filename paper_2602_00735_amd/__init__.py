@@ -86,6 +86,18 @@ SYMBOLS = [
     ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
+    ("ras_pml_wsnet_create", _I, [_I, _IP, _I, ctypes.POINTER(_P)]),
+    ("ras_pml_wsnet_destroy", None, [_P]),
+    ("ras_pml_wsnet_num_weights", _I, [_P, _LLP]),
+    ("ras_pml_wsnet_set_weights", _I, [_P, _P, _LL]),
+    ("ras_pml_wsnet_get_weights", _I, [_P, _P, _LL]),
+    ("ras_pml_wsnet_forward", _I, [_P, _P, _I, _P, _P]),
+    ("ras_pml_wsnet_gradient", _I, [_P, _P, _P, _I, _DP, _P, _P]),
+    ("ras_pml_wsnet_adam", _I, [_P, ctypes.c_float, _P]),
+    ("ras_pml_wsnet_train_step", _I, [_P, _P, _P, _I, ctypes.c_float, _DP, _P]),
+    ("ras_pml_wsnet_last_error", ctypes.c_char_p, [_P]),
+    ("ras_pml_grid_sample", _I, [_P, _P, _D, _P, _P]),
+    ("ras_pml_warm_start", _I, [_P, _P, _P, _P, _P, _IP, _P]),
     ("ras_pml_export_stencil", _I, [_P, _P]),
     ("ras_pml_export_local", _I, [_P, _I, _P]),
     ("ras_pml_export_factor", _I, [_P, _I, _P, _LL]),
@@ -204,6 +216,12 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    def grid_side(self):
+        """Interior grid nodes per side (single-problem handles): N_c - 2G."""
+        import math
+        n1 = math.isqrt(self.ndof)
+        return n1 + 1 - 2 * self.desc()[0][22]
 
     def problem_offset(self, p):
         off, n = ctypes.c_longlong(0), ctypes.c_longlong(0)
@@ -403,3 +421,125 @@ def ras_pml_tuning(H: Handle) -> dict:
 
 def ras_pml_strerror(status: int) -> str:
     return lib().ras_pml_strerror(status).decode()
+
+
+# ---------------------------------------------------------------- learned warm start
+WS_LAYERS = ("e0", "e1", "e2", "e3", "e4", "d3", "d2", "d1", "d0", "head")
+
+
+def ws_shapes(channels):
+    """(cin, cout) of every convolution, in the order of the weights."""
+    c0, c1, c2, c3, c4 = channels
+    return [(2, c0), (c0, c1), (c1, c2), (c2, c3), (c3, c4), (c4, c2), (c2, c1), (c1, c0),
+            (c0, c0), (c0, 2)]
+
+
+class WSNet:
+    """The warm-start encoder-decoder (all compute in the library's kernels)."""
+
+    def __init__(self, grid, channels, batch_max):
+        self.grid, self.channels, self.batch_max = int(grid), tuple(channels), int(batch_max)
+        ptr = _P()
+        rc = lib().ras_pml_wsnet_create(self.grid, (ctypes.c_int * 5)(*self.channels),
+                                        self.batch_max, ctypes.byref(ptr))
+        if rc:
+            raise RasPmlError(rc, "ras_pml_wsnet_create: %s" % _STATUS.get(rc, rc))
+        self.ptr = ptr
+        n = _LL(0)
+        lib().ras_pml_wsnet_num_weights(self.ptr, ctypes.byref(n))
+        self.nweights = n.value
+
+    def _check(self, rc):
+        if rc:
+            msg = lib().ras_pml_wsnet_last_error(self.ptr).decode()
+            raise RasPmlError(rc, "%s: %s" % (_STATUS.get(rc, rc), msg))
+
+    def set_weights(self, flat):
+        import numpy as np
+        w = np.ascontiguousarray(flat, dtype=np.float32)
+        assert w.size == self.nweights
+        self._check(lib().ras_pml_wsnet_set_weights(self.ptr, w.ctypes.data_as(_P), w.size))
+
+    def get_weights(self):
+        import numpy as np
+        w = np.zeros(self.nweights, dtype=np.float32)
+        self._check(lib().ras_pml_wsnet_get_weights(self.ptr, w.ctypes.data_as(_P), w.size))
+        return w
+
+    def _grid(self, t, name):
+        import torch
+        if (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4
+                or tuple(t.shape[1:]) != (self.grid, self.grid, 2) or t.shape[0] > self.batch_max):
+            raise ValueError("%s must be a contiguous float32 CUDA tensor (B, %d, %d, 2), B <= %d"
+                             % (name, self.grid, self.grid, self.batch_max))
+
+    def forward(self, x, y=None, stream=None):
+        import torch
+        self._grid(x, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        self._grid(y, "y")
+        self._check(lib().ras_pml_wsnet_forward(self.ptr, _ptr(x), x.shape[0], _ptr(y),
+                                                _stream(stream)))
+        return y
+
+    def gradient(self, x, target, want_grad=True, stream=None):
+        """Returns (loss, flat gradient or None)."""
+        import numpy as np
+        self._grid(x, "x")
+        self._grid(target, "target")
+        loss = ctypes.c_double(0.0)
+        g = np.zeros(self.nweights, dtype=np.float32) if want_grad else None
+        self._check(lib().ras_pml_wsnet_gradient(self.ptr, _ptr(x), _ptr(target), x.shape[0],
+                                                 ctypes.byref(loss),
+                                                 g.ctypes.data_as(_P) if want_grad else None,
+                                                 _stream(stream)))
+        return loss.value, g
+
+    def adam(self, lr, stream=None):
+        self._check(lib().ras_pml_wsnet_adam(self.ptr, float(lr), _stream(stream)))
+
+    def train_step(self, x, target, lr, want_loss=False, stream=None):
+        loss = ctypes.c_double(0.0)
+        self._check(lib().ras_pml_wsnet_train_step(self.ptr, _ptr(x), _ptr(target), x.shape[0],
+                                                   float(lr),
+                                                   ctypes.byref(loss) if want_loss else None,
+                                                   _stream(stream)))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().ras_pml_wsnet_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ras_pml_grid_sample(H: Handle, vec, scale=1.0, out=None, stream=None):
+    """vec (complex128 over the unknowns) on the interior grid, times scale:
+    float32 (grid, grid, 2)."""
+    import torch
+    _check_vec(vec, H.ndof, "vec")
+    n = H.grid_side()
+    if out is None:
+        out = torch.empty((n, n, 2), dtype=torch.float32, device=vec.device)
+    rc = lib().ras_pml_grid_sample(H.ptr, _ptr(vec), float(scale), _ptr(out), _stream(stream))
+    if rc:
+        H._raise(rc)
+    return out
+
+
+def ras_pml_warm_start(H: Handle, net: WSNet, f, b, x0, stream=None):
+    """Fills x0 with the network's guess (or zeros); returns whether it was kept."""
+    for t, nm in ((f, "f"), (b, "b"), (x0, "x0")):
+        _check_vec(t, H.ndof, nm)
+    used = ctypes.c_int(0)
+    rc = lib().ras_pml_warm_start(H.ptr, net.ptr, _ptr(f), _ptr(b), _ptr(x0), ctypes.byref(used),
+                                  _stream(stream))
+    if rc:
+        H._raise(rc)
+    return bool(used.value)

@@ -23,7 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HIP_SOURCES = ["k_assemble.hip", "k_lu.hip", "k_lu_mfma.hip", "k_solve.hip", "k_krylov.hip",
-               "abi.hip"]
+               "k_warm.hip", "warm_net.hip", "abi.hip"]
 CPP_SOURCES = ["plan.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -16,6 +16,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "warm.h"
 
 namespace raspml {
 
@@ -1143,6 +1144,66 @@ int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int max
         H->last_error = e.what();
         return RAS_ENOMEM;
     }
+}
+
+static int single_grid(ras_pml_t H, int *grid) {
+    if (H->nprob != 1) {
+        H->last_error = "the interior grid is defined for single-problem handles";
+        return RAS_EINVAL;
+    }
+    const DevProb &D = H->hprobs[0];
+    if (D.G < 1) {
+        H->last_error = "the interior grid needs a global PML of at least one cell";
+        return RAS_EINVAL;
+    }
+    *grid = D.Nc - 2 * D.G;
+    return RAS_OK;
+}
+
+int ras_pml_grid_sample(ras_pml_t H, const void *vec, double scale, float *grid_out, void *stream) {
+    if (!H || !vec || !grid_out) return RAS_EINVAL;
+    int grid = 0;
+    RCHK(single_grid(H, &grid));
+    const DevProb &D = H->hprobs[0];
+    warm_grid_sample(static_cast<const double2 *>(vec), D.n1, D.G, grid, scale, grid_out,
+                     as_stream(stream));
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+int ras_pml_warm_start(ras_pml_t H, ras_pml_wsnet_t N, const void *f, const void *b, void *x0,
+                       int *used, void *stream) {
+    if (!H || !N || !f || !b || !x0 || b == x0 || f == x0) return RAS_EINVAL;
+    int grid = 0;
+    RCHK(single_grid(H, &grid));
+    if (grid != wsnet_grid(N)) {
+        H->last_error = "the network's grid differs from the problem's interior grid";
+        return RAS_EINVAL;
+    }
+    hipStream_t st = as_stream(stream);
+    const DevProb &D = H->hprobs[0];
+    double2 *x = static_cast<double2 *>(x0);
+    const double2 *bb = static_cast<const double2 *>(b);
+    RCHK(ensure_krylov(H, 1));
+    warm_grid_sample(static_cast<const double2 *>(f), D.n1, D.G, grid, 1.0, wsnet_stage(N), st);
+    HCHK(H, hipGetLastError());
+    RCHK(wsnet_forward(N, wsnet_stage(N), 1, wsnet_out(N), st));
+    warm_grid_scatter(wsnet_out(N), D.n1, D.G, grid, 1.0 / (D.k * D.k), x, D.ndof, st);
+    HCHK(H, hipGetLastError());
+    // keep the guess only if its residual is below that of x0 = 0
+    RCHK(reduce_sync(H, bb, nullptr, 0, st));
+    const double bn = H->h_red[0].x;
+    launch_spmv(H->d_probs, 1, H->max_ndof, nullptr, H->d_coef, H->ntot, x, bb, H->d_r, st);
+    HCHK(H, hipGetLastError());
+    RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
+    const double rn = H->h_red[0].x;
+    const bool keep = std::isfinite(rn) && rn <= bn;
+    if (!keep) {
+        HCHK(H, hipMemsetAsync(x, 0, sizeof(double2) * D.ndof, st));
+        HCHK(H, hipStreamSynchronize(st));
+    }
+    if (used) *used = keep ? 1 : 0;
+    return RAS_OK;
 }
 
 int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged) {

@@ -66,3 +66,22 @@ def random_vector(n: int, seed: int) -> np.ndarray:
 def batch_source(n_int: int, G: int, draw) -> np.ndarray:
     """Nodal values of a ``batch_draw`` source on the given mesh."""
     return gaussian(n_int, G, draw["centres"], draw["amps"], draw["width"])
+
+
+def warm_draw(seed: int, k: float = 320.0, width: float = 0.03):
+    """A seeded source for the learned warm start: fixed k, then the draws of
+    ``batch_draw`` after k (number of sources, centres, |a|, phase)."""
+    rng = np.random.default_rng(seed)
+    ns = int(rng.integers(1, 5))
+    centres = rng.uniform(0.2, 0.8, (ns, 2))
+    mag = rng.uniform(0.5, 1.0, ns)
+    phase = rng.uniform(0.0, 2.0 * np.pi, ns)
+    return {"k": float(k), "centres": centres, "amps": mag * np.exp(1j * phase), "width": width}
+
+
+def ws_init_weights(shapes, seed: int, gain: float = 1.0) -> np.ndarray:
+    """Seeded He-normal weights for a list of (cin, cout) 3 x 3 convolutions,
+    each W[ky][kx][cin][cout], concatenated as float32."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal(9 * ci * co) * gain * np.sqrt(2.0 / (9 * ci)) for ci, co in shapes]
+    return np.concatenate(parts).astype(np.float32)
