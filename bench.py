@@ -80,6 +80,15 @@ def main():
                          "subdomain boundary conditions (Tables 1/2 set-up) and the growth of "
                          "iterations and time with k (Tables 3/4 set-up); one JSON line per run")
     ap.add_argument("--sweep-max-k", type=float, default=1280.0)
+    ap.add_argument("--warmstart", action="store_true",
+                    help="only run the learned warm start at k = 320, h = 1/640, 16x16 subdomains: "
+                         "solve --ws-train seeded problems, train the encoder-decoder on the "
+                         "(source, k^2 u) pairs, compare GMRES from the network's guess with GMRES "
+                         "from zero on --ws-test held-out seeds")
+    ap.add_argument("--ws-train", type=int, default=4096)
+    ap.add_argument("--ws-test", type=int, default=256)
+    ap.add_argument("--ws-epochs", type=int, default=4)
+    ap.add_argument("--ws-batch", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC traffic calibration)")
     args = ap.parse_args()
@@ -108,6 +117,9 @@ def main():
 
     if args.sweep:
         sweep(args.sweep_max_k)
+        return
+    if args.warmstart:
+        warmstart(args)
         return
 
     k, n_int, P = WORKLOADS[args.workload]
@@ -391,6 +403,151 @@ def sweep(max_k):
         r.update(sweep="growth", variant="RAS-PML-Imp",
                  total_per_k=round((r["setup_s"] + r["solve_s"]) / k, 6))
         print(json.dumps(r), flush=True)
+
+
+def warmstart(args):
+    """Learned warm start (config: k = 320, h = 1/640, 16 x 16 subdomains,
+    overlap = PML = global PML = ceil(ln k / (k h)) = 12 cells, sources of 1-4
+    Gaussians of width 0.03 as in the 32-problem batch, mixed precision,
+    GMRES(100) to rtol 1e-6).  Training seeds 1..N, held-out seeds from
+    100001.  One JSON line per phase."""
+    import numpy as np
+    import torch
+    import paper_2602_00735_amd as rp
+    from paper_2602_00735_amd import inputs
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    k, n, P = 320.0, 640, 16
+    h = 1.0 / n
+    L = log_width(k, h)
+    G = L
+    H = rp.ras_pml_setup(k, h, (n, n), (P, P), L, L, rp.default_opts(global_pml=G))
+    assert H.grid_side() == n
+    channels = (16, 32, 64, 64, 64)
+
+    def problem(seed):
+        f = torch.from_numpy(inputs.batch_source(n, G, inputs.warm_draw(seed, k))).to(dev)
+        b = torch.empty_like(f)
+        rp.ras_pml_rhs(H, f, b)
+        return f, b
+
+    # ------------------------------------------------------------ data
+    N = args.ws_train
+    X = torch.empty((N, n, n, 2), dtype=torch.float32, device=dev)
+    T = torch.empty_like(X)
+    t0 = time.perf_counter()
+    its = []
+    for i in range(N):
+        f, b = problem(1 + i)
+        x = torch.zeros_like(f)
+        rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+        assert rc == rp.RAS_OK
+        its.append(it)
+        rp.ras_pml_grid_sample(H, f, 1.0, X[i])
+        rp.ras_pml_grid_sample(H, x, k * k, T[i])
+        if (i + 1) % 512 == 0:
+            torch.cuda.synchronize()
+            print(json.dumps({"phase": "data", "solved": i + 1, "s": round(time.perf_counter() - t0, 1),
+                              "mean_iters": round(float(np.mean(its)), 2)}), flush=True)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+
+    # ------------------------------------------------------------ training
+    net = rp.WSNet(n, channels, args.ws_batch)
+    net.set_weights(inputs.ws_init_weights(rp.ws_shapes(channels), 0))
+    rng = np.random.default_rng(0)
+    Bt = args.ws_batch
+    steps_per_epoch = N // Bt
+    xb = torch.empty((Bt, n, n, 2), dtype=torch.float32, device=dev)
+    tb = torch.empty_like(xb)
+    # algorithmic flops of one training step: forward, input gradient (all but
+    # the first convolution) and weight gradient of every 3 x 3 convolution
+    lv = (0, 1, 2, 3, 4, 3, 2, 1, 0, 0)
+    flops = 0.0
+    for li, (ci, co) in enumerate(rp.ws_shapes(channels)):
+        m = Bt * (n >> lv[li]) ** 2
+        flops += (3 if li > 0 else 2) * 2.0 * m * 9 * ci * co
+    t0 = time.perf_counter()
+    step_times = []
+    for ep in range(args.ws_epochs):
+        lr = 1e-3 if ep < args.ws_epochs - 1 else 3e-4
+        perm = rng.permutation(N)
+        losses = []
+        te = time.perf_counter()
+        for st in range(steps_per_epoch):
+            idx = torch.from_numpy(perm[st * Bt:(st + 1) * Bt]).to(dev)
+            torch.index_select(X, 0, idx, out=xb)
+            torch.index_select(T, 0, idx, out=tb)
+            want = st % 64 == 0
+            loss = net.train_step(xb, tb, lr, want_loss=want)
+            if want:
+                losses.append(loss)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - te
+        step_times.append(dt / steps_per_epoch)
+        print(json.dumps({"phase": "train", "epoch": ep + 1, "lr": lr, "s": round(dt, 2),
+                          "loss_first": losses[0], "loss_last": losses[-1]}), flush=True)
+    t_train = time.perf_counter() - t0
+    # one step timed alone with HIP events (the training step's kernels)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.gradient(xb, tb, want_grad=False)
+    e1.record()
+    torch.cuda.synchronize()
+    grad_ms = e0.elapsed_time(e1) / 10
+    e0.record()
+    for _ in range(10):
+        net.forward(xb)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+
+    # ------------------------------------------------------------ held-out
+    res = {"zero": [], "warm": []}
+    used = 0
+    for i in range(args.ws_test):
+        f, b = problem(100001 + i)
+        x = torch.zeros_like(f)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rc, it0, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+        torch.cuda.synchronize()
+        tb_ = time.perf_counter()
+        x0 = torch.empty_like(f)
+        u = rp.ras_pml_warm_start(H, net, f, b, x0)
+        rc1, it1, rr1, _ = rp.gmres_solve(H, b, x0, rtol=1e-6, restart=100, maxit=500)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        assert rc == rp.RAS_OK and rc1 == rp.RAS_OK
+        used += int(u)
+        res["zero"].append((it0, tb_ - ta))
+        res["warm"].append((it1, tc - tb_))
+    z = np.array(res["zero"])
+    w = np.array(res["warm"])
+    out = {
+        "phase": "result",
+        "workload": "learned warm start: k=320 h=1/640 16x16 subdomains overlap=pml=%d, "
+                    "1-4 Gaussians (width 0.03), GMRES(100) rtol 1e-6, mixed precision" % L,
+        "network": {"levels": 5, "channels": channels, "grid": n, "weights": net.nweights,
+                    "dtype": "bf16 weights/activations, fp32 accumulation and Adam"},
+        "training": {"pairs": N, "epochs": args.ws_epochs, "batch": Bt, "data_s": round(t_data, 1),
+                     "train_s": round(t_train, 1), "samples_per_s": round(N * args.ws_epochs / t_train, 1),
+                     "mean_iters_from_zero": round(float(np.mean(its)), 2)},
+        "kernels": {"train_step_ms": round(grad_ms, 3), "forward_ms": round(fwd_ms, 3),
+                    "train_step_tflops": round(flops / (grad_ms * 1e-3) / 1e12, 2),
+                    "bf16_mfma_peak_tflops": 2500.0,
+                    "frac": round(flops / (grad_ms * 1e-3) / 1e12 / 2500.0, 4)},
+        "held_out": {"seeds": args.ws_test, "guess_kept": used,
+                     "iters_zero_mean": round(float(z[:, 0].mean()), 2),
+                     "iters_warm_mean": round(float(w[:, 0].mean()), 2),
+                     "time_zero_ms_mean": round(1000 * float(z[:, 1].mean()), 3),
+                     "time_warm_ms_mean": round(1000 * float(w[:, 1].mean()), 3),
+                     "note": "warm times include the network's forward pass and the residual test"},
+    }
+    net.close()
+    H.close()
+    print(json.dumps(out), flush=True)
 
 
 def batch32(dev, no_fp64):
