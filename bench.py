@@ -462,11 +462,19 @@ def warmstart(args):
     tb = torch.empty_like(xb)
     # algorithmic flops of one training step: forward, input gradient (all but
     # the first convolution) and weight gradient of every 3 x 3 convolution
+    # and its algorithmic HBM bytes: every convolution reads its input and
+    # writes its output (bf16, channels padded to 16), the input gradient
+    # reads the masked output gradient and writes the input gradient, the
+    # weight gradient reads input and masked gradient, the mask reads the
+    # gradient and the activation and writes the masked gradient
     lv = (0, 1, 2, 3, 4, 3, 2, 1, 0, 0)
-    flops = 0.0
+    cp = lambda c: (c + 15) // 16 * 16
+    flops = nbytes = 0.0
     for li, (ci, co) in enumerate(rp.ws_shapes(channels)):
         m = Bt * (n >> lv[li]) ** 2
         flops += (3 if li > 0 else 2) * 2.0 * m * 9 * ci * co
+        a, b = 2.0 * m * cp(ci), 2.0 * m * cp(co)
+        nbytes += (a + b) * (3 if li > 0 else 2) + (3 * b if li < 9 else 0)
     t0 = time.perf_counter()
     step_times = []
     for ep in range(args.ws_epochs):
@@ -537,7 +545,11 @@ def warmstart(args):
         "kernels": {"train_step_ms": round(grad_ms, 3), "forward_ms": round(fwd_ms, 3),
                     "train_step_tflops": round(flops / (grad_ms * 1e-3) / 1e12, 2),
                     "bf16_mfma_peak_tflops": 2500.0,
-                    "frac": round(flops / (grad_ms * 1e-3) / 1e12 / 2500.0, 4)},
+                    "mfma_frac": round(flops / (grad_ms * 1e-3) / 1e12 / 2500.0, 4),
+                    "train_step_algorithmic_GB": round(nbytes / 1e9, 3),
+                    "train_step_GBs": round(nbytes / (grad_ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(nbytes / (grad_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "bound": "hbm (about 70 flop per byte at 16 channels, below the bf16 ridge)"},
         "held_out": {"seeds": args.ws_test, "guess_kept": used,
                      "iters_zero_mean": round(float(z[:, 0].mean()), 2),
                      "iters_warm_mean": round(float(w[:, 0].mean()), 2),

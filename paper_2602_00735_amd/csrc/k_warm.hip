@@ -9,9 +9,9 @@
 //     A operand is gathered straight from the input tensor (4 channels of
 //     one pixel per lane, one 8-byte load), the B operand from weights
 //     packed per (tap, channel block, column tile) as 16 x 16 blocks;
-//     the input gradient is the same kernel on the output gradient with
-//     the taps flipped and the channel roles swapped, the ReLU of the
-//     forward applied as a gate on the gathered values;
+//     the input gradient is the same kernel on the output gradient (after
+//     the ReLU mask, applied once per layer) with the taps flipped and the
+//     channel roles swapped;
 //   weight gradient: rows = (tap, input channel), columns = output
 //     channels, K = pixels, split over workgroups in fixed chunks; every
 //     workgroup writes its partial sums and a second kernel adds them in a
@@ -34,29 +34,24 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
     u += 0x7FFFu + ((u >> 16) & 1u);
     return static_cast<bf16>(u >> 16);
 }
-// a post-ReLU value is positive exactly when its bits are non-zero
-__device__ __forceinline__ short gate1(short x, short g) { return g != 0 ? x : short(0); }
-
-// out[p][co] (+)= sum_{tap, ci} in[p + off(tap)][ci] W[tap][ci][co], with
-// in = X (times [gate > 0] when gate is given).  NT: output channel tiles.
-// OUT_F32: write the first `creal` channels as fp32 (the network's head).
+// out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
+// NT: output channel tiles.  OUT_F32: write the first `creal` channels as
+// fp32 (the network's head).
 template <int NT, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
-                                                 const bf16 *__restrict__ gate,
                                                  const bf16 *__restrict__ Wp, void *__restrict__ Y,
                                                  int B, int H, int W, int CPin, int relu, int acc,
                                                  int creal) {
     constexpr int CPout = 16 * NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long M = static_cast<long long>(B) * H * W;
-    const long long p0 = (static_cast<long long>(blockIdx.x) * 4 + wave) * 16;
+    const int M = B * H * W;                // < 2^31 (checked by the launcher)
+    const int p0 = (blockIdx.x * 4 + wave) * 16;
     if (p0 >= M) return;                    // no barrier in this kernel
     const int i = lane & 15, kq = lane >> 4;
-    const long long p = p0 + i;
+    const int p = p0 + i;
     const bool pin = p < M;
-    const long long pc = pin ? p : M - 1;
-    const int x = static_cast<int>(pc % W), y = static_cast<int>((pc / W) % H);
-    const long long b = pc / (static_cast<long long>(W) * H);
+    const int pc = pin ? p : M - 1;
+    const int x = pc % W, y = (pc / W) % H, b = pc / (W * H);
     v4f c[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) c[t] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -64,15 +59,10 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
     for (int tap = 0; tap < 9; ++tap) {
         const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
         const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const long long q = ok ? (b * H + yy) * W + xx : 0;
+        const long long q = ok ? (static_cast<long long>(b) * H + yy) * W + xx : 0;
         const bf16 *xr = X + q * CPin + 4 * kq;
-        const bf16 *gr = (gate != nullptr ? gate : X) + q * CPin + 4 * kq;
         for (int kc = 0; kc < KC; ++kc) {
             v4s a = *reinterpret_cast<const v4s *>(xr + 16 * kc);
-            if (gate != nullptr) {
-                const v4s g = *reinterpret_cast<const v4s *>(gr + 16 * kc);
-                a = v4s{gate1(a[0], g[0]), gate1(a[1], g[1]), gate1(a[2], g[2]), gate1(a[3], g[3])};
-            }
             if (!ok) a = v4s{0, 0, 0, 0};
             const bf16 *wb = Wp + static_cast<long long>((tap * KC + kc) * NT) * 256 + i * 16 + 4 * kq;
 #pragma unroll
@@ -88,7 +78,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long long po = p0 + 4 * kq + r;
-            if (po >= M) continue;
+            if (po >= static_cast<long long>(M)) continue;
             float v = c[t][r];
             if (relu) v = fmaxf(v, 0.f);
             const int ch = 16 * t + i;
@@ -103,50 +93,50 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
 }
 
 // Partial weight gradient of one pixel chunk:
-//   part[blk][tap][ci][co] = sum_{p in chunk} X[p + off(tap)][ci] dZ[p][co],
-//   dZ = dY (times [gate > 0] when gate is given).
+//   part[blk][tap][ci][co] = sum_{p in chunk} X[p + off(tap)][ci] dZ[p][co]
+// (dZ: the output gradient, already multiplied by the ReLU mask).
 // Each wave owns the (tap, channel block) row tiles w, w + 4, ...: at most
-// MAXT = ceil(9 KC / 4) of them (KC = input channel blocks).
+// MAXT = ceil(9 KC / 4) of them (KC = input channel blocks).  The lane's four
+// pixels advance by 16 per step; their coordinates are stepped, not divided.
 template <int NT, int KC>
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ X,
-                                                       const bf16 *__restrict__ dY,
-                                                       const bf16 *__restrict__ gate,
+                                                       const bf16 *__restrict__ dZ,
                                                        float *__restrict__ part, int B, int H,
-                                                       int W, int CPin, int chunk) {
-    constexpr int CPout = 16 * NT;
+                                                       int W, int chunk) {
+    constexpr int CPin = 16 * KC, CPout = 16 * NT;
     constexpr int ntile = 9 * KC, MAXT = (ntile + 3) / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kq = lane >> 4;
-    const long long M = static_cast<long long>(B) * H * W;
-    const long long c0 = static_cast<long long>(blockIdx.x) * chunk;
-    const long long c1 = min(c0 + chunk, M);
+    const int M = B * H * W;
+    const int c0 = blockIdx.x * chunk;
+    const int c1 = min(c0 + chunk, M);
     v4f c[MAXT][NT];
 #pragma unroll
     for (int s = 0; s < MAXT; ++s)
 #pragma unroll
         for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (long long pb = c0; pb < c1; pb += 16) {
-        // pixels of this lane's K quad
-        int px[4], py[4];
-        long long pbb[4];
+    int px[4], py[4], pb[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int q = min(c0 + 4 * kq + e, M - 1);
+        px[e] = q % W;
+        py[e] = (q / W) % H;
+        pb[e] = q / (W * H);
+    }
+    for (int p = c0; p < c1; p += 16) {
         bool pv[4];
+        int q[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const long long pe = pb + 4 * kq + e;
-            pv[e] = pe < c1;
-            const long long q = pv[e] ? pe : c0;
-            px[e] = static_cast<int>(q % W);
-            py[e] = static_cast<int>((q / W) % H);
-            pbb[e] = q / (static_cast<long long>(W) * H);
+            pv[e] = p + 4 * kq + e < c1;
+            q[e] = (pb[e] * H + py[e]) * W + px[e];
         }
         v4s bz[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const long long q = (pbb[e] * H + py[e]) * W + px[e];
-                short v = static_cast<short>(dY[q * CPout + 16 * t + i]);
-                if (gate != nullptr) v = gate1(v, static_cast<short>(gate[q * CPout + 16 * t + i]));
+                const short v = static_cast<short>(dZ[static_cast<long long>(pv[e] ? q[e] : 0) * CPout + 16 * t + i]);
                 bz[t][e] = pv[e] ? v : short(0);
             }
 #pragma unroll
@@ -154,18 +144,31 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ 
             const int T = wave + 4 * s;
             if (T >= ntile) continue;
             const int tap = T / KC, kc = T % KC;
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
             v4s a;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int yy = py[e] + tap / 3 - 1, xx = px[e] + tap % 3 - 1;
+                const int yy = py[e] + dy, xx = px[e] + dx;
                 const bool ok = pv[e] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-                const long long q = ok ? (pbb[e] * H + yy) * W + xx : 0;
-                const short v = static_cast<short>(X[q * CPin + 16 * kc + i]);
+                const int qq = ok ? q[e] + dy * W + dx : 0;
+                const short v = static_cast<short>(X[static_cast<long long>(qq) * CPin + 16 * kc + i]);
                 a[e] = ok ? v : short(0);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
                 c[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[s][t], 0, 0, 0);
+        }
+        // advance the four pixels by 16
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            px[e] += 16;
+            while (px[e] >= W) {
+                px[e] -= W;
+                if (++py[e] == H) {
+                    py[e] = 0;
+                    ++pb[e];
+                }
+            }
         }
     }
     float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
@@ -179,19 +182,38 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ci = 16 * kc + 4 * kq + r, co = 16 * t + i;
-                pw[(static_cast<long long>(tap) * CPin + ci) * CPout + co] = c[s][t][r];
+                pw[(tap * CPin + ci) * CPout + co] = c[s][t][r];
             }
     }
 }
 
-// g[idx] = sum over blocks of part[blk][idx], in block order.
-__global__ void k_sum_partials(const float *__restrict__ part, int nblk, int n,
-                               float *__restrict__ g) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+// dZ = dY where the forward output G is positive (a post-ReLU value is
+// positive exactly when its bits are non-zero), else 0.
+__global__ void k_gate(const bf16 *__restrict__ dY, const bf16 *__restrict__ G,
+                       bf16 *__restrict__ dZ, long long n) {
+    const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    dZ[o] = G[o] != 0 ? dY[o] : bf16(0);
+}
+
+// g[idx] = sum over blocks of part[blk][idx]: 32 slices of the blocks are
+// summed in order by 32 threads, then the slice sums in slice order
+// (the same order at every launch: deterministic).
+__global__ __launch_bounds__(256) void k_sum_partials(const float *__restrict__ part, int nblk,
+                                                      int n, float *__restrict__ g) {
+    __shared__ float red[8][33];
+    const int sl = threadIdx.x & 31, o = threadIdx.x >> 5;     // slice, output in block
+    const int idx = blockIdx.x * 8 + o;
     float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += part[static_cast<long long>(k) * n + idx];
-    g[idx] = s;
+    if (idx < n)
+        for (int k = sl; k < nblk; k += 32) s += part[static_cast<long long>(k) * n + idx];
+    red[o][sl] = s;
+    __syncthreads();
+    if (sl == 0 && idx < n) {
+        float t = 0.f;
+        for (int j = 0; j < 32; ++j) t += red[o][j];
+        g[idx] = t;
+    }
 }
 
 // 2 x 2 mean: Y (B, H/2, W/2, C) from X (B, H, W, C).
@@ -372,14 +394,14 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-void warm_conv(const void *X, const void *gate, const void *Wp, void *Y, int B, int H, int W,
-               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
+// B * H * W < 2^31 (the network object checks it at creation).
+void warm_conv(const void *X, const void *Wp, void *Y, int B, int H, int W, int CPin, int CPout,
+               bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
     const dim3 grid(blocks(M, 64)), blk(256);
-    const bf16 *x = static_cast<const bf16 *>(X), *g = static_cast<const bf16 *>(gate),
-               *w = static_cast<const bf16 *>(Wp);
+    const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp);
 #define RAS_CONV(NT, F32)                                                                        \
-    hipLaunchKernelGGL((k_conv3x3<NT, F32>), grid, blk, 0, s, x, g, w, Y, B, H, W, CPin,        \
+    hipLaunchKernelGGL((k_conv3x3<NT, F32>), grid, blk, 0, s, x, w, Y, B, H, W, CPin,           \
                        relu ? 1 : 0, acc ? 1 : 0, creal)
     if (out_f32) {
         RAS_CONV(1, true);
@@ -401,16 +423,15 @@ int warm_wgrad_blocks(long long M, int *chunk) {
     return static_cast<int>((M + c - 1) / c);
 }
 
-void warm_wgrad(const void *X, const void *dY, const void *gate, float *part, float *g, int B,
-                int H, int W, int CPin, int CPout, hipStream_t s) {
+void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int H, int W,
+                int CPin, int CPout, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
     int chunk = 0;
     const int nblk = warm_wgrad_blocks(M, &chunk);
-    const bf16 *x = static_cast<const bf16 *>(X), *dy = static_cast<const bf16 *>(dY),
-               *gt = static_cast<const bf16 *>(gate);
+    const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
 #define RAS_WG(NT, KC)                                                                           \
-    hipLaunchKernelGGL((k_conv3x3_wgrad<NT, KC>), dim3(nblk), dim3(256), 0, s, x, dy, gt, part, B, \
-                       H, W, CPin, chunk)
+    hipLaunchKernelGGL((k_conv3x3_wgrad<NT, KC>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H, \
+                       W, chunk)
 #define RAS_WG_KC(NT)                                                                            \
     do {                                                                                         \
         if (CPin == 16) RAS_WG(NT, 1);                                                           \
@@ -426,7 +447,12 @@ void warm_wgrad(const void *X, const void *dY, const void *gate, float *part, fl
 #undef RAS_WG_KC
 #undef RAS_WG
     const int n = 9 * CPin * CPout;
-    hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 256)), dim3(256), 0, s, part, nblk, n, g);
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, nblk, n, g);
+}
+
+void warm_gate(const void *dY, const void *G, void *dZ, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_gate, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(dY),
+                       static_cast<const bf16 *>(G), static_cast<bf16 *>(dZ), n);
 }
 
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s) {
