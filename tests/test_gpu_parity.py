@@ -589,6 +589,23 @@ def test_k640_gmres_mixed_vs_fp64_and_true_residual():
     assert relerr(xs[rp.RAS_MIXED], xs[rp.RAS_FP64]) <= 1e-5
 
 
+def test_k640_runs_the_fused_arnoldi_step():
+    """Performance guard: at k = 640 the whole grid of the cooperative
+    Arnoldi kernel fits on the chip, so no step falls back to the
+    one-launch-per-projection path (which would launch the SpMV separately)."""
+    pb = geometry.config_problem("k640")
+    o = rp.default_opts(global_pml=pb.G, flags=rp.RAS_FLAG_TIMING)
+    H = rp.ras_pml_setup(pb.k, 1.0 / pb.n_int, (pb.n_int, pb.n_int), (pb.Px, pb.Py), pb.delta,
+                         pb.kappa, o)
+    b = dev(inputs.random_vector(pb.ndof, 3))
+    x = torch.zeros_like(b)
+    rp.ras_pml_reset_stats(H)
+    rp.gmres_solve(H, b, x, rtol=1e-12, restart=100, maxit=3, check=False)
+    st = rp.ras_pml_get_stats(H)
+    assert st["n_mgs"] == 3 and st["n_spmv"] == 0, st
+    H.close()
+
+
 def test_k160_gmres_mixed_against_full_oracle():
     """k = 160, h = 1/320, 16 x 16 subdomains: the whole oracle solve."""
     pb = geometry.config_problem("k160")
