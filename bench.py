@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--ws-test", type=int, default=256)
     ap.add_argument("--ws-epochs", type=int, default=4)
     ap.add_argument("--ws-batch", type=int, default=8)
+    ap.add_argument("--ws-source", default="gaussian", choices=["gaussian", "narrow"],
+                    help="gaussian: 1-4 Gaussians of width 0.03; narrow: 1-4 of the paper's "
+                         "smoothed point sources (width pi/(4k)), which radiate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC traffic calibration)")
     args = ap.parse_args()
@@ -425,8 +428,12 @@ def warmstart(args):
     assert H.grid_side() == n
     channels = (16, 32, 64, 64, 64)
 
+    draw = inputs.warm_draw if args.ws_source == "gaussian" else inputs.warm_draw_narrow
+    # sources and targets at unit scale (the map f -> u is linear)
+    fscale = 1.0 if args.ws_source == "gaussian" else 16.0 * k * k / math.pi ** 3
+
     def problem(seed):
-        f = torch.from_numpy(inputs.batch_source(n, G, inputs.warm_draw(seed, k))).to(dev)
+        f = torch.from_numpy(inputs.batch_source(n, G, draw(seed, k))).to(dev)
         b = torch.empty_like(f)
         rp.ras_pml_rhs(H, f, b)
         return f, b
@@ -443,8 +450,8 @@ def warmstart(args):
         rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
         assert rc == rp.RAS_OK
         its.append(it)
-        rp.ras_pml_grid_sample(H, f, 1.0, X[i])
-        rp.ras_pml_grid_sample(H, x, k * k, T[i])
+        rp.ras_pml_grid_sample(H, f, 1.0 / fscale, X[i])
+        rp.ras_pml_grid_sample(H, x, k * k / fscale, T[i])
         if (i + 1) % 512 == 0:
             torch.cuda.synchronize()
             print(json.dumps({"phase": "data", "solved": i + 1, "s": round(time.perf_counter() - t0, 1),
@@ -523,7 +530,7 @@ def warmstart(args):
         torch.cuda.synchronize()
         tb_ = time.perf_counter()
         x0 = torch.empty_like(f)
-        u = rp.ras_pml_warm_start(H, net, f, b, x0)
+        u = rp.ras_pml_warm_start(H, net, f, b, x0, fscale)
         rc1, it1, rr1, _ = rp.gmres_solve(H, b, x0, rtol=1e-6, restart=100, maxit=500)
         torch.cuda.synchronize()
         tc = time.perf_counter()
@@ -536,7 +543,9 @@ def warmstart(args):
     out = {
         "phase": "result",
         "workload": "learned warm start: k=320 h=1/640 16x16 subdomains overlap=pml=%d, "
-                    "1-4 Gaussians (width 0.03), GMRES(100) rtol 1e-6, mixed precision" % L,
+                    "1-4 %s, GMRES(100) rtol 1e-6, mixed precision"
+                    % (L, "Gaussians (width 0.03)" if args.ws_source == "gaussian"
+                       else "smoothed point sources (width pi/(4k))"),
         "network": {"levels": 5, "channels": channels, "grid": n, "weights": net.nweights,
                     "dtype": "bf16 weights/activations, fp32 accumulation and Adam"},
         "training": {"pairs": N, "epochs": args.ws_epochs, "batch": Bt, "data_s": round(t_data, 1),

@@ -268,13 +268,15 @@ const char *ras_pml_wsnet_last_error(ras_pml_wsnet_t N);
  * times `scale`, into grid_out (device fp32, grid x grid x 2).            */
 int ras_pml_grid_sample(ras_pml_t H, const void *vec, double scale, float *grid_out, void *stream);
 
-/* Initial guess for gmres_solve / ras_pml_richardson: x0 = network(f on
- * the grid) / k^2 on the grid nodes, 0 elsewhere; kept only if
- * ||b - A x0|| <= ||b||, else x0 = 0.  *used (nullable) = 1 when kept.
- * Single-problem handles whose grid equals the network's.  f, b, x0:
- * device complex128 over the unknowns.  Synchronises `stream`.           */
+/* Initial guess for gmres_solve / ras_pml_richardson: x0 = fscale *
+ * network(f / fscale on the grid) / k^2 on the grid nodes, 0 elsewhere (the
+ * map from f to u is linear: fscale, > 0, is the scale the network was
+ * trained at); kept only if ||b - A x0|| <= ||b||, else x0 = 0.  *used
+ * (nullable) = 1 when kept.  Single-problem handles whose grid equals the
+ * network's.  f, b, x0: device complex128 over the unknowns.  Synchronises
+ * `stream`.                                                               */
 int ras_pml_warm_start(ras_pml_t H, ras_pml_wsnet_t N, const void *f, const void *b, void *x0,
-                       int *used, void *stream);
+                       double fscale, int *used, void *stream);
 
 /* Inspection (tests).  All outputs are HOST memory, complex128.
  *   export_stencil: 4 * n_dofs values: the C, E, N and NE couplings of every

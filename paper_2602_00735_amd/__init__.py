@@ -97,7 +97,7 @@ SYMBOLS = [
     ("ras_pml_wsnet_train_step", _I, [_P, _P, _P, _I, ctypes.c_float, _DP, _P]),
     ("ras_pml_wsnet_last_error", ctypes.c_char_p, [_P]),
     ("ras_pml_grid_sample", _I, [_P, _P, _D, _P, _P]),
-    ("ras_pml_warm_start", _I, [_P, _P, _P, _P, _P, _IP, _P]),
+    ("ras_pml_warm_start", _I, [_P, _P, _P, _P, _P, _D, _IP, _P]),
     ("ras_pml_export_stencil", _I, [_P, _P]),
     ("ras_pml_export_local", _I, [_P, _I, _P]),
     ("ras_pml_export_factor", _I, [_P, _I, _P, _LL]),
@@ -533,13 +533,13 @@ def ras_pml_grid_sample(H: Handle, vec, scale=1.0, out=None, stream=None):
     return out
 
 
-def ras_pml_warm_start(H: Handle, net: WSNet, f, b, x0, stream=None):
+def ras_pml_warm_start(H: Handle, net: WSNet, f, b, x0, fscale=1.0, stream=None):
     """Fills x0 with the network's guess (or zeros); returns whether it was kept."""
     for t, nm in ((f, "f"), (b, "b"), (x0, "x0")):
         _check_vec(t, H.ndof, nm)
     used = ctypes.c_int(0)
-    rc = lib().ras_pml_warm_start(H.ptr, net.ptr, _ptr(f), _ptr(b), _ptr(x0), ctypes.byref(used),
-                                  _stream(stream))
+    rc = lib().ras_pml_warm_start(H.ptr, net.ptr, _ptr(f), _ptr(b), _ptr(x0), float(fscale),
+                                  ctypes.byref(used), _stream(stream))
     if rc:
         H._raise(rc)
     return bool(used.value)

@@ -1172,8 +1172,12 @@ int ras_pml_grid_sample(ras_pml_t H, const void *vec, double scale, float *grid_
 }
 
 int ras_pml_warm_start(ras_pml_t H, ras_pml_wsnet_t N, const void *f, const void *b, void *x0,
-                       int *used, void *stream) {
+                       double fscale, int *used, void *stream) {
     if (!H || !N || !f || !b || !x0 || b == x0 || f == x0) return RAS_EINVAL;
+    if (!(fscale > 0.0) || !std::isfinite(fscale)) {
+        H->last_error = "fscale must be a positive finite number";
+        return RAS_EINVAL;
+    }
     int grid = 0;
     RCHK(single_grid(H, &grid));
     if (grid != wsnet_grid(N)) {
@@ -1185,10 +1189,11 @@ int ras_pml_warm_start(ras_pml_t H, ras_pml_wsnet_t N, const void *f, const void
     double2 *x = static_cast<double2 *>(x0);
     const double2 *bb = static_cast<const double2 *>(b);
     RCHK(ensure_krylov(H, 1));
-    warm_grid_sample(static_cast<const double2 *>(f), D.n1, D.G, grid, 1.0, wsnet_stage(N), st);
+    warm_grid_sample(static_cast<const double2 *>(f), D.n1, D.G, grid, 1.0 / fscale, wsnet_stage(N),
+                     st);
     HCHK(H, hipGetLastError());
     RCHK(wsnet_forward(N, wsnet_stage(N), 1, wsnet_out(N), st));
-    warm_grid_scatter(wsnet_out(N), D.n1, D.G, grid, 1.0 / (D.k * D.k), x, D.ndof, st);
+    warm_grid_scatter(wsnet_out(N), D.n1, D.G, grid, fscale / (D.k * D.k), x, D.ndof, st);
     HCHK(H, hipGetLastError());
     // keep the guess only if its residual is below that of x0 = 0
     RCHK(reduce_sync(H, bb, nullptr, 0, st));

@@ -79,6 +79,15 @@ def warm_draw(seed: int, k: float = 320.0, width: float = 0.03):
     return {"k": float(k), "centres": centres, "amps": mag * np.exp(1j * phase), "width": width}
 
 
+def warm_draw_narrow(seed: int, k: float = 320.0):
+    """``warm_draw`` with the paper's smoothed point source (Section 4) in
+    place of each Gaussian: width pi / (4 k) and peak 16 k^2 / pi^3 times the
+    drawn amplitude."""
+    d = warm_draw(seed, k, width=np.pi / (4.0 * k))
+    d["amps"] = d["amps"] * (16.0 * k * k / np.pi ** 3)
+    return d
+
+
 def ws_init_weights(shapes, seed: int, gain: float = 1.0) -> np.ndarray:
     """Seeded He-normal weights for a list of (cin, cout) 3 x 3 convolutions,
     each W[ky][kx][cin][cout], concatenated as float32."""

@@ -180,6 +180,18 @@ def test_warm_start_guess_and_fallback():
     x0 = torch.ones_like(fd)
     assert rp.ras_pml_warm_start(H, net, fd, bd, x0)
     assert torch.count_nonzero(x0) == 0
+    # the source scale is divided out before the network and multiplied back
+    # after it: with fscale = 2 the guess is 2 * network(f / 2) / k^2
+    net.set_weights(flat)
+    x2 = torch.zeros_like(fd)
+    rp.ras_pml_warm_start(H, net, fd, bd, x2, fscale=2.0)
+    y2, _ = ows.forward(as_dict(flat, CH), fg / 2.0)
+    guess2 = 2.0 * (y2[0, :, :, 0] + 1j * y2[0, :, :, 1]).ravel() / pb.k ** 2
+    x2h = x2.cpu().numpy()
+    if np.any(x2h != 0):
+        assert relerr(x2h[idx], guess2) <= 3e-2
+    with pytest.raises(rp.RasPmlError):
+        rp.ras_pml_warm_start(H, net, fd, bd, x2, fscale=0.0)
     # GMRES from the guess converges to the same tolerance
     net.set_weights(flat)
     x0 = torch.zeros_like(fd)
