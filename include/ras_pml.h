@@ -207,7 +207,9 @@ int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, i
  * (nullable, maxit+1 doubles, host) gets the relative residual of x0 and
  * of every iterate.  Batch handles: as gmres_solve (each problem stops on
  * its own; hist and relres give the worst problem; per problem through
- * ras_pml_batch_result).  Synchronises `stream` after every step.
+ * ras_pml_batch_result).  The stopping test runs on the device; the host
+ * enqueues steps ahead and reads the flags every eight steps (steps
+ * enqueued after a problem stopped skip it).  Synchronises `stream`.
  * Errors: RAS_EINVAL, RAS_ENONFINITE (also when a diverging iteration
  * overflows: *iters then holds the steps taken, *relres = HUGE_VAL),
  * RAS_ENOTCONV, RAS_ENOMEM, RAS_EHIP.                                       */

@@ -47,6 +47,7 @@ void launch_normalize(const DevProb *, int, long long, const KState *, double2 *
                       const double2 *, hipStream_t);
 void launch_start_cycle(const DevProb *, int, long long, const KState *, const double2 *,
                         double2 *, hipStream_t);
+void launch_rich_update(RState *, int *, const double2 *, double *, int, int, double, hipStream_t);
 void launch_givens(KState *, int, int, int, double2 *, double *, double2 *, double2 *, double *,
                    int *, hipStream_t);
 void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, double2 *,
@@ -110,6 +111,10 @@ struct ras_pml_handle {
     double *d_cs = nullptr, *d_hist = nullptr;
     KState *d_ks = nullptr;
     int *d_active = nullptr;
+    // fixed-point iteration: per-problem state and residual histories
+    RState *d_rs = nullptr, *h_rs = nullptr;      // h_rs pinned
+    double *d_rhist = nullptr;
+    int rhist_cap = -1;                            // maxit the history holds
     double2 *d_partials = nullptr, *d_redout = nullptr;
     unsigned int *d_counters = nullptr;
     // fused Arnoldi step (cooperative launch); E = 0 selects the
@@ -240,9 +245,10 @@ ras_pml_handle::~ras_pml_handle() {
     void *ptrs[] = {d_probs, d_subs,  d_order, d_lu_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
-                    d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err};
+                    d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err, d_rs, d_rhist};
     for (void *p : ptrs) dfree(p);
     if (h_ks) (void)hipHostFree(h_ks);
+    if (h_rs) (void)hipHostFree(h_rs);
     if (h_red) (void)hipHostFree(h_red);
     if (h_err) (void)hipHostFree(h_err);
     for (int c = 0; c < C_NCAT; ++c)
@@ -742,11 +748,26 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
 // Algorithm 1 as an iteration: x <- x + B^{-1} (b - A x) for every problem
 // not yet converged.  The correction is summed straight into x (the PoU sum
 // in accumulate mode), so a step is one batched solve, one sum, one
-// residual and one reduction.  The host reads the norms after every step.
+// residual and one reduction.  The stopping test runs on the device
+// (k_rich_update clears a finished problem's active flag, which every later
+// launch reads); the host enqueues steps ahead and looks at the flags every
+// kSyncSteps steps.
 int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int maxit,
                     int *iters, double *relres, double *hist, hipStream_t st) {
+    constexpr int kSyncSteps = 8;
     const int P = H->nprob;
     RCHK(ensure_krylov(H, 1));
+    if (!H->d_rs) {
+        RCHK(dalloc(H, &H->d_rs, sizeof(RState) * P));
+        HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_rs), sizeof(RState) * P));
+    }
+    if (H->rhist_cap < maxit) {
+        dfree(H->d_rhist);
+        H->d_rhist = nullptr;
+        H->rhist_cap = -1;
+        RCHK(dalloc(H, &H->d_rhist, sizeof(double) * static_cast<size_t>(P) * (maxit + 1)));
+        H->rhist_cap = maxit;
+    }
     H->res_iters.assign(P, 0);
     H->res_relres.assign(P, 0.0);
     H->res_conv.assign(P, 0);
@@ -764,48 +785,71 @@ int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol
             HCHK(H, hipMemsetAsync(x + D.dof_off, 0, sizeof(double2) * D.ndof, st));
         }
     }
-    // residual r = b - A x of the problems in `act` (nullptr: all), its norms
-    // into relres and the stopping test into need
-    auto residual = [&](const int *act) -> int {
-        launch_spmv(H->d_probs, P, H->max_ndof, act, H->d_coef, H->ntot, x, b, H->d_r, st);
-        HCHK(H, hipGetLastError());
-        RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
-        for (int p = 0; p < P; ++p) {
-            if (act != nullptr && !need[p]) continue;
-            const double beta = std::sqrt(H->h_red[p].x);
-            if (!std::isfinite(beta)) {
-                H->last_error = "iterate is not finite";
-                return RAS_ENONFINITE;
-            }
-            H->res_relres[p] = bnorm[p] > 0.0 ? beta / bnorm[p] : 0.0;
-            need[p] = (bnorm[p] > 0.0 && beta > rtol * bnorm[p]) ? 1 : 0;
-            H->res_conv[p] = need[p] ? 0 : 1;
-        }
-        return RAS_OK;
-    };
-    RCHK(residual(nullptr));
-    int it = 0;
-    if (hist) hist[0] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    launch_spmv(H->d_probs, P, H->max_ndof, nullptr, H->d_coef, H->ntot, x, b, H->d_r, st);
+    HCHK(H, hipGetLastError());
+    RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
+    std::vector<double> rel0(P);
     int nneed = 0;
-    for (int p = 0; p < P; ++p) nneed += need[p];
-    while (nneed > 0 && it < maxit) {
-        HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
-        RCHK(do_apply(H, H->d_r, x, H->d_active, st, true));
-        for (int p = 0; p < P; ++p) H->res_iters[p] += need[p];
-        ++it;
-        // the residual of the stepped problems only; r of the others is kept
-        const int rc = residual(H->d_active);
-        if (rc != RAS_OK) {       // a diverging iteration overflows: report how far it got
-            if (iters) *iters = it;
-            if (relres) *relres = HUGE_VAL;
-            return rc;
+    for (int p = 0; p < P; ++p) {
+        const double beta = std::sqrt(H->h_red[p].x);
+        if (!std::isfinite(beta)) {
+            H->last_error = "initial residual is not finite";
+            return RAS_ENONFINITE;
         }
-        if (hist) hist[it] = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+        rel0[p] = bnorm[p] > 0.0 ? beta / bnorm[p] : 0.0;
+        need[p] = (bnorm[p] > 0.0 && beta > rtol * bnorm[p] && maxit > 0) ? 1 : 0;
+        nneed += need[p];
+        H->h_rs[p] = RState{bnorm[p] > 0.0 ? bnorm[p] : 1.0, rel0[p], 0, 0};
+    }
+    HCHK(H, hipMemcpyAsync(H->d_rs, H->h_rs, sizeof(RState) * P, hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    for (int it = 1; nneed > 0 && it <= maxit; ++it) {
+        RCHK(do_apply(H, H->d_r, x, H->d_active, st, true));
+        launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, H->ntot, x, b, H->d_r, st);
+        launch_reduce(H->d_probs, P, nullptr, H->d_r, nullptr, 0, H->d_redout, H->d_partials,
+                      H->d_counters, st);
+        launch_rich_update(H->d_rs, H->d_active, H->d_redout, H->d_rhist, P, maxit, rtol, st);
+        HCHK(H, hipGetLastError());
+        if (it % kSyncSteps != 0 && it != maxit) continue;
+        HCHK(H, hipMemcpyAsync(need.data(), H->d_active, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+        HCHK(H, hipStreamSynchronize(st));
         nneed = 0;
         for (int p = 0; p < P; ++p) nneed += need[p];
     }
-    if (iters) *iters = it;
+    // per-problem outcome and histories
+    HCHK(H, hipMemcpyAsync(H->h_rs, H->d_rs, sizeof(RState) * P, hipMemcpyDeviceToHost, st));
+    int steps = 0;
+    HCHK(H, hipStreamSynchronize(st));
+    bool nonfinite = false;
+    for (int p = 0; p < P; ++p) {
+        const RState &R = H->h_rs[p];
+        H->res_iters[p] = R.iters;
+        H->res_relres[p] = R.nonfinite ? HUGE_VAL : R.relres;
+        H->res_conv[p] = (!R.nonfinite && R.relres <= rtol) || bnorm[p] == 0.0 ? 1 : 0;
+        nonfinite = nonfinite || R.nonfinite;
+        steps = std::max(steps, R.iters);
+    }
+    if (hist) {
+        std::vector<double> rh(static_cast<size_t>(P) * (maxit + 1));
+        if (steps > 0)
+            HCHK(H, hipMemcpy(rh.data(), H->d_rhist, sizeof(double) * rh.size(),
+                              hipMemcpyDeviceToHost));
+        for (int t = 0; t <= steps; ++t) {
+            double worst = 0.0;
+            for (int p = 0; p < P; ++p) {
+                const int tp = std::min(t, H->res_iters[p]);
+                const double v = tp == 0 ? rel0[p] : rh[static_cast<size_t>(p) * (maxit + 1) + tp];
+                worst = std::max(worst, v);
+            }
+            hist[t] = worst;
+        }
+    }
+    if (iters) *iters = steps;
     if (relres) *relres = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    if (nonfinite) {                   // a diverging iteration overflows
+        H->last_error = "iterate is not finite";
+        return RAS_ENONFINITE;
+    }
     for (int p = 0; p < P; ++p)
         if (!H->res_conv[p]) {
             H->last_error = "maximum number of iterations reached";

@@ -74,6 +74,14 @@ struct KState {
     int pad_;
 };
 
+// Per-problem state of the fixed-point iteration kept on the device.
+struct RState {
+    double bnorm;      // ||b||
+    double relres;     // ||b - A x|| / ||b|| of the current iterate
+    int iters;         // steps taken
+    int nonfinite;     // the residual stopped being finite
+};
+
 // One block of the fused Arnoldi-step kernel: a contiguous slice of one
 // problem's unknowns.
 struct ArnoldiBlock {

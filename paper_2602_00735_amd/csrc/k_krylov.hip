@@ -304,6 +304,27 @@ __global__ void k_update_x(const DevProb *__restrict__ probs, const KState *__re
     st(x, g, acc);
 }
 
+// ---------------------------------------------------------------- fixed point
+// After one step of the fixed-point iteration: for every problem that took
+// it, the residual norm (from the reduction) becomes its relative residual,
+// history entry `iters` and stopping test; a stopped problem's active flag
+// is cleared, so later steps enqueued ahead of the host's check skip it.
+__global__ void k_rich_update(RState *__restrict__ rs, int *__restrict__ active,
+                              const double2 *__restrict__ red, double *__restrict__ hist,
+                              int nprob, int maxit, double rtol) {
+    for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
+        if (!active[p]) continue;
+        RState R = rs[p];
+        const double beta = sqrt(red[p].x);
+        R.iters += 1;
+        R.relres = beta / R.bnorm;
+        hist[static_cast<long long>(p) * (maxit + 1) + R.iters] = R.relres;
+        if (!isfinite(beta)) R.nonfinite = 1;
+        if (R.nonfinite || R.relres <= rtol || R.iters >= maxit) active[p] = 0;
+        rs[p] = R;
+    }
+}
+
 // ---------------------------------------------------------------- fused step
 // Values exchanged between blocks inside one launch (partial sums) are
 // written and read with device-scope atomic accesses, which are coherent
@@ -518,6 +539,12 @@ void launch_start_cycle(const DevProb *probs, int nprob, long long max_ndof, con
                         const double2 *r, double2 *v0, hipStream_t s) {
     dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
     hipLaunchKernelGGL(k_start_cycle, grid, dim3(256), 0, s, probs, ks, r, v0);
+}
+
+void launch_rich_update(RState *rs, int *active, const double2 *red, double *hist, int nprob,
+                        int maxit, double rtol, hipStream_t s) {
+    hipLaunchKernelGGL(k_rich_update, dim3(1), dim3(64), 0, s, rs, active, red, hist, nprob, maxit,
+                       rtol);
 }
 
 void launch_givens(KState *ks, int nprob, int j, int m, double2 *H, double *cs, double2 *sn,
