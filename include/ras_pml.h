@@ -221,8 +221,8 @@ int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int max
 int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged);
 
 /* ------------------------------------------------------------------------
- * Learned warm start (the north-star's learned initial guess; not part of
- * the paper's method).  A convolutional encoder-decoder maps the source,
+ * Learned warm start (a learned initial guess for the solvers; an addition
+ * to the paper's method).  A convolutional encoder-decoder maps the source,
  * sampled on the grid x grid nodes of the interior box (node (G + gx,
  * G + gy) for gx, gy in [0, grid), x_i = (i - G) h), to k^2 times a guess
  * of the solution on the same nodes; the guess is zero elsewhere.  Five
