@@ -96,8 +96,8 @@ def main():
                     help="only run a plain device copy of known size (PMC traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole hot path on a single "
-              "MI355X (multi-GPU sharding is a design note, not implemented); use --gpus 1",
+        print("bench.py measures one GPU only: the library runs the whole hot path on a single "
+              "MI355X (sharding across GPUs is designed, not implemented); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
