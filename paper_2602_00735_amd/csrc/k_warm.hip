@@ -44,30 +44,34 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
                                                  int creal) {
     constexpr int CPout = 16 * NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int M = B * H * W;                // < 2^31 (checked by the launcher)
+    const int M = B * H * W;                // M * 64 < 2^31 (checked at creation)
     const int p0 = (blockIdx.x * 4 + wave) * 16;
     if (p0 >= M) return;                    // no barrier in this kernel
     const int i = lane & 15, kq = lane >> 4;
     const int p = p0 + i;
     const bool pin = p < M;
     const int pc = pin ? p : M - 1;
-    const int x = pc % W, y = (pc / W) % H, b = pc / (W * H);
+    const int x = pc % W, y = (pc / W) % H;
+    // border flags of the pixel, then each tap is a uniform offset from it
+    const bool xlo = x > 0, xhi = x < W - 1, ylo = y > 0, yhi = y < H - 1;
+    const bf16 *xc = X + pc * CPin + 4 * kq;
     v4f c[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) c[t] = v4f{0.f, 0.f, 0.f, 0.f};
     const int KC = CPin >> 4;
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-        const bool ok = pin && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const long long q = ok ? (static_cast<long long>(b) * H + yy) * W + xx : 0;
-        const bf16 *xr = X + q * CPin + 4 * kq;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const bool ok = pin && (dy < 0 ? ylo : (dy > 0 ? yhi : true)) &&
+                        (dx < 0 ? xlo : (dx > 0 ? xhi : true));
+        const bf16 *xr = xc + (ok ? (dy * W + dx) * CPin : 0);
+        const bf16 *wb = Wp + tap * KC * NT * 256 + i * 16 + 4 * kq;
         for (int kc = 0; kc < KC; ++kc) {
             v4s a = *reinterpret_cast<const v4s *>(xr + 16 * kc);
             if (!ok) a = v4s{0, 0, 0, 0};
-            const bf16 *wb = Wp + static_cast<long long>((tap * KC + kc) * NT) * 256 + i * 16 + 4 * kq;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const v4s bb = *reinterpret_cast<const v4s *>(wb + t * 256);
+                const v4s bb = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
                 c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, c[t], 0, 0, 0);
             }
         }
@@ -77,8 +81,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const long long po = p0 + 4 * kq + r;
-            if (po >= static_cast<long long>(M)) continue;
+            const int po = p0 + 4 * kq + r;
+            if (po >= M) continue;
             float v = c[t][r];
             if (relu) v = fmaxf(v, 0.f);
             const int ch = 16 * t + i;
@@ -185,6 +189,83 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ 
                 pw[(tap * CPin + ci) * CPout + co] = c[s][t][r];
             }
     }
+}
+
+// The weight gradient for 16 input channels and W divisible by 4: a lane's
+// four pixels then lie in one image row, so for each kernel row the six
+// input values x-1 .. x+4 serve the three horizontal taps (6 loads instead
+// of 12), and each wave takes all nine taps for its own pixels (no output
+// gradient is loaded twice).  Every wave writes its own partial sums:
+//   part[4 blk + wave][tap][ci][co].
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restrict__ X,
+                                                           const bf16 *__restrict__ dZ,
+                                                           float *__restrict__ part, int B, int H,
+                                                           int W, int chunk) {
+    constexpr int CPin = 16, CPout = 16 * NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int M = B * H * W;                   // a multiple of 4, as is every chunk bound
+    const int c0 = blockIdx.x * chunk;
+    const int c1 = min(c0 + chunk, M);
+    v4f c[9][NT];
+#pragma unroll
+    for (int s = 0; s < 9; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    int p = c0 + 16 * wave + 4 * kq;           // first of the lane's four pixels
+    const int q0 = min(p, M - 4);
+    int x = q0 % W, y = (q0 / W) % H, b = q0 / (W * H);
+    for (; p - 4 * kq < c1; p += 64) {
+        const bool pv = p < c1;                // then p + 3 < c1 too
+        v4s bz[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+            {
+                const short z = static_cast<short>(dZ[static_cast<long long>(pv ? p + e : 0) * CPout + 16 * t + i]);
+                bz[t][e] = pv ? z : short(0);
+            }
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = y + dy;
+            const bool rok = pv && yy >= 0 && yy < H;
+            const int row = (b * H + (rok ? yy : 0)) * W;
+            short v[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int xx = x - 1 + k;
+                const bool ok = rok && xx >= 0 && xx < W;
+                const short u = static_cast<short>(X[static_cast<long long>(ok ? row + xx : 0) * CPin + i]);
+                v[k] = ok ? u : short(0);
+            }
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const v4s a = v4s{v[dx], v[dx + 1], v[dx + 2], v[dx + 3]};
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    c[3 * (dy + 1) + dx][t] =
+                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[3 * (dy + 1) + dx][t], 0, 0, 0);
+            }
+        }
+        x += 64;                               // next step: 64 pixels on
+        while (x >= W) {
+            x -= W;
+            if (++y == H) {
+                y = 0;
+                ++b;
+            }
+        }
+    }
+    float *pw = part + (static_cast<long long>(blockIdx.x) * 4 + wave) * 9 * CPin * CPout;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = c[tap][t][r];
 }
 
 // dZ = dY where the forward output G is positive (a post-ReLU value is
@@ -429,6 +510,17 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int
     int chunk = 0;
     const int nblk = warm_wgrad_blocks(M, &chunk);
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
+    const int n = 9 * CPin * CPout;
+    if (CPin == 16 && CPout <= 32 && W % 4 == 0) {     // per-wave partials: 4 per block
+        if (CPout == 16)
+            hipLaunchKernelGGL(k_conv3x3_wgrad_k16<1>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
+                               W, chunk);
+        else
+            hipLaunchKernelGGL(k_conv3x3_wgrad_k16<2>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
+                               W, chunk);
+        hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, 4 * nblk, n, g);
+        return;
+    }
 #define RAS_WG(NT, KC)                                                                           \
     hipLaunchKernelGGL((k_conv3x3_wgrad<NT, KC>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H, \
                        W, chunk)
@@ -446,7 +538,6 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int
         RAS_WG_KC(4);
 #undef RAS_WG_KC
 #undef RAS_WG
-    const int n = 9 * CPin * CPout;
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, nblk, n, g);
 }
 

@@ -224,7 +224,8 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
         const int S = grid >> lvl[L];
         const long long M = static_cast<long long>(batch_max) * S * S;
         const long long nblk = std::min(1024LL, (M + 255) / 256);
-        part_max = std::max(part_max, static_cast<size_t>(nblk) * np);
+        // 16 input channels: four partial sums per block (one per wave)
+        part_max = std::max(part_max, static_cast<size_t>(nblk) * np * (N->cip(L) == 16 ? 4 : 1));
     }
     auto act = [&](void **ptr, int l, int C) {
         const size_t S = static_cast<size_t>(grid >> l);
