@@ -472,8 +472,8 @@ def warmstart(args):
     # and its algorithmic HBM bytes: every convolution reads its input and
     # writes its output (bf16, channels padded to 16), the input gradient
     # reads the masked output gradient and writes the input gradient, the
-    # weight gradient reads input and masked gradient, the mask reads the
-    # gradient and the activation and writes the masked gradient
+    # weight gradient reads input and masked gradient, and the kernel that
+    # writes a masked gradient reads the activation for its ReLU mask
     lv = (0, 1, 2, 3, 4, 3, 2, 1, 0, 0)
     cp = lambda c: (c + 15) // 16 * 16
     flops = nbytes = 0.0
@@ -481,7 +481,7 @@ def warmstart(args):
         m = Bt * (n >> lv[li]) ** 2
         flops += (3 if li > 0 else 2) * 2.0 * m * 9 * ci * co
         a, b = 2.0 * m * cp(ci), 2.0 * m * cp(co)
-        nbytes += (a + b) * (3 if li > 0 else 2) + (3 * b if li < 9 else 0)
+        nbytes += (a + b) * (3 if li > 0 else 2) + (b if li < 9 else 0)
     t0 = time.perf_counter()
     step_times = []
     for ep in range(args.ws_epochs):

@@ -9,9 +9,10 @@
 //     A operand is gathered straight from the input tensor (4 channels of
 //     one pixel per lane, one 8-byte load), the B operand from weights
 //     packed per (tap, channel block, column tile) as 16 x 16 blocks;
-//     the input gradient is the same kernel on the output gradient (after
-//     the ReLU mask, applied once per layer) with the taps flipped and the
-//     channel roles swapped;
+//     the input gradient is the same kernel on the output gradient with
+//     the taps flipped and the channel roles swapped (every gradient is
+//     written already multiplied by the ReLU mask of its tensor, by the
+//     kernel that produces it);
 //   weight gradient: rows = (tap, input channel), columns = output
 //     channels, K = pixels, split over workgroups in fixed chunks; every
 //     workgroup writes its partial sums and a second kernel adds them in a
@@ -36,12 +37,15 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
 }
 // out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
 // NT: output channel tiles.  OUT_F32: write the first `creal` channels as
-// fp32 (the network's head).
+// fp32 (the network's head).  gate (nullable, shaped as the output): values
+// are kept only where the gate is positive (the ReLU mask of the tensor
+// whose gradient this is; a post-ReLU value is positive exactly when its
+// bits are non-zero).
 template <int NT, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
                                                  const bf16 *__restrict__ Wp, void *__restrict__ Y,
-                                                 int B, int H, int W, int CPin, int relu, int acc,
-                                                 int creal) {
+                                                 const bf16 *__restrict__ gate, int B, int H, int W,
+                                                 int CPin, int relu, int acc, int creal) {
     constexpr int CPout = 16 * NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int M = B * H * W;                // M * 64 < 2^31 (checked at creation)
@@ -91,6 +95,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
             } else {
                 bf16 *yb = static_cast<bf16 *>(Y) + po * CPout + ch;
                 if (acc) v += bf2f(*yb);
+                if (gate != nullptr && gate[po * CPout + ch] == 0) v = 0.f;
                 *yb = f2bf(v);
             }
         }
@@ -268,15 +273,6 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restric
                 pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = c[tap][t][r];
 }
 
-// dZ = dY where the forward output G is positive (a post-ReLU value is
-// positive exactly when its bits are non-zero), else 0.
-__global__ void k_gate(const bf16 *__restrict__ dY, const bf16 *__restrict__ G,
-                       bf16 *__restrict__ dZ, long long n) {
-    const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (o >= n) return;
-    dZ[o] = G[o] != 0 ? dY[o] : bf16(0);
-}
-
 // g[idx] = sum over blocks of part[blk][idx]: 32 slices of the blocks are
 // summed in order by 32 threads, then the slice sums in slice order
 // (the same order at every launch: deterministic).
@@ -313,9 +309,11 @@ __global__ void k_pool2(const bf16 *__restrict__ X, bf16 *__restrict__ Y, int B,
     Y[o] = f2bf(0.25f * s);
 }
 
-// dX (B, H, W, C) = dY (B, H/2, W/2, C) / 4 spread over each block, plus `add`.
+// dX (B, H, W, C) = dY (B, H/2, W/2, C) / 4 spread over each block, plus
+// `add`, kept where `gate` (nullable) is positive.
 __global__ void k_pool2_bwd(const bf16 *__restrict__ dY, const bf16 *__restrict__ add,
-                            bf16 *__restrict__ dX, int B, int H, int W, int C) {
+                            const bf16 *__restrict__ gate, bf16 *__restrict__ dX, int B, int H,
+                            int W, int C) {
     const long long n = static_cast<long long>(B) * H * W * C;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
@@ -325,6 +323,7 @@ __global__ void k_pool2_bwd(const bf16 *__restrict__ dY, const bf16 *__restrict_
     const long long b = pix / (static_cast<long long>(W) * H);
     float v = 0.25f * bf2f(dY[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
     if (add != nullptr) v += bf2f(add[o]);
+    if (gate != nullptr && gate[o] == 0) v = 0.f;
     dX[o] = f2bf(v);
 }
 
@@ -342,9 +341,10 @@ __global__ void k_up2_add(const bf16 *__restrict__ Yc, const bf16 *__restrict__ 
     S[o] = f2bf(v);
 }
 
-// dYc (B, H/2, W/2, C) = sum of dS over each 2 x 2 block.
-__global__ void k_up2_bwd(const bf16 *__restrict__ dS, bf16 *__restrict__ dYc, int B, int H, int W,
-                          int C) {
+// dYc (B, H/2, W/2, C) = sum of dS over each 2 x 2 block, kept where `gate`
+// (nullable, shaped as dYc) is positive.
+__global__ void k_up2_bwd(const bf16 *__restrict__ dS, const bf16 *__restrict__ gate,
+                          bf16 *__restrict__ dYc, int B, int H, int W, int C) {
     const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
@@ -353,8 +353,9 @@ __global__ void k_up2_bwd(const bf16 *__restrict__ dS, bf16 *__restrict__ dYc, i
     const int x = static_cast<int>(pix % (W / 2)), y = static_cast<int>((pix / (W / 2)) % (H / 2));
     const long long b = pix / (static_cast<long long>(W / 2) * (H / 2));
     const long long base = ((b * H + 2 * y) * W + 2 * x) * C + c;
-    const float s = bf2f(dS[base]) + bf2f(dS[base + C]) + bf2f(dS[base + static_cast<long long>(W) * C]) +
-                    bf2f(dS[base + static_cast<long long>(W) * C + C]);
+    float s = bf2f(dS[base]) + bf2f(dS[base + C]) + bf2f(dS[base + static_cast<long long>(W) * C]) +
+              bf2f(dS[base + static_cast<long long>(W) * C + C]);
+    if (gate != nullptr && gate[o] == 0) s = 0.f;
     dYc[o] = f2bf(s);
 }
 
@@ -476,13 +477,14 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 
 // ---------------------------------------------------------------- launchers
 // B * H * W < 2^31 (the network object checks it at creation).
-void warm_conv(const void *X, const void *Wp, void *Y, int B, int H, int W, int CPin, int CPout,
-               bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
+void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
+               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
     const dim3 grid(blocks(M, 64)), blk(256);
-    const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp);
+    const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
+               *g = static_cast<const bf16 *>(gate);
 #define RAS_CONV(NT, F32)                                                                        \
-    hipLaunchKernelGGL((k_conv3x3<NT, F32>), grid, blk, 0, s, x, w, Y, B, H, W, CPin,           \
+    hipLaunchKernelGGL((k_conv3x3<NT, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W, CPin,        \
                        relu ? 1 : 0, acc ? 1 : 0, creal)
     if (out_f32) {
         RAS_CONV(1, true);
@@ -541,32 +543,29 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, nblk, n, g);
 }
 
-void warm_gate(const void *dY, const void *G, void *dZ, long long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_gate, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(dY),
-                       static_cast<const bf16 *>(G), static_cast<bf16 *>(dZ), n);
-}
 
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s) {
     const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
     hipLaunchKernelGGL(k_pool2, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(X),
                        static_cast<bf16 *>(Y), B, H, W, C);
 }
-void warm_pool_bwd(const void *dY, const void *add, void *dX, int B, int H, int W, int C,
-                   hipStream_t s) {
+void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
+                   int W, int C, hipStream_t s) {
     const long long n = static_cast<long long>(B) * H * W * C;
     hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks(n, 256)), dim3(256), 0, s,
                        static_cast<const bf16 *>(dY), static_cast<const bf16 *>(add),
-                       static_cast<bf16 *>(dX), B, H, W, C);
+                       static_cast<const bf16 *>(gate), static_cast<bf16 *>(dX), B, H, W, C);
 }
 void warm_up_add(const void *Yc, const void *E, void *S, int B, int H, int W, int C, hipStream_t s) {
     const long long n = static_cast<long long>(B) * H * W * C;
     hipLaunchKernelGGL(k_up2_add, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(Yc),
                        static_cast<const bf16 *>(E), static_cast<bf16 *>(S), B, H, W, C);
 }
-void warm_up_bwd(const void *dS, void *dYc, int B, int H, int W, int C, hipStream_t s) {
+void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int W, int C,
+                 hipStream_t s) {
     const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
     hipLaunchKernelGGL(k_up2_bwd, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(dS),
-                       static_cast<bf16 *>(dYc), B, H, W, C);
+                       static_cast<const bf16 *>(gate), static_cast<bf16 *>(dYc), B, H, W, C);
 }
 void warm_pack_input(const float *x, void *X, long long npix, hipStream_t s) {
     hipLaunchKernelGGL(k_pack_input, dim3(blocks(npix * 16, 256)), dim3(256), 0, s, x,

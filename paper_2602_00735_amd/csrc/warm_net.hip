@@ -30,17 +30,17 @@
 
 namespace raspml {
 
-void warm_conv(const void *X, const void *Wp, void *Y, int B, int H, int W, int CPin, int CPout,
-               bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
+void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
+               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
 int warm_wgrad_blocks(long long M, int *chunk);
 void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int H, int W,
                 int CPin, int CPout, hipStream_t s);
-void warm_gate(const void *dY, const void *G, void *dZ, long long n, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
-void warm_pool_bwd(const void *dY, const void *add, void *dX, int B, int H, int W, int C,
-                   hipStream_t s);
+void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
+                   int W, int C, hipStream_t s);
 void warm_up_add(const void *Yc, const void *E, void *S, int B, int H, int W, int C, hipStream_t s);
-void warm_up_bwd(const void *dS, void *dYc, int B, int H, int W, int C, hipStream_t s);
+void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int W, int C,
+                 hipStream_t s);
 void warm_pack_input(const float *x, void *X, long long npix, hipStream_t s);
 void warm_mse(const float *y, const float *t, long long npix, double *partial, int nblk, void *dY,
               double *loss, hipStream_t s);
@@ -68,8 +68,8 @@ struct ras_pml_wsnet {
     float *w[kLayers] = {}, *m[kLayers] = {}, *v[kLayers] = {}, *g[kLayers] = {};
     void *wf[kLayers] = {}, *wb[kLayers] = {};
     void *xin = nullptr, *e[5] = {}, *p[5] = {}, *s[4] = {}, *d[4] = {};
-    void *gy = nullptr, *ge[5] = {}, *gp[5] = {}, *gs[4] = {}, *gd[4] = {};
-    void *dz = nullptr;                 // an output gradient after the ReLU mask
+    void *gy = nullptr, *gp[5] = {}, *gs[4] = {};
+    void *dz = nullptr;                 // the current layer's output gradient, ReLU-masked
     float *y = nullptr, *stage = nullptr;
     float *part = nullptr;
     double *lpart = nullptr, *loss = nullptr;
@@ -101,11 +101,11 @@ int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream
     const int G = N->grid;
     const int C[5] = {cp16(N->ch[0]), cp16(N->ch[1]), cp16(N->ch[2]), cp16(N->ch[3]), cp16(N->ch[4])};
     warm_pack_input(x, N->xin, static_cast<long long>(B) * G * G, st);
-    warm_conv(N->xin, N->wf[0], N->e[0], B, G, G, 16, C[0], true, false, false, 0, st);
+    warm_conv(N->xin, N->wf[0], N->e[0], nullptr, B, G, G, 16, C[0], true, false, false, 0, st);
     for (int l = 1; l <= 4; ++l) {
         const int S = N->side(l);
         warm_pool(N->e[l - 1], N->p[l], B, 2 * S, 2 * S, C[l - 1], st);
-        warm_conv(N->p[l], N->wf[l], N->e[l], B, S, S, C[l - 1], C[l], true, false, false, 0,
+        warm_conv(N->p[l], N->wf[l], N->e[l], nullptr, B, S, S, C[l - 1], C[l], true, false, false, 0,
                   st);
     }
     // decoder: layer index 5 + (3 - l) for level l = 3..0
@@ -115,11 +115,11 @@ int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream
     for (int l = 3; l >= 0; --l) {
         const int S = N->side(l), L = 5 + (3 - l);
         warm_up_add(prev, N->e[l], N->s[l], B, S, S, din[l], st);
-        warm_conv(N->s[l], N->wf[L], N->d[l], B, S, S, din[l], dout[l], true, false, false, 0,
+        warm_conv(N->s[l], N->wf[L], N->d[l], nullptr, B, S, S, din[l], dout[l], true, false, false, 0,
                   st);
         prev = N->d[l];
     }
-    warm_conv(N->d[0], N->wf[9], out, B, G, G, C[0], 16, false, false, true, 2, st);
+    warm_conv(N->d[0], N->wf[9], out, nullptr, B, G, G, C[0], 16, false, false, true, 2, st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -130,29 +130,31 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     const int C[5] = {cp16(N->ch[0]), cp16(N->ch[1]), cp16(N->ch[2]), cp16(N->ch[3]), cp16(N->ch[4])};
     RCHK(wsnet_forward(N, x, B, N->y, st));
     warm_mse(N->y, t, static_cast<long long>(B) * G * G, N->lpart, kMseBlocks, N->gy, N->loss, st);
-    // head (no ReLU)
+    // Every gradient is written already multiplied by the ReLU mask of the
+    // tensor it belongs to, into dz, which the next layer's weight gradient
+    // and input gradient then read.
+    // head (no ReLU): gradient of d0
     warm_wgrad(N->d[0], N->gy, N->part, N->g[9], B, G, G, C[0], 16, st);
-    warm_conv(N->gy, N->wb[9], N->gd[0], B, G, G, 16, C[0], false, false, false, 0, st);
+    warm_conv(N->gy, N->wb[9], N->dz, N->d[0], B, G, G, 16, C[0], false, false, false, 0, st);
     // decoder, level 0 up to 3
     const int din[4] = {C[0], C[1], C[2], C[3]};
     const int dout[4] = {C[0], C[0], C[1], C[2]};
     for (int l = 0; l <= 3; ++l) {
         const int S = N->side(l), L = 5 + (3 - l);
-        warm_gate(N->gd[l], N->d[l], N->dz, static_cast<long long>(B) * S * S * dout[l], st);
         warm_wgrad(N->s[l], N->dz, N->part, N->g[L], B, S, S, din[l], dout[l], st);
-        warm_conv(N->dz, N->wb[L], N->gs[l], B, S, S, dout[l], din[l], false, false, false, 0, st);
-        void *below = l < 3 ? N->gd[l + 1] : N->ge[4];
-        warm_up_bwd(N->gs[l], below, B, S, S, din[l], st);
+        warm_conv(N->dz, N->wb[L], N->gs[l], nullptr, B, S, S, dout[l], din[l], false, false, false, 0,
+                  st);
+        const void *below = l < 3 ? N->d[l + 1] : N->e[4];   // the tensor one level down
+        warm_up_bwd(N->gs[l], below, N->dz, B, S, S, din[l], st);
     }
     // encoder, level 4 down to 1; the skip gradient of s_{l-1} joins e_{l-1}
     for (int l = 4; l >= 1; --l) {
         const int S = N->side(l);
-        warm_gate(N->ge[l], N->e[l], N->dz, static_cast<long long>(B) * S * S * C[l], st);
         warm_wgrad(N->p[l], N->dz, N->part, N->g[l], B, S, S, C[l - 1], C[l], st);
-        warm_conv(N->dz, N->wb[l], N->gp[l], B, S, S, C[l], C[l - 1], false, false, false, 0, st);
-        warm_pool_bwd(N->gp[l], N->gs[l - 1], N->ge[l - 1], B, 2 * S, 2 * S, C[l - 1], st);
+        warm_conv(N->dz, N->wb[l], N->gp[l], nullptr, B, S, S, C[l], C[l - 1], false, false, false, 0,
+                  st);
+        warm_pool_bwd(N->gp[l], N->gs[l - 1], N->e[l - 1], N->dz, B, 2 * S, 2 * S, C[l - 1], st);
     }
-    warm_gate(N->ge[0], N->e[0], N->dz, static_cast<long long>(B) * G * G * C[0], st);
     warm_wgrad(N->xin, N->dz, N->part, N->g[0], B, G, G, 16, C[0], st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
@@ -232,13 +234,12 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
         return N->alloc(ptr, static_cast<size_t>(batch_max) * S * S * cp16(C) * 2);
     };
     bool ok = act(&N->xin, 0, 16) && act(&N->gy, 0, 16);
-    for (int l = 0; l < 5 && ok; ++l) ok = act(&N->e[l], l, c[l]) && act(&N->ge[l], l, c[l]);
+    for (int l = 0; l < 5 && ok; ++l) ok = act(&N->e[l], l, c[l]);
     for (int l = 1; l < 5 && ok; ++l) ok = act(&N->p[l], l, c[l - 1]) && act(&N->gp[l], l, c[l - 1]);
     const int dch[4] = {c[0], c[0], c[1], c[2]};
     for (int l = 0; l < 4 && ok; ++l)
-        ok = act(&N->s[l], l, c[l]) && act(&N->gs[l], l, c[l]) && act(&N->d[l], l, dch[l]) &&
-             act(&N->gd[l], l, dch[l]);
-    // the masked gradient: the largest of the gated tensors (e_l, d_l)
+        ok = act(&N->s[l], l, c[l]) && act(&N->gs[l], l, c[l]) && act(&N->d[l], l, dch[l]);
+    // the masked gradient: the largest of the tensors it stands for (e_l, d_l)
     size_t dz_max = 0;
     for (int l = 0; l < 5; ++l) {
         const size_t S = static_cast<size_t>(grid >> l);
