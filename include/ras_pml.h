@@ -198,6 +198,15 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream);
 int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, int maxit,
                 int *iters, double *relres, double *hist, void *stream);
 
+/* gmres_solve for a batch handle with one tolerance per problem: rtol,
+ * iters and relres are host arrays of ras_pml_num_problems values (iters
+ * and relres nullable: the steps and final true relative residual of each
+ * problem); hist as for gmres_solve (the worst problem after each step).
+ * Errors as gmres_solve; RAS_ENOTCONV when some problem missed its
+ * tolerance.                                                              */
+int gmres_solve_batch(ras_pml_t H, const void *b, void *x, const double *rtol, int restart,
+                      int maxit, int *iters, double *relres, double *hist, void *stream);
+
 /* Algorithm 1 (Section 2) as a solver: the fixed-point iteration
  * x <- x + B^{-1} (b - A x), every step one batched local solve and the
  * PoU-weighted sum added into x, the residual in complex128.  x holds x0 on

@@ -83,6 +83,7 @@ SYMBOLS = [
     ("ras_pml_apply", _I, [_P, _P, _P, _P]),
     ("ras_pml_local_solve", _I, [_P, _P, _P, _P]),
     ("gmres_solve", _I, [_P, _P, _P, _D, _I, _I, _IP, _DP, _DP, _P]),
+    ("gmres_solve_batch", _I, [_P, _P, _P, _DP, _I, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
@@ -345,6 +346,26 @@ def ras_pml_width_rule(k, h, C, k0=150.0):
     if rc:
         raise ValueError(lib().ras_pml_plan_error().decode())
     return cells.value
+
+
+def gmres_solve_batch(H: Handle, b, x, rtols, restart=100, maxit=500, stream=None, check=True):
+    """One tolerance per problem.  Returns (status, iters per problem, relres
+    per problem, hist of the worst problem)."""
+    import numpy as np
+    _check_vec(b, H.ndof, "b")
+    _check_vec(x, H.ndof, "x")
+    r = np.ascontiguousarray(rtols, dtype=np.float64)
+    if r.size != H.nprob:
+        raise ValueError("one tolerance per problem (%d)" % H.nprob)
+    it = np.zeros(H.nprob, dtype=np.int32)
+    rr = np.zeros(H.nprob)
+    hist = np.full(maxit + 1, np.nan)
+    rc = lib().gmres_solve_batch(H.ptr, _ptr(b), _ptr(x), r.ctypes.data_as(_DP), restart, maxit,
+                                 it.ctypes.data_as(_IP), rr.ctypes.data_as(_DP),
+                                 hist.ctypes.data_as(_DP), _stream(stream))
+    if check and rc not in (RAS_OK, RAS_ENOTCONV, RAS_EBREAKDOWN):
+        H._raise(rc)
+    return rc, it.tolist(), rr.tolist(), hist[~np.isnan(hist)]
 
 
 def ras_pml_batch_result(H: Handle, p):

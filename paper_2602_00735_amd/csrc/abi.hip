@@ -559,7 +559,8 @@ int reduce_sync(ras_pml_handle *H, const double2 *a, const double2 *b, int mode,
     return RAS_OK;
 }
 
-int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int m, int maxit,
+// rtol: one tolerance per problem.
+int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rtol, int m, int maxit,
                int *iters, double *relres, double *hist, hipStream_t st) {
     const int P = H->nprob;
     RCHK(ensure_krylov(H, m));
@@ -590,7 +591,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
             H->last_error = "initial residual is not finite";
             return RAS_ENONFINITE;
         }
-        need[p] = (bnorm[p] > 0.0 && beta[p] > rtol * bnorm[p]) ? 1 : 0;
+        need[p] = (bnorm[p] > 0.0 && beta[p] > rtol[p] * bnorm[p]) ? 1 : 0;
         H->res_relres[p] = bnorm[p] > 0.0 ? beta[p] / bnorm[p] : 0.0;
         H->res_conv[p] = need[p] ? 0 : 1;
         nneed += need[p];
@@ -607,7 +608,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
             K.bnorm = bnorm[p];
             K.beta = beta[p];
             K.est = beta[p];
-            K.rtol = rtol;
+            K.rtol = rtol[p];
             K.kp = 0;
             K.in_cycle = need[p];
             K.breakdown = 0;
@@ -721,7 +722,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int
                 return RAS_ENONFINITE;
             }
             H->res_relres[p] = beta[p] / bnorm[p];
-            if (beta[p] <= rtol * bnorm[p]) {
+            if (beta[p] <= rtol[p] * bnorm[p]) {
                 need[p] = 0;
                 H->res_conv[p] = 1;
             } else if (H->h_ks[p].breakdown) {
@@ -1166,8 +1167,38 @@ int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, i
         return RAS_EINVAL;
     }
     try {
-        return gmres_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
+        const std::vector<double> r(H->nprob, rtol);
+        return gmres_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), r.data(),
                           restart, maxit, iters, relres, hist, as_stream(stream));
+    } catch (const std::exception &e) {
+        H->last_error = e.what();
+        return RAS_ENOMEM;
+    }
+}
+
+int gmres_solve_batch(ras_pml_t H, const void *b, void *x, const double *rtol, int restart,
+                      int maxit, int *iters, double *relres, double *hist, void *stream) {
+    if (!H) return RAS_EINVAL;
+    if (!b || !x || b == x || !rtol || restart < 1 || maxit < 0) {
+        H->last_error = "invalid gmres arguments";
+        return RAS_EINVAL;
+    }
+    for (int p = 0; p < H->nprob; ++p)
+        if (!(rtol[p] > 0.0)) {
+            H->last_error = "every tolerance must be positive";
+            return RAS_EINVAL;
+        }
+    try {
+        int it = 0;
+        double rr = 0.0;
+        const int rc = gmres_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
+                                  restart, maxit, &it, &rr, hist, as_stream(stream));
+        if (!H->res_iters.empty())
+            for (int p = 0; p < H->nprob; ++p) {
+                if (iters) iters[p] = H->res_iters[p];
+                if (relres) relres[p] = H->res_relres[p];
+            }
+        return rc;
     } catch (const std::exception &e) {
         H->last_error = e.what();
         return RAS_ENOMEM;

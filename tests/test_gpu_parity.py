@@ -515,6 +515,35 @@ def test_batch_handle_matches_separate_problems():
         assert np.linalg.norm(bs[p] - R.A @ xs[off:off + m]) <= 1e-6 * np.linalg.norm(bs[p]) * (1 + 1e-9)
 
 
+def test_batch_gmres_with_one_tolerance_per_problem():
+    """gmres_solve_batch: each problem stops at its own tolerance, with the
+    oracle's iteration count at that tolerance (+-1)."""
+    base = [PROBLEMS["k20"], PROBLEMS["ragged"], PROBLEMS["k40_two_slot"]]
+    pbs = [Problem(k=p.k, n_int=p.n_int, G=p.kappa, Px=p.Px, Py=p.Py, delta=p.delta,
+                   kappa=p.kappa, sigma=10 * p.k) for p in base]
+    tols = [1e-4, 1e-8, 1e-6]
+    o = rp.default_opts(precision=rp.RAS_FP64)
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs], o)
+    Rs = [ras.RasPml(p) for p in pbs]
+    bs = [fem.rhs(R.M1, inputs.centre_gaussian(p.n_int, p.G, 0.1)) for p, R in zip(pbs, Rs)]
+    x = torch.zeros(H.ndof, dtype=torch.complex128, device="cuda")
+    rc, its, rrs, hist = rp.gmres_solve_batch(H, dev(np.concatenate(bs)), x, tols, restart=50,
+                                              maxit=300)
+    assert rc == rp.RAS_OK
+    xs = host(x)
+    for p, (R, b, tol) in enumerate(zip(Rs, bs, tols)):
+        off, m = H.problem_offset(p)
+        ref = gmres.gmres(lambda y: R.A @ y, R.apply, b, rtol=tol, restart=50, maxit=300)
+        assert abs(its[p] - ref.iters) <= 1, (p, its[p], ref.iters)
+        res = np.linalg.norm(b - R.A @ xs[off:off + m]) / np.linalg.norm(b)
+        assert res <= tol * (1 + 1e-9) and abs(res - rrs[p]) <= 1e-3 * tol
+    assert len(hist) >= max(its) + 1 and hist[-1] <= max(tols)
+    with pytest.raises(rp.RasPmlError):
+        rp.gmres_solve_batch(H, dev(np.concatenate(bs)), x, [1e-6, 0.0, 1e-6])
+
+
 # ------------------------------------------------------------------ full sizes
 def covering(pb, wx, wy, i, j):
     """Subdomains whose partition-of-unity weight is non-zero at node (i, j)."""
