@@ -167,10 +167,10 @@ def main():
         rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        stats = rp.ras_pml_get_stats(H) if timing else None
+        stats = rp.ras_pml_get_stats(H)
         H.close()
         return dict(rc=rc, iters=it, relres=rr, setup_s=t1 - t0, solve_s=t2 - t1,
-                    total_s=t2 - t0, stats=stats, x=x)
+                    total_s=t2 - t0, stats=stats, x=x, alloc_s=stats["alloc_ms"] / 1000.0)
 
     # ---------------------------------------------------------------- warmup
     for _ in range(args.warmup):
@@ -239,6 +239,7 @@ def main():
         },
         "mixed": {"iters": mixed["iters"], "relres": mixed["relres"],
                   "setup_s": round(mixed["setup_s"], 5), "solve_s": round(mixed["solve_s"], 5),
+                  "device_alloc_s": round(mixed["alloc_s"], 5),
                   "breakdown_note": "per-kernel sums over one extra solve with per-launch "
                                     "events (which slow each launch a little)",
                   "per_step_breakdown_ms": {
@@ -269,7 +270,7 @@ def main():
         d = (mixed["x"] - r64["x"]).norm().item() / r64["x"].norm().item()
         out["fp64"] = {"iters": r64["iters"], "relres": r64["relres"],
                        "setup_s": round(r64["setup_s"], 5), "solve_s": round(r64["solve_s"], 5),
-                       "total_s": round(r64["total_s"], 5),
+                       "total_s": round(r64["total_s"], 5), "device_alloc_s": round(r64["alloc_s"], 5),
                        "band_solve_avg_ms": round(ms64, 4),
                        "band_solve_GBs": round(b64 / (ms64 * 1e-3) / 1e9, 1)}
         out["mixed_vs_fp64_solution_rel_l2"] = d
@@ -608,9 +609,11 @@ def batch32(dev, no_fp64):
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             per = [rp.ras_pml_batch_result(H, m) for m in range(32)]
+            alloc = rp.ras_pml_get_stats(H)["alloc_ms"] / 1000.0
             H.close()
         res[name] = {"total_s": round(t2 - t0, 5), "setup_s": round(t1 - t0, 5),
-                     "solve_s": round(t2 - t1, 5), "status": rc,
+                     "solve_s": round(t2 - t1, 5), "device_alloc_s": round(alloc, 5),
+                     "status": rc,
                      "iters_max": max(p[0] for p in per), "iters_min": min(p[0] for p in per),
                      "all_converged": all(p[2] for p in per),
                      "relres_max": max(p[1] for p in per)}

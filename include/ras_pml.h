@@ -315,6 +315,9 @@ typedef struct {
     double setup_assemble_ms, setup_factor_ms;
     double solve_bytes;    /* algorithmic bytes of one band-solve launch      */
     double factor_bytes;   /* bytes of all stored factors                     */
+    double alloc_ms;       /* host wall time spent in the handle's device
+                              allocations (setup and Krylov workspace; always
+                              recorded, kept by reset_stats)                  */
 } ras_pml_stats;
 /* Launch counts cover the GMRES steps that ran: steps enqueued after every
  * problem had stopped (gmres_solve enqueues up to eight ahead of its
@@ -322,6 +325,27 @@ typedef struct {
  * microseconds remain in the times. */
 int ras_pml_get_stats(ras_pml_t H, ras_pml_stats *out);
 int ras_pml_reset_stats(ras_pml_t H);
+
+/* Device-memory cache (process-wide; performance only).  Every device
+ * buffer of a handle comes from it: ras_pml_destroy (and a Krylov or
+ * history buffer that grows) waits for the handle's device, as hipFree
+ * would, and keeps the released blocks mapped for later handles on the same
+ * device whose buffers fit them (rounded size within 1/8).  A device
+ * allocation that runs out of memory first hands that device's idle blocks
+ * back to the driver.  Thread-safe.
+ *   ras_pml_empty_cache: hands every idle block back to the driver;
+ *     released_bytes (nullable) receives their total.
+ *   ras_pml_set_cache_limit: most bytes kept idle (0: keep none; negative:
+ *     the default, a third of the device's memory); trims idle blocks now.
+ *   ras_pml_cache_info: idle and handed-out bytes (each nullable).
+ *   ras_pml_fill_idle_cache: sets every byte of the current device's idle
+ *     blocks to `byte` and waits (tests: a handle must not depend on what
+ *     reused memory holds); RAS_EHIP if a fill fails.
+ * The others return RAS_OK.                                               */
+int ras_pml_empty_cache(long long *released_bytes);
+int ras_pml_set_cache_limit(long long bytes);
+int ras_pml_cache_info(long long *cached_bytes, long long *live_bytes);
+int ras_pml_fill_idle_cache(int byte);
 
 /* Autotuner (performance only: every variant computes the same values).
  * Times, on this handle's own factors and subdomain tables, the kernel

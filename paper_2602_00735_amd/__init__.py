@@ -49,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("n_mgs", ctypes.c_longlong), ("mgs_ms", ctypes.c_double),
                 ("n_givens", ctypes.c_longlong), ("givens_ms", ctypes.c_double),
                 ("setup_assemble_ms", ctypes.c_double), ("setup_factor_ms", ctypes.c_double),
-                ("solve_bytes", ctypes.c_double), ("factor_bytes", ctypes.c_double)]
+                ("solve_bytes", ctypes.c_double), ("factor_bytes", ctypes.c_double),
+                ("alloc_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -104,6 +105,11 @@ SYMBOLS = [
     ("ras_pml_export_factor", _I, [_P, _I, _P, _LL]),
     ("ras_pml_get_stats", _I, [_P, ctypes.POINTER(Stats)]),
     ("ras_pml_reset_stats", _I, [_P]),
+    ("ras_pml_empty_cache", _I, [ctypes.POINTER(ctypes.c_longlong)]),
+    ("ras_pml_set_cache_limit", _I, [ctypes.c_longlong]),
+    ("ras_pml_fill_idle_cache", _I, [_I]),
+    ("ras_pml_cache_info", _I, [ctypes.POINTER(ctypes.c_longlong),
+                                ctypes.POINTER(ctypes.c_longlong)]),
     ("ras_pml_autotune", _I, [_P, ctypes.c_char_p, _P]),
     ("ras_pml_tuning", _I, [_P, _IP, _IP, _I, _IP]),
     ("ras_pml_strerror", ctypes.c_char_p, [_I]),
@@ -413,6 +419,30 @@ def ras_pml_get_stats(H: Handle) -> dict:
     if rc:
         H._raise(rc)
     return s.as_dict()
+
+
+def ras_pml_empty_cache() -> int:
+    """Hand the idle cached device blocks back to the driver; returns their bytes."""
+    n = ctypes.c_longlong(0)
+    lib().ras_pml_empty_cache(ctypes.byref(n))
+    return n.value
+
+
+def ras_pml_set_cache_limit(nbytes: int):
+    lib().ras_pml_set_cache_limit(int(nbytes))
+
+
+def ras_pml_fill_idle_cache(byte: int):
+    rc = lib().ras_pml_fill_idle_cache(int(byte))
+    if rc != RAS_OK:
+        raise RasPmlError(rc, "filling the idle device blocks failed")
+
+
+def ras_pml_cache_info():
+    """(idle cached bytes, handed-out bytes)."""
+    a, b = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    lib().ras_pml_cache_info(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
 
 
 def ras_pml_reset_stats(H: Handle):

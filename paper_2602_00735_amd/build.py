@@ -24,7 +24,7 @@ ARCH = "gfx950"
 
 HIP_SOURCES = ["k_assemble.hip", "k_lu.hip", "k_lu_mfma.hip", "k_solve.hip", "k_krylov.hip",
                "k_warm.hip", "warm_net.hip", "abi.hip"]
-CPP_SOURCES = ["plan.cpp"]
+CPP_SOURCES = ["plan.cpp", "devpool.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 HIP_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH,

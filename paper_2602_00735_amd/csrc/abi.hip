@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -14,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "devpool.h"
 #include "device.h"
 #include "internal.h"
 #include "warm.h"
@@ -91,6 +93,7 @@ struct ras_pml_handle {
     long long ntot = 0, nloc = 0, nvec = 0, max_ndof = 0;
     bool fp64 = false;
     int flags = 0;
+    int device = 0;            // the device current at setup
     size_t csize = 8;          // bytes of one local complex value
     size_t fac_elems = 0;
 
@@ -148,8 +151,20 @@ namespace {
 
 thread_local std::string g_plan_error;
 
+// Device buffers come from the process-wide cache (devpool.cpp), which may
+// hand a released block to the next request at once: release only what no
+// queued work uses (idle_device first).
 void dfree(void *p) {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p);
+}
+
+// Waits for the handle's device, as hipFree would.
+void idle_device(int device) {
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != device;
+    if (other) (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    if (other) (void)hipSetDevice(cur);
 }
 
 #define HCHK(H, call)                                                                 \
@@ -165,10 +180,13 @@ template <typename P>
 int dalloc(ras_pml_handle *H, P **p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipError_t e = pool_alloc(reinterpret_cast<void **>(p), bytes);
+    H->stats.alloc_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) {
         char buf[128];
-        std::snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed: ", bytes);
+        std::snprintf(buf, sizeof buf, "device allocation of %zu bytes failed: ", bytes);
         H->last_error = std::string(buf) + hipGetErrorString(e);
         *p = nullptr;
         return e == hipErrorOutOfMemory ? RAS_ENOMEM : RAS_EHIP;
@@ -246,6 +264,9 @@ ras_pml_handle::~ras_pml_handle() {
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
                     d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err, d_rs, d_rhist};
+    bool any = false;
+    for (void *p : ptrs) any = any || p != nullptr;
+    if (any) idle_device(device);
     for (void *p : ptrs) dfree(p);
     if (h_ks) (void)hipHostFree(h_ks);
     if (h_rs) (void)hipHostFree(h_rs);
@@ -496,6 +517,7 @@ int plan_arnoldi(ras_pml_handle *H) {
 int ensure_krylov(ras_pml_handle *H, int m) {
     if (H->m_alloc >= m) return RAS_OK;
     void *ptrs[] = {H->d_V, H->d_Z, H->d_r, H->d_H, H->d_g, H->d_sn, H->d_y, H->d_cs, H->d_hist};
+    if (H->m_alloc > 0) idle_device(H->device);
     for (void *p : ptrs) dfree(p);
     H->d_V = H->d_Z = H->d_r = H->d_H = H->d_g = H->d_sn = H->d_y = nullptr;
     H->d_cs = H->d_hist = nullptr;
@@ -763,6 +785,7 @@ int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol
         HCHK(H, hipHostMalloc(reinterpret_cast<void **>(&H->h_rs), sizeof(RState) * P));
     }
     if (H->rhist_cap < maxit) {
+        if (H->d_rhist) idle_device(H->device);
         dfree(H->d_rhist);
         H->d_rhist = nullptr;
         H->rhist_cap = -1;
@@ -889,6 +912,10 @@ int setup_common(int nprob, const double *k, const double *h, const int *grid, c
     H->fp64 = o.precision == RAS_FP64;
     H->flags = o.flags;
     if (o.tune_cache) H->tune_cache = o.tune_cache;
+    if (hipGetDevice(&H->device) != hipSuccess) {
+        g_plan_error = "no HIP device";
+        return RAS_EHIP;
+    }
     int rc = build(H.get(), as_stream(stream));
     if (rc != RAS_OK) {
         g_plan_error = H->last_error;
@@ -1442,7 +1469,9 @@ int ras_pml_reset_stats(ras_pml_t H) {
     collect_events(H);
     const double sb = H->stats.solve_bytes, fb = H->stats.factor_bytes;
     const double a = H->stats.setup_assemble_ms, f = H->stats.setup_factor_ms;
+    const double al = H->stats.alloc_ms;
     std::memset(&H->stats, 0, sizeof(H->stats));
+    H->stats.alloc_ms = al;
     H->skipped_steps = 0;
     H->stats.solve_bytes = sb;
     H->stats.factor_bytes = fb;

@@ -246,6 +246,8 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
             const int k = tid & 15;
             int slk = sl0 + k;
             slk = slk >= W ? slk - W : slk;
+            // row c's own position (c mod W) holds 0
+            if (tid < 16) Rw[static_cast<long long>(npad - 1 - (c0 + k)) * W + slk] = zero;
             for (int r = c0 + 1 + (tid >> 4); r < c0 + W + 15; r += 16) {
                 const int c = c0 + k;
                 if (r > c && r < c + W && r < npad) {

@@ -48,6 +48,13 @@ def test_every_declared_symbol_is_exported(L):
     assert set(names) == bound
 
 
+def test_device_memory_cache_calls_need_no_device(L):
+    rp.ras_pml_set_cache_limit(1 << 30)
+    assert rp.ras_pml_cache_info() == (0, 0)
+    assert rp.ras_pml_empty_cache() == 0
+    rp.ras_pml_set_cache_limit(-1)
+
+
 def test_strerror(L):
     for s in range(9):
         assert rp.ras_pml_strerror(s)

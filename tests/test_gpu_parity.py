@@ -544,6 +544,91 @@ def test_batch_gmres_with_one_tolerance_per_problem():
         rp.gmres_solve_batch(H, dev(np.concatenate(bs)), x, [1e-6, 0.0, 1e-6])
 
 
+def test_device_memory_cache_reuses_released_blocks():
+    """A destroyed handle's buffers stay cached and serve the next handle of
+    the same shape (no new mapping), whose results are those of a fresh
+    handle; empty_cache and a zero limit hand the blocks back."""
+    pb = PROBLEMS["k40_two_slot"]
+    R = ras.RasPml(pb)
+    v = inputs.random_vector(pb.ndof, 4)
+    want = R.apply(v)
+    rp.ras_pml_set_cache_limit(-1)
+    rp.ras_pml_empty_cache()
+    H = setup_gpu(pb, rp.RAS_FP64)
+    z = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
+    rp.ras_pml_apply(H, dev(v), z)
+    assert relerr(host(z), want) <= 1e-12
+    cached0, live0 = rp.ras_pml_cache_info()
+    assert live0 > 0
+    H.close()
+    cached1, live1 = rp.ras_pml_cache_info()
+    assert live1 == live0 - (cached1 - cached0) and cached1 > cached0
+    moved = cached1 - cached0
+    for _ in range(2):
+        cb, lb = rp.ras_pml_cache_info()
+        H = setup_gpu(pb, rp.RAS_FP64)
+        ca, la = rp.ras_pml_cache_info()
+        assert la - lb == moved and cb - ca == moved        # every block came from the cache
+        z.zero_()
+        rp.ras_pml_apply(H, dev(v), z)
+        assert relerr(host(z), want) <= 1e-12
+        b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+        x = torch.zeros_like(b)
+        rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-8, restart=30)
+        assert rc == rp.RAS_OK and rr <= 1e-8
+        H.close()
+    assert rp.ras_pml_empty_cache() >= moved
+    assert rp.ras_pml_cache_info()[0] == 0
+    rp.ras_pml_set_cache_limit(0)
+    H = setup_gpu(pb, rp.RAS_FP64)
+    H.close()
+    assert rp.ras_pml_cache_info()[0] == 0
+    rp.ras_pml_set_cache_limit(-1)
+
+
+@pytest.mark.parametrize("name", ["k20", "ragged", "max_band", "clip_drch"])
+@pytest.mark.parametrize("precision", [rp.RAS_FP64, rp.RAS_MIXED])
+def test_results_do_not_depend_on_reused_memory(name, precision):
+    """A handle set up on cached blocks filled with 0xFF bytes (NaN in every
+    floating-point view) factors, applies, solves and iterates bit for bit
+    as one set up before: no kernel reads memory that it has not written."""
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    v = dev(inputs.random_vector(pb.ndof, 5))
+    b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+    rp.ras_pml_set_cache_limit(-1)
+
+    def run():
+        H = setup_gpu(pb, precision)
+        desc = H.desc()
+        facs = [rp.ras_pml_export_factor(H, m, (desc[m][0] + 63) // 64 * 64, desc[m][2])
+                for m in range(min(3, len(desc)))]
+        z = torch.zeros_like(v)
+        rp.ras_pml_apply(H, v, z)
+        x = torch.zeros_like(b)
+        g = rp.gmres_solve(H, b, x, rtol=1e-8, restart=20, maxit=200)
+        xr = torch.zeros_like(b)
+        r = rp.ras_pml_richardson(H, b, xr, rtol=1e-6, maxit=40)
+        H.close()
+        return facs, host(z), host(x), g[:3], host(xr), r[:3]
+
+    first = run()
+    rp.ras_pml_fill_idle_cache(0xFF)
+    cb, lb = rp.ras_pml_cache_info()
+    second = run()
+    ca, la = rp.ras_pml_cache_info()
+    assert ca == cb and la == lb                     # the second handle ran on the filled blocks
+    for (a, b_, c), (d, e, f) in zip(first[0], second[0]):
+        assert np.array_equal(a, d) and np.array_equal(b_, e) and np.array_equal(c, f)
+    for u, w in zip(first[1:], second[1:]):
+        if isinstance(u, np.ndarray):
+            assert np.array_equal(u, w)
+        else:
+            assert u == w
+    tol = 1e-12 if precision == rp.RAS_FP64 else 1e-4
+    assert relerr(second[1], R.apply(host(v))) <= tol
+
+
 # ------------------------------------------------------------------ full sizes
 def covering(pb, wx, wy, i, j):
     """Subdomains whose partition-of-unity weight is non-zero at node (i, j)."""
