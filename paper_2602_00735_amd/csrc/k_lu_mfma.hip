@@ -67,6 +67,41 @@ __device__ __forceinline__ cplx<float> band_entry(const double2 *__restrict__ ls
     return cplx<float>{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
 }
 
+// What one panel needs from the stencil, staged in LDS a panel ahead so that
+// no global load waits inside the panel: entries i < 64 are the couplings of
+// row r = c0 + M + i / 4 (the rows entering the window's last tile row) to
+// rows r - {0, 1, n_fast, n_fast + 1} (i mod 4), entries 64..79 the
+// magnitudes |A_j(c, c)| of the panel's columns c = c0 + i - 64 (pivot
+// test).  stage_load issues the one load of entry i, stage_value finishes it
+// where the value is written to LDS.
+struct StageRef {
+    int r, q;        // entry A_j(r, q), r >= q
+    bool diag;       // magnitude of a diagonal entry
+};
+__device__ __forceinline__ StageRef stage_ref(int i, int c0, int M, int nf) {
+    if (i < 64) {
+        const int r = c0 + M + (i >> 2), e = i & 3;
+        return {r, r - (e == 0 ? 0 : e == 1 ? 1 : e == 2 ? nf : nf + 1), false};
+    }
+    const int c = c0 + i - 64;
+    return {c, c, true};
+}
+__device__ __forceinline__ double2 stage_load(const double2 *__restrict__ lst, int n, int nf,
+                                              const StageRef &a) {
+    const int d = a.r - a.q;
+    const int e = d == 0 ? 0 : d == 1 ? 1 : d == nf ? 2 : 3;
+    return lst[4LL * min(a.q, n - 1) + e];
+}
+__device__ __forceinline__ cplx<float> stage_value(int n, int nf, const StageRef &a, double2 v) {
+    const int d = a.r - a.q;
+    const bool wrap = (a.r % nf) == 0;
+    const bool in = a.r < n;
+    const bool coupled = in && (d == 0 || d == nf || ((d == 1 || d == nf + 1) && !wrap));
+    const float id = (!in && d == 0) ? 1.0f : 0.0f;
+    const cplx<float> x{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
+    return a.diag ? cplx<float>{sqrtf(cabs2(x)), 0.0f} : x;
+}
+
 // Rows of the panel factorisation: NW = 1 + ceil((M - 64) / 48) waves take
 // part.  Part v = 0 holds rows 0..63 (one per lane); part v >= 1 holds rows
 // 0..15 in lanes 0..15 (the same values as part 0, computed again so that no
@@ -141,10 +176,10 @@ __device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
 
 // OCC: the kernel is held to 128 registers, so that four workgroups (one
 // subdomain each) share a CU (at k = 640 all 1024 subdomains are then
-// resident at once; the largest windows spill a little to fit).  Without
-// it the compiler's own budget applies (two workgroups per CU, no spills).
+// resident at once; from NT = 6 on the window spills to fit).  Without it
+// the compiler's own budget applies (two workgroups per CU, no spills).
 // Which is faster depends on the window and the number of subdomains; the
-// default is OCC up to NT = 7 and the autotuner measures both.
+// default is OCC up to NT = 6 and the autotuner measures both.
 template <int NT, bool OCC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 4 : 1))) void
 k_band_ldlt_mfma(const DevSub *__restrict__ subs,
@@ -160,6 +195,7 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     __shared__ cplx<float> LP[(M + 1) * kLdsStride];   // published panel, then L (rows 16..)
     __shared__ cplx<float> LT[16 * kLdsStride];        // L of the panel's first 16 rows
     __shared__ cplx<float> WB[(M + 1) * kLdsStride];   // W = L D (rows 16..)
+    __shared__ cplx<float> STG[2][80];                 // stencil staged per panel parity
 
     const int sid = order[blockIdx.x];
     const DevSub S = subs[sid];
@@ -203,12 +239,20 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     }
 
     int bad = -1;
-    // original diagonal magnitudes of the next panel's columns (pivot test),
-    // loaded one panel ahead
-    auto diag = [&](int c0) { return sqrtf(cabs2(band_entry(lst, n, nf, c0 + tj, c0 + tj))); };
-    float dg = diag(0);
+    // staged entries of panel 0; every thread loads one (branch-free), the
+    // first 80 store theirs
+    const int si = min(tid, 79);
+    {
+        const StageRef a = stage_ref(si, 0, M, nf);
+        const cplx<float> v = stage_value(n, nf, a, stage_load(lst, n, nf, a));
+        if (tid < 80) STG[0][tid] = v;
+    }
+    lds_barrier();
     for (int c0 = 0; c0 < npad; c0 += 16) {
-        const float dg_next = diag(c0 + 16);
+        const int buf = (c0 >> 4) & 1;
+        // the next panel's entries: loaded now, stored at the end of the panel
+        const double2 rnext = stage_load(lst, n, nf, stage_ref(si, c0 + 16, M, nf));
+        const float dg = STG[buf][64 + tj].re;
         // 1. publish logical tile column 0 (J == 0 on every diagonal)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -224,7 +268,6 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
         // rotates with the workgroup so that the workgroups sharing a CU
         // tend to factorise on different SIMDs
         if (part < panel_waves<M>()) bad = factor_panel<M>(LP, LT, WB, dg, c0, Dinv, bad, part);
-        dg = dg_next;
         lds_barrier();
         // 3. columns c0 .. c0+15 of L (slot order) and their entries in the
         //    rows of L; row r's entry of column c sits at position c mod W
@@ -239,8 +282,11 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                 if (pos < W) {
                     const int r = c + (pos >= sl ? pos - sl : pos - sl + W);
                     const int rr = r - c0;
-                    L[static_cast<long long>(c) * W + pos] =
-                        r == c ? zero : (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                    // values, not a select of lvalues (which would make a
+                    // generic pointer and flat loads that wait on the stores)
+                    const cplx<float> a = LT[min(rr, 15) * kLdsStride + k];
+                    const cplx<float> b = LP[rr * kLdsStride + k];
+                    L[static_cast<long long>(c) * W + pos] = csel(r == c, zero, csel(rr < 16, a, b));
                 }
             }
             const int k = tid & 15;
@@ -252,13 +298,16 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                 const int c = c0 + k;
                 if (r > c && r < c + W && r < npad) {
                     const int rr = r - c0;
-                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] =
-                        (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                    const cplx<float> a = LT[min(rr, 15) * kLdsStride + k];
+                    const cplx<float> b = LP[rr * kLdsStride + k];
+                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] = csel(rr < 16, a, b);
                 }
             }
         }
         // 4. rank-16 update of the tiles with J >= 1; the tiles with J == 0
         //    leave and come back as their diagonal's last tile
+        int tdiff = ti - tj;
+        asm volatile("" : "+v"(tdiff));   // per panel: keeps the per-slot offsets out of registers
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int d = dg_[s], J = jc_[s];
@@ -279,16 +328,24 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                         cim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.im, w.re, cim[s], 0, 0, 0);
                     }
                 } else {
-                    // next window: row NT - 1, column NT - 1 - d
+                    // next window: row NT - 1, column NT - 1 - d, from the
+                    // staged couplings of the entering rows; entry (ti + r,
+                    // tj) of the tile lies dd = 16 d + ti + r - tj below the
+                    // diagonal
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const cplx<float> v = band_entry(lst, n, nf, c0 + M + ti + r,
-                                                         c0 + 16 + 16 * (NT - 1 - d) + tj);
-                        cre[s][r] = v.re;
-                        cim[s][r] = v.im;
+                        const int dd = 16 * d + tdiff + r;
+                        const int e = dd == 0 ? 0 : dd == 1 ? 1 : dd == nf ? 2 : dd == nf + 1 ? 3 : -1;
+                        const cplx<float> v = STG[buf][4 * (ti + r) + max(e, 0)];
+                        cre[s][r] = e >= 0 ? v.re : 0.0f;
+                        cim[s][r] = e >= 0 ? v.im : 0.0f;
                     }
                 }
             }
+        }
+        {
+            const cplx<float> v = stage_value(n, nf, stage_ref(si, c0 + 16, M, nf), rnext);
+            if (tid < 80) STG[buf ^ 1][tid] = v;
         }
         lds_barrier();
     }
@@ -312,7 +369,7 @@ void launch_nt(bool occ, const DevSub *subs, const int *order, int count, const 
 int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }
 
 // Default register budget of a window class (see k_band_ldlt_mfma).
-bool ldlt_mfma_default_occ(int NT) { return NT <= 7; }
+bool ldlt_mfma_default_occ(int NT) { return NT <= 6; }
 
 // count subdomains order[0 .. count) that all have ldlt_mfma_tiles(W) == NT.
 void launch_band_ldlt_mfma(int NT, bool occ, const DevSub *subs, const int *order, int count,
