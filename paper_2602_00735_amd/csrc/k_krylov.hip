@@ -350,42 +350,53 @@ constexpr int kBarStride = 32;          // unsigned long long per line
 
 // Grid-wide barrier for a cooperative launch (every block co-resident).
 // Counters only grow: barrier `epoch` (absolute, counted since the handle
-// was created) completes when group g has epoch * size(g) arrivals and the
-// top word epoch * ngroups.  The first block of each group waits on the top
-// word and then publishes the epoch to its group.  Polls are bounded;
-// running out sets *err and lets the block continue (wrong numbers that the
-// host reports, never a hang).
+// was created) is complete when every block has arrived at it.  A block
+// arrives by incrementing its group's counter; the block whose increment
+// completes the group (epoch * size(g)) increments the top counter, and the
+// block whose increment completes the top (epoch * ngroups) writes the
+// epoch to every group's release word, which the group's blocks poll.  No
+// block waits to forward an arrival, so the release follows the last
+// arrival by two atomic round trips and a store.  Polls are bounded: running
+// out sets *err, and the block stops waiting at this launch's later
+// barriers (`failed`), so the launch ends quickly with wrong numbers that
+// the host reports, never a hang.
 __device__ __forceinline__ bool spin_until(unsigned long long *p, unsigned long long target) {
     unsigned int polls = 0;
     while (peek(p) < target) {
         __builtin_amdgcn_s_sleep(1);
-        if (++polls > (1u << 26)) return false;
+        if (++polls > (1u << 22)) return false;
     }
     return true;
 }
 
+// Counts `n` arrivals of this block (n > 1: barriers a skipped step passes
+// without waiting) and releases the epoch `target` when they complete it.
+__device__ __forceinline__ void barrier_arrive(unsigned long long *bar, unsigned long long target,
+                                               unsigned long long n) {
+    const int nb = gridDim.x;
+    const int ngroups = (nb + kBarGroup - 1) / kBarGroup;
+    const int g = blockIdx.x / kBarGroup;
+    const unsigned long long gsize = min(kBarGroup, nb - g * kBarGroup);
+    const unsigned long long old = atomicAdd(bar + kBarStride * (g + 1), n);
+    if (old + n != target * gsize) return;                  // not the group's last arrival
+    const unsigned long long t = atomicAdd(bar, n);
+    if (t + n != target * static_cast<unsigned long long>(ngroups)) return;
+    for (int q = 0; q < ngroups; ++q)
+        __hip_atomic_store(bar + kBarStride * (q + 1) + 16, target, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned long long epoch,
-                                             int *err) {
+                                             int *err, bool &failed) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_s_waitcnt(0);          // this block's published values are complete
-        const int nb = gridDim.x;
-        const int ngroups = (nb + kBarGroup - 1) / kBarGroup;
-        const int g = blockIdx.x / kBarGroup;
-        const int gsize = min(kBarGroup, nb - g * kBarGroup);
-        unsigned long long *garr = bar + kBarStride * (g + 1);
-        unsigned long long *grel = garr + 16;
-        atomicAdd(garr, 1ull);
-        bool ok = true;
-        if (blockIdx.x % kBarGroup == 0) {
-            ok = spin_until(garr, epoch * gsize);
-            atomicAdd(bar, 1ull);
-            ok = spin_until(bar, epoch * ngroups) && ok;
-            __hip_atomic_store(grel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            ok = spin_until(grel, epoch);
+        barrier_arrive(bar, epoch, 1);
+        unsigned long long *grel = bar + kBarStride * (blockIdx.x / kBarGroup + 1) + 16;
+        if (!failed && !spin_until(grel, epoch)) {
+            failed = true;
+            atomicOr(err, 1);
         }
-        if (!ok) atomicOr(err, 1);
     }
     __syncthreads();
 }
@@ -424,13 +435,7 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
     if (!any) {
         if (threadIdx.x == 0) {
             const unsigned long long nbar = static_cast<unsigned long long>(j) + 2;
-            unsigned long long *garr = bar + kBarStride * (blockIdx.x / kBarGroup + 1);
-            atomicAdd(garr, nbar);
-            if (blockIdx.x % kBarGroup == 0) {
-                atomicAdd(bar, nbar);
-                __hip_atomic_store(garr + 16, epoch0 + nbar, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
+            barrier_arrive(bar, epoch0 + nbar, nbar);
         }
         return;
     }
@@ -464,6 +469,7 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
         }
     }
     unsigned long long epoch = 0;
+    bool failed = false;                  // (thread 0) a poll of this launch ran out
     for (int i = 0; i <= j; ++i) {
         const double2 *vi = V + static_cast<long long>(i) * ntot;
         cplx<double> v[E];
@@ -478,7 +484,7 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
         const cplx<double> bs = block_sum(acc, sh);
         if (threadIdx.x == 0) put_agent(part + blockIdx.x, bs);
         ++epoch;
-        grid_barrier(bar, epoch0 + epoch, err);
+        grid_barrier(bar, epoch0 + epoch, err, failed);
         const cplx<double> h = problem_sum(part, B, sh);
 #pragma unroll
         for (int q = 0; q < E; ++q) w[q] = cfms(w[q], h, v[q]);
@@ -491,7 +497,7 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
     const cplx<double> bs = block_sum(cplx<double>{nrm, 0.0}, sh);
     if (threadIdx.x == 0) put_agent(part + blockIdx.x, cplx<double>{bs.re, 0.0});
     ++epoch;
-    grid_barrier(bar, epoch0 + epoch, err);
+    grid_barrier(bar, epoch0 + epoch, err, failed);
     const double hn = sqrt(problem_sum(part, B, sh).re);
     if (!on) return;
     const double s = hn > 0.0 ? 1.0 / hn : 0.0;
