@@ -10,6 +10,7 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -156,6 +157,21 @@ thread_local std::string g_plan_error;
 // queued work uses (idle_device first).
 void dfree(void *p) {
     if (p) pool_free(p);
+}
+
+// One auxiliary stream per device (default priority, created on first use,
+// kept for the life of the process): the smaller factorisation classes run
+// on it beside the largest, so their workgroups take the slots the largest
+// class leaves free in its last round.
+hipStream_t aux_stream(int device) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    std::lock_guard<std::mutex> g(mu);
+    if (device < 0) return nullptr;
+    if (streams.size() <= static_cast<size_t>(device)) streams.resize(device + 1, nullptr);
+    if (!streams[device] && hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking) != hipSuccess)
+        streams[device] = nullptr;
+    return streams[device];
 }
 
 // Waits for the handle's device, as hipFree would.
@@ -430,10 +446,27 @@ int build(ras_pml_handle *H, hipStream_t st) {
                          H->d_status, st);
         HCHK(H, hipGetLastError());
     } else {
-        for (const auto &g : H->lu_groups) {
+        // the largest window class on the caller's stream, the others beside
+        // it on the auxiliary stream (fork and join through events)
+        hipStream_t aux = H->lu_groups.size() > 1 ? aux_stream(H->device) : nullptr;
+        hipEvent_t fork{}, join{};
+        if (aux) {
+            HCHK(H, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+            HCHK(H, hipEventCreateWithFlags(&join, hipEventDisableTiming));
+            HCHK(H, hipEventRecord(fork, st));
+            HCHK(H, hipStreamWaitEvent(aux, fork, 0));
+        }
+        for (size_t i = 0; i < H->lu_groups.size(); ++i) {
+            const auto &g = H->lu_groups[i];
             launch_band_ldlt_mfma(g[0], g[3] != 0, H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
-                                  H->d_F, H->d_status, st);
+                                  H->d_F, H->d_status, i == 0 || !aux ? st : aux);
             HCHK(H, hipGetLastError());
+        }
+        if (aux) {
+            HCHK(H, hipEventRecord(join, aux));
+            HCHK(H, hipStreamWaitEvent(st, join, 0));
+            (void)hipEventDestroy(fork);
+            (void)hipEventDestroy(join);
         }
     }
     if (timing) HCHK(H, hipEventRecord(e2, st));
