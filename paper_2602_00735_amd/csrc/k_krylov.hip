@@ -72,28 +72,45 @@ __device__ cplx<double> block_sum(cplx<double> v, cplx<double> *sh) {
     return r;
 }
 
+// Values exchanged between blocks inside one launch (partial sums) are
+// written and read with device-scope atomic accesses, which are coherent
+// across the XCDs without L2 write-back/invalidate fences; the store is
+// complete (s_waitcnt) before the arrival is counted.
+__device__ __forceinline__ void put_agent(double2 *p, cplx<double> v) {
+    __hip_atomic_store(&p->x, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&p->y, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ cplx<double> get_agent(const double2 *p) {
+    double2 *q = const_cast<double2 *>(p);
+    return {__hip_atomic_load(&q->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+            __hip_atomic_load(&q->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+__device__ __forceinline__ unsigned long long peek(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Write this block's partial; the last block of the problem to arrive sums
 // all partials in index order and returns true with the total in *out.
+// The partials travel through agent-scope atomic accesses (the store is
+// complete before the ticket is drawn): no fence, which on this part would
+// write back and invalidate the L2 of the block's XCD.
 __device__ bool finish_reduction(cplx<double> part, int p, int nb, double2 *partials,
                                  unsigned int *counters, cplx<double> *sh, cplx<double> *out) {
     __shared__ int last;
     const int tid = threadIdx.x;
     if (tid == 0) {
-        partials[static_cast<long long>(p) * kRedBlocks + blockIdx.x] = make_double2(part.re, part.im);
-        __threadfence();
+        put_agent(partials + static_cast<long long>(p) * kRedBlocks + blockIdx.x, part);
+        __builtin_amdgcn_s_waitcnt(0);
         const unsigned int ticket = atomicAdd(&counters[p], 1u);
         last = (ticket == static_cast<unsigned int>(nb - 1)) ? 1 : 0;
     }
     __syncthreads();
     if (!last) return false;
-    __threadfence();
     cplx<double> acc{0, 0};
-    for (int e = tid; e < nb; e += kRedThreads) {
-        double2 v = partials[static_cast<long long>(p) * kRedBlocks + e];
-        acc = cadd(acc, cplx<double>{v.x, v.y});
-    }
+    for (int e = tid; e < nb; e += kRedThreads)
+        acc = cadd(acc, get_agent(partials + static_cast<long long>(p) * kRedBlocks + e));
     *out = block_sum(acc, sh);
-    if (tid == 0) counters[p] = 0u;
+    if (tid == 0) __hip_atomic_store(&counters[p], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
@@ -326,22 +343,6 @@ __global__ void k_rich_update(RState *__restrict__ rs, int *__restrict__ active,
 }
 
 // ---------------------------------------------------------------- fused step
-// Values exchanged between blocks inside one launch (partial sums) are
-// written and read with device-scope atomic accesses, which are coherent
-// across the XCDs without L2 write-back/invalidate fences; the store is
-// complete (s_waitcnt) before the arrival is counted.
-__device__ __forceinline__ void put_agent(double2 *p, cplx<double> v) {
-    __hip_atomic_store(&p->x, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&p->y, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ cplx<double> get_agent(const double2 *p) {
-    double2 *q = const_cast<double2 *>(p);
-    return {__hip_atomic_load(&q->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-            __hip_atomic_load(&q->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
-}
-__device__ __forceinline__ unsigned long long peek(unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Barrier words, each on its own 256-byte line: [0] top arrivals,
 // [32 (g+1)] arrivals of group g, [32 (g+1) + 16] release epoch of group g.
