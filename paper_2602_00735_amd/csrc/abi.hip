@@ -57,8 +57,10 @@ void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, 
                     hipStream_t);
 void launch_update_x(const DevProb *, int, long long, const KState *, const int *, int,
                      const double2 *, long long, const double2 *, double2 *, hipStream_t);
-int arnoldi_block_capacity(int E, int *blocks_per_cu);
-hipError_t launch_arnoldi(int E, int nblocks, const DevProb *, const KState *, const ArnoldiBlock *,
+int arnoldi_variants();
+int arnoldi_variant_e(int variant);
+int arnoldi_block_capacity(int variant, int *blocks_per_cu);
+hipError_t launch_arnoldi(int variant, int nblocks, const DevProb *, const KState *, const ArnoldiBlock *,
                           const double2 *, long long, const double2 *, double2 *, int, int,
                           double2 *, double2 *, unsigned long long *, unsigned long long, int *,
                           int, hipStream_t);
@@ -123,7 +125,7 @@ struct ras_pml_handle {
     unsigned int *d_counters = nullptr;
     // fused Arnoldi step (cooperative launch); E = 0 selects the
     // one-launch-per-projection path
-    int arn_E = -1, arn_nblocks = 0;
+    int arn_E = -1, arn_nblocks = 0, arn_var = 0;   // fused Arnoldi: unknowns per thread, variant
     ArnoldiBlock *d_ablocks = nullptr;
     double2 *d_part2 = nullptr;
     unsigned long long *d_bar = nullptr;
@@ -507,9 +509,10 @@ int plan_arnoldi(ras_pml_handle *H) {
     int coop = 0;
     HCHK(H, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return RAS_OK;
-    for (int E : {8, 16}) {
+    for (int var = 0; var < arnoldi_variants(); ++var) {
+        const int E = arnoldi_variant_e(var);
         int per_cu = 0;
-        if (arnoldi_block_capacity(E, &per_cu) != 0 || per_cu < 1) continue;
+        if (arnoldi_block_capacity(var, &per_cu) != 0 || per_cu < 1) continue;
         const long long cap = static_cast<long long>(per_cu) * cus;
         const long long slice = 256LL * E;
         long long need = 0;
@@ -542,6 +545,7 @@ int plan_arnoldi(ras_pml_handle *H) {
         HCHK(H, hipMemset(H->d_err, 0, sizeof(int)));
         H->bar_base = 0;
         H->arn_E = E;
+        H->arn_var = var;
         return RAS_OK;
     }
     return RAS_OK;
@@ -694,7 +698,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rt
             RCHK(do_apply(H, Vj, Zj, H->d_active, st));
             if (H->arn_E > 0) {
                 Timer t(H, C_MGS, st);
-                hipError_t e = launch_arnoldi(H->arn_E, H->arn_nblocks, H->d_probs, H->d_ks,
+                hipError_t e = launch_arnoldi(H->arn_var, H->arn_nblocks, H->d_probs, H->d_ks,
                                               H->d_ablocks, H->d_coef, n, Zj, H->d_V, j, m, H->d_H,
                                               H->d_part2, H->d_bar, H->bar_base, H->d_err, P, st);
                 if (e != hipSuccess) {

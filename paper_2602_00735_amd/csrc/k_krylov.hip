@@ -419,8 +419,8 @@ __device__ cplx<double> problem_sum(const double2 *__restrict__ part, const Arno
 // Each block keeps its slice of w (and the current v_i) in registers, so w is
 // never re-read; j + 2 grid barriers separate the reductions.  Problems not
 // in the cycle skip the arithmetic but take part in every barrier.
-template <int E>
-__global__ __launch_bounds__(kRedThreads) void k_arnoldi(
+template <int E, bool KEEPV>
+__device__ __forceinline__ void arnoldi_step(
     const DevProb *__restrict__ probs, const KState *__restrict__ ks,
     const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef, long long ntot,
     const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,
@@ -455,9 +455,16 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
         w[q] = cplx<double>{0, 0};
         if (on && o < B.n) {
             const long long g = B.first + o;
-            const long long idx = g - P.dof_off;
-            const int i = static_cast<int>(idx % n1) + 1;
-            const int jj = static_cast<int>(idx / n1) + 1;
+            int i, jj;
+            if constexpr (KEEPV) {
+                const long long idx = g - P.dof_off;
+                i = static_cast<int>(idx % n1) + 1;
+                jj = static_cast<int>(idx / n1) + 1;
+            } else {   // (a problem's unknowns are int-indexed)
+                const int idx = static_cast<int>(g - P.dof_off);
+                i = idx % n1 + 1;
+                jj = idx / n1 + 1;
+            }
             const double2 *C = coef, *Ec = coef + ntot, *N = coef + 2 * ntot, *NE = coef + 3 * ntot;
             cplx<double> acc = cmul(ld(C, g), ld(zj, g));
             if (i < n1) acc = cfma(acc, ld(Ec, g), ld(zj, g + 1));
@@ -468,18 +475,22 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
             if (i > 1 && jj > 1) acc = cfma(acc, ld(NE, g - n1 - 1), ld(zj, g - n1 - 1));
             w[q] = acc;
         }
+        // lean variant: at most two unknowns' stencil loads in flight
+        if constexpr (!KEEPV)
+            if ((q & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
     unsigned long long epoch = 0;
     bool failed = false;                  // (thread 0) a poll of this launch ran out
     for (int i = 0; i <= j; ++i) {
         const double2 *vi = V + static_cast<long long>(i) * ntot;
-        cplx<double> v[E];
+        cplx<double> v[KEEPV ? E : 1];
         cplx<double> acc{0, 0};
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int o = threadIdx.x + q * kRedThreads;
-            v[q] = (on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0};
-            acc = cdotacc(acc, v[q], w[q]);
+            const cplx<double> vq = (on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0};
+            if (KEEPV) v[q] = vq;
+            acc = cdotacc(acc, vq, w[q]);
         }
         double2 *part = part2 + static_cast<long long>(i & 1) * nblocks;
         const cplx<double> bs = block_sum(acc, sh);
@@ -488,7 +499,14 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
         grid_barrier(bar, epoch0 + epoch, err, failed);
         const cplx<double> h = problem_sum(part, B, sh);
 #pragma unroll
-        for (int q = 0; q < E; ++q) w[q] = cfms(w[q], h, v[q]);
+        for (int q = 0; q < E; ++q) {
+            const int o = threadIdx.x + q * kRedThreads;
+            // KEEPV: v_i stayed in registers; else it is read again (the
+            // register budget then leaves room for more blocks per CU)
+            const cplx<double> vq =
+                KEEPV ? v[q] : ((on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0});
+            w[q] = cfms(w[q], h, vq);
+        }
         if (on && blockIdx.x == B.first_blk && threadIdx.x == 0) st(Hp, col + i, h);
     }
     double nrm = 0.0;
@@ -510,6 +528,30 @@ __global__ __launch_bounds__(kRedThreads) void k_arnoldi(
     }
     if (blockIdx.x == B.first_blk && threadIdx.x == 0) st(Hp, col + j + 1, cplx<double>{hn, 0.0});
 }
+
+#define ARNOLDI_PARAMS                                                                          \
+    const DevProb *__restrict__ probs, const KState *__restrict__ ks,                           \
+        const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef,              \
+        long long ntot, const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,  \
+        double2 *__restrict__ H, double2 *__restrict__ part2, unsigned long long *bar,          \
+        unsigned long long epoch0, int *err, int nprob
+#define ARNOLDI_ARGS probs, ks, blocks, coef, ntot, zj, V, j, m, H, part2, bar, epoch0, err, nprob
+
+template <int E>
+__global__ __launch_bounds__(kRedThreads) void k_arnoldi(ARNOLDI_PARAMS) {
+    arnoldi_step<E, true>(ARNOLDI_ARGS);
+}
+
+// v_i read again after each barrier instead of kept, and the register
+// budget held to three workgroups per CU: for grids the kernel above cannot
+// keep co-resident.
+template <int E>
+__global__ __launch_bounds__(kRedThreads) __attribute__((amdgpu_waves_per_eu(3))) void
+k_arnoldi_lean(ARNOLDI_PARAMS) {
+    arnoldi_step<E, false>(ARNOLDI_ARGS);
+}
+#undef ARNOLDI_PARAMS
+#undef ARNOLDI_ARGS
 
 }  // namespace
 
@@ -576,16 +618,34 @@ void launch_update_x(const DevProb *probs, int nprob, long long max_ndof, const 
 
 namespace raspml {
 
-int arnoldi_block_capacity(int E, int *blocks_per_cu) {
+// Fused Arnoldi variants in the order the planner tries them: 8 or 16
+// unknowns per thread with v_i kept in registers across the barrier, then 12
+// with v_i read again (168 registers, three workgroups per CU instead of two;
+// the few values it spills live outside the projection loop): for batches
+// whose grid would not fit otherwise.
+namespace {
+const void *arnoldi_fn(int variant) {
+    switch (variant) {
+        case 0: return reinterpret_cast<const void *>(k_arnoldi<8>);
+        case 1: return reinterpret_cast<const void *>(k_arnoldi<16>);
+        default: return reinterpret_cast<const void *>(k_arnoldi_lean<12>);
+    }
+}
+}  // namespace
+
+int arnoldi_variants() { return 3; }
+int arnoldi_variant_e(int variant) { return variant == 0 ? 8 : variant == 1 ? 16 : 12; }
+
+int arnoldi_block_capacity(int variant, int *blocks_per_cu) {
     int nb = 0;
-    hipError_t e = E <= 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_arnoldi<8>, kRedThreads, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_arnoldi<16>, kRedThreads, 0);
-    if (e != hipSuccess) return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, arnoldi_fn(variant), kRedThreads, 0) !=
+        hipSuccess)
+        return -1;
     *blocks_per_cu = nb;
     return 0;
 }
 
-hipError_t launch_arnoldi(int E, int nblocks, const DevProb *probs, const KState *ks,
+hipError_t launch_arnoldi(int variant, int nblocks, const DevProb *probs, const KState *ks,
                           const ArnoldiBlock *blocks, const double2 *coef, long long ntot,
                           const double2 *zj, double2 *V, int j, int m, double2 *H, double2 *part2,
                           unsigned long long *bar, unsigned long long epoch0, int *err, int nprob,
@@ -593,9 +653,8 @@ hipError_t launch_arnoldi(int E, int nblocks, const DevProb *probs, const KState
     void *args[] = {(void *)&probs, (void *)&ks, (void *)&blocks, (void *)&coef, (void *)&ntot,
                     (void *)&zj, (void *)&V, (void *)&j, (void *)&m, (void *)&H, (void *)&part2,
                     (void *)&bar, (void *)&epoch0, (void *)&err, (void *)&nprob};
-    const void *fn = E <= 8 ? reinterpret_cast<const void *>(k_arnoldi<8>)
-                            : reinterpret_cast<const void *>(k_arnoldi<16>);
-    return hipLaunchCooperativeKernel(fn, dim3(nblocks), dim3(kRedThreads), args, 0, s);
+    return hipLaunchCooperativeKernel(arnoldi_fn(variant), dim3(nblocks), dim3(kRedThreads), args, 0,
+                                      s);
 }
 
 }  // namespace raspml

@@ -775,6 +775,38 @@ def config4_items():
     return items
 
 
+def test_batch_of_32_runs_the_fused_arnoldi_step_and_matches_the_unfused():
+    """Performance guard and parity: the 32-problem batch's grid fits the
+    chip only in the lean fused variant (v_i read again after each barrier);
+    it runs there (no separate SpMV launch) and its FP64 iterates, step
+    counts and residual histories equal those of the one-launch-per-
+    projection path to rounding."""
+    items = config4_items()
+    pbs = [p for p, _ in items]
+    f = dev(np.concatenate([inputs.batch_source(p.n_int, p.G, d) for p, d in items]))
+    res = {}
+    for flags in (rp.RAS_FLAG_TIMING, rp.RAS_FLAG_TIMING | rp.RAS_FLAG_UNFUSED_ARNOLDI):
+        H = rp.ras_pml_setup_batch([p.k for p in pbs], [1.0 / p.n_int for p in pbs],
+                                   [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                                   [p.delta for p in pbs], [p.kappa for p in pbs],
+                                   rp.default_opts(precision=rp.RAS_FP64, flags=flags))
+        b = torch.zeros_like(f)
+        rp.ras_pml_rhs(H, f, b)
+        x = torch.zeros_like(f)
+        rp.ras_pml_reset_stats(H)
+        rc, it, rr, hist = rp.gmres_solve(H, b, x, rtol=1e-6, restart=100, maxit=500)
+        st = rp.ras_pml_get_stats(H)
+        assert rc == rp.RAS_OK
+        if not flags & rp.RAS_FLAG_UNFUSED_ARNOLDI:
+            assert st["n_spmv"] == 0 and st["n_mgs"] == it, st
+        res[flags] = (host(x), it, hist, [rp.ras_pml_batch_result(H, m)[0] for m in range(32)])
+        H.close()
+    (xa, ia, ha, pa), (xb, ib, hb, pb_) = res.values()
+    assert ia == ib and pa == pb_
+    assert np.allclose(ha, hb, rtol=1e-8, atol=1e-15)
+    assert relerr(xa, xb) <= 1e-10
+
+
 def test_config4_batch_of_32_problems():
     """All 32 problems (about 5 k subdomains, 2.2 M unknowns) in one handle and
     one GMRES(100) call, mixed and FP64: every problem converges to a true
