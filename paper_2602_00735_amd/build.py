@@ -30,6 +30,11 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I
 HIP_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
+# Per-source additions.  The factorisation keeps its accumulator tiles in
+# ordinary vector registers (its vector code reads and writes them between
+# the matrix-core updates): without this the compiler moves every tile into
+# accumulation registers and back around each update.
+HIP_EXTRA = {"k_lu_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd, verbose):
@@ -64,7 +69,8 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
     jobs_list = []
     for s in HIP_SOURCES:
         o = os.path.join(BUILD, s + ".o")
-        jobs_list.append([HIPCC, "-c", *COMMON, *HIP_FLAGS, os.path.join(CSRC, s), "-o", o])
+        jobs_list.append([HIPCC, "-c", *COMMON, *HIP_FLAGS, *HIP_EXTRA.get(s, []),
+                          os.path.join(CSRC, s), "-o", o])
     for s in CPP_SOURCES:
         o = os.path.join(BUILD, s + ".o")
         jobs_list.append([HIPCC, "-c", *COMMON, os.path.join(CSRC, s), "-o", o])
