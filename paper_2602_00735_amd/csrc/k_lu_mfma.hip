@@ -176,10 +176,11 @@ __device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
 
 // OCC: the kernel is held to 128 registers, so that four workgroups (one
 // subdomain each) share a CU (at k = 640 all 1024 subdomains are then
-// resident at once; from NT = 6 on the window spills to fit).  Without it
-// the compiler's own budget applies (two workgroups per CU, no spills).
-// Which is faster depends on the window and the number of subdomains; the
-// default is OCC up to NT = 6 and the autotuner measures both.
+// resident at once; from NT = 6 on the window spills a little to fit).
+// Without it the compiler's own budget applies (146 registers at NT = 7:
+// three workgroups per CU, no spills).  Which is faster depends on the
+// window and the number of subdomains; the default is OCC up to NT = 7 and
+// the autotuner measures both.
 template <int NT, bool OCC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 4 : 1))) void
 k_band_ldlt_mfma(const DevSub *__restrict__ subs,
@@ -282,11 +283,11 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                 if (pos < W) {
                     const int r = c + (pos >= sl ? pos - sl : pos - sl + W);
                     const int rr = r - c0;
-                    // values, not a select of lvalues (which would make a
+                    // one LDS read through a select of the two LDS arrays, the
+                    // zero selected as a value (a select with a local would make a
                     // generic pointer and flat loads that wait on the stores)
-                    const cplx<float> a = LT[min(rr, 15) * kLdsStride + k];
-                    const cplx<float> b = LP[rr * kLdsStride + k];
-                    L[static_cast<long long>(c) * W + pos] = csel(r == c, zero, csel(rr < 16, a, b));
+                    const cplx<float> v = (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                    L[static_cast<long long>(c) * W + pos] = csel(r == c, zero, v);
                 }
             }
             const int k = tid & 15;
@@ -298,9 +299,8 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                 const int c = c0 + k;
                 if (r > c && r < c + W && r < npad) {
                     const int rr = r - c0;
-                    const cplx<float> a = LT[min(rr, 15) * kLdsStride + k];
-                    const cplx<float> b = LP[rr * kLdsStride + k];
-                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] = csel(rr < 16, a, b);
+                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] =
+                        (rr < 16 ? LT : LP)[rr * kLdsStride + k];
                 }
             }
         }
@@ -369,7 +369,7 @@ void launch_nt(bool occ, const DevSub *subs, const int *order, int count, const 
 int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }
 
 // Default register budget of a window class (see k_band_ldlt_mfma).
-bool ldlt_mfma_default_occ(int NT) { return NT <= 6; }
+bool ldlt_mfma_default_occ(int NT) { return NT <= 7; }
 
 // count subdomains order[0 .. count) that all have ldlt_mfma_tiles(W) == NT.
 void launch_band_ldlt_mfma(int NT, bool occ, const DevSub *subs, const int *order, int count,
