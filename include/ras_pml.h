@@ -353,7 +353,9 @@ int ras_pml_fill_idle_cache(int byte);
  * subdomains, and keeps the faster for the handle's later calls:
  *   - per complex64 factorisation window class (tiles per side): the
  *     128-register variant (four workgroups per CU) or the unconstrained
- *     one (re-runs that class's factorisation; the factor is unchanged);
+ *     one, one class at a time with the others at their current choice,
+ *     each timed as the whole factorisation (the classes run side by side;
+ *     re-runs it, the factor is unchanged);
  *   - the band-solve prefetch depth (16 or 8 vectors; 32 or 16 for a
  *     complex64 handle whose bands all have W <= 64).
  * cache_path (nullable): the choices are merged into this flat JSON file,

@@ -302,6 +302,43 @@ namespace {
 
 void apply_cache(ras_pml_handle *H, const char *path);
 
+// The complex64 factorisation of every window class with each class's
+// register variant (lu_groups[i][3]): the largest class on the caller's
+// stream, the others beside it on the auxiliary stream (fork and join
+// through events), so that their workgroups take the slots the largest
+// class leaves free in its last round.
+int factorise_c64(ras_pml_handle *H, hipStream_t st) {
+    hipStream_t aux = H->lu_groups.size() > 1 ? aux_stream(H->device) : nullptr;
+    hipEvent_t fork{}, join{};
+    if (aux) {
+        HCHK(H, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(fork);
+            H->last_error = "factorisation: cannot create an event";
+            return RAS_EHIP;
+        }
+        if (hipEventRecord(fork, st) != hipSuccess || hipStreamWaitEvent(aux, fork, 0) != hipSuccess)
+            aux = nullptr;          // everything on the caller's stream instead
+    }
+    for (size_t i = 0; i < H->lu_groups.size(); ++i) {
+        const auto &g = H->lu_groups[i];
+        launch_band_ldlt_mfma(g[0], g[3] != 0, H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
+                              H->d_F, H->d_status, i == 0 || !aux ? st : aux);
+    }
+    hipError_t e = hipGetLastError();
+    if (aux && e == hipSuccess) {
+        e = hipEventRecord(join, aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (e != hipSuccess) {
+        H->last_error = std::string("factorisation launch: ") + hipGetErrorString(e);
+        return RAS_EHIP;
+    }
+    return RAS_OK;
+}
+
 int build(ras_pml_handle *H, hipStream_t st) {
     // ---- concatenate problems
     H->nprob = static_cast<int>(H->plans.size());
@@ -448,28 +485,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
                          H->d_status, st);
         HCHK(H, hipGetLastError());
     } else {
-        // the largest window class on the caller's stream, the others beside
-        // it on the auxiliary stream (fork and join through events)
-        hipStream_t aux = H->lu_groups.size() > 1 ? aux_stream(H->device) : nullptr;
-        hipEvent_t fork{}, join{};
-        if (aux) {
-            HCHK(H, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-            HCHK(H, hipEventCreateWithFlags(&join, hipEventDisableTiming));
-            HCHK(H, hipEventRecord(fork, st));
-            HCHK(H, hipStreamWaitEvent(aux, fork, 0));
-        }
-        for (size_t i = 0; i < H->lu_groups.size(); ++i) {
-            const auto &g = H->lu_groups[i];
-            launch_band_ldlt_mfma(g[0], g[3] != 0, H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
-                                  H->d_F, H->d_status, i == 0 || !aux ? st : aux);
-            HCHK(H, hipGetLastError());
-        }
-        if (aux) {
-            HCHK(H, hipEventRecord(join, aux));
-            HCHK(H, hipStreamWaitEvent(st, join, 0));
-            (void)hipEventDestroy(fork);
-            (void)hipEventDestroy(join);
-        }
+        RCHK(factorise_c64(H, st));
     }
     if (timing) HCHK(H, hipEventRecord(e2, st));
     std::vector<int> status(H->nsub);
@@ -1421,16 +1437,17 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         return best;
     };
     int rc = RAS_OK;
-    // factorisation classes (complex64): both register budgets; the factor
-    // they write is the same
+    // factorisation classes (complex64): both register budgets, one class at
+    // a time with the others at their current choice, each timed as the whole
+    // factorisation (the classes run side by side there); the factor they
+    // write is the same
     if (!H->fp64)
         for (auto &g : H->lu_groups) {
             float t[2];
-            for (int occ = 0; occ < 2; ++occ)
-                t[occ] = timeit([&] {
-                    launch_band_ldlt_mfma(g[0], occ != 0, H->d_subs, H->d_lu_order + g[1], g[2],
-                                          H->d_lst, H->d_F, H->d_status, st);
-                }, 2);
+            for (int occ = 0; occ < 2; ++occ) {
+                g[3] = occ;
+                t[occ] = timeit([&] { (void)factorise_c64(H, st); }, 2);
+            }
             g[3] = t[1] <= t[0] ? 1 : 0;
         }
     // band solve: both prefetch depths on a zero right-hand side (the kernel
