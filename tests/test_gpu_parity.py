@@ -568,6 +568,19 @@ def test_batch_gmres_with_one_tolerance_per_problem():
     assert len(hist) >= max(its) + 1 and hist[-1] <= max(tols)
     with pytest.raises(rp.RasPmlError):
         rp.gmres_solve_batch(H, dev(np.concatenate(bs)), x, [1e-6, 0.0, 1e-6])
+    # a tolerance one problem cannot reach within maxit: RAS_ENOTCONV, the
+    # others still stop at theirs with the oracle's step counts
+    x.zero_()
+    k = gmres.gmres(lambda y: Rs[1].A @ y, Rs[1].apply, bs[1], rtol=1e-6, restart=50).iters
+    rc, its, rrs, _ = rp.gmres_solve_batch(H, dev(np.concatenate(bs)), x, [1e-4, 1e-14, 1e-6],
+                                           restart=50, maxit=max(k, 12))
+    assert rc == rp.RAS_ENOTCONV
+    conv = [rp.ras_pml_batch_result(H, p)[2] for p in range(3)]
+    assert conv[0] and not conv[1] and rrs[1] > 1e-14
+    for p, tol in ((0, 1e-4), (2, 1e-6)):
+        ref = gmres.gmres(lambda y: Rs[p].A @ y, Rs[p].apply, bs[p], rtol=tol, restart=50)
+        if ref.iters <= max(k, 12):
+            assert conv[p] and abs(its[p] - ref.iters) <= 1
 
 
 def test_device_memory_cache_reuses_released_blocks():
