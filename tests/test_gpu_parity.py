@@ -625,6 +625,35 @@ def test_device_memory_cache_reuses_released_blocks():
     rp.ras_pml_set_cache_limit(-1)
 
 
+def test_cached_blocks_are_not_shared_between_live_handles():
+    """Handles alive at the same time hold disjoint blocks: a destroyed
+    handle's blocks go to the next one while another handle keeps working,
+    and every apply matches the oracle."""
+    pa, pb = PROBLEMS["k40_two_slot"], PROBLEMS["ragged"]
+    Ra, Rb = oracle_for("k40_two_slot"), oracle_for("ragged")
+    va, vb = inputs.random_vector(pa.ndof, 21), inputs.random_vector(pb.ndof, 22)
+    wa, wb = Ra.apply(va), Rb.apply(vb)
+
+    def check(H, v, want, n):
+        z = torch.zeros(n, dtype=torch.complex128, device="cuda")
+        rp.ras_pml_apply(H, dev(v), z)
+        assert relerr(host(z), want) <= 1e-12
+
+    rp.ras_pml_set_cache_limit(-1)
+    H1 = setup_gpu(pa, rp.RAS_FP64)
+    H2 = setup_gpu(pb, rp.RAS_FP64)
+    check(H1, va, wa, pa.ndof)
+    check(H2, vb, wb, pb.ndof)
+    H1.close()
+    rp.ras_pml_fill_idle_cache(0xFF)
+    H3 = setup_gpu(pa, rp.RAS_FP64)          # takes H1's blocks, filled
+    check(H2, vb, wb, pb.ndof)               # H2 untouched by the fill and by H3
+    check(H3, va, wa, pa.ndof)
+    check(H2, vb, wb, pb.ndof)
+    H2.close()
+    H3.close()
+
+
 @pytest.mark.parametrize("name", ["k20", "ragged", "max_band", "clip_drch"])
 @pytest.mark.parametrize("precision", [rp.RAS_FP64, rp.RAS_MIXED])
 def test_results_do_not_depend_on_reused_memory(name, precision):
