@@ -374,6 +374,15 @@ int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, in
 const char *ras_pml_strerror(int status);
 const char *ras_pml_last_error(ras_pml_t H);
 
+/* Process teardown: waits for and destroys the library's auxiliary streams
+ * (one per device, used by the factorisation) and hands every idle cached
+ * device block back to the driver (ras_pml_empty_cache), so that nothing of
+ * the library outlives the HIP runtime or a profiler's tool library at
+ * exit.  Handles still alive keep working (an auxiliary stream is created
+ * again on demand) and release their blocks into the cache when destroyed.
+ * The Python binding calls it from an exit hook.  Returns RAS_OK.           */
+int ras_pml_shutdown(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,7 +48,18 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+_threads = None
+
+
+def set_threads(n=None):
+    """Host threads of the batched factorisation and solves (None: up to 16)."""
+    global _threads
+    _threads = None if n is None else max(1, int(n))
+
+
 def nthreads() -> int:
+    if _threads is not None:
+        return _threads
     return max(1, min(16, os.cpu_count() or 1))
 
 

@@ -114,6 +114,7 @@ SYMBOLS = [
     ("ras_pml_tuning", _I, [_P, _IP, _IP, _I, _IP]),
     ("ras_pml_strerror", ctypes.c_char_p, [_I]),
     ("ras_pml_last_error", ctypes.c_char_p, [_P]),
+    ("ras_pml_shutdown", _I, []),
 ]
 
 _lib = None
@@ -140,7 +141,16 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        import atexit
+        atexit.register(_shutdown)
     return _lib
+
+
+def _shutdown():
+    """Exit hook: the library's streams and idle device blocks go before
+    the HIP runtime (and any profiler's tool library) is torn down."""
+    if _lib is not None:
+        _lib.ras_pml_shutdown()
 
 
 def default_opts(**kw) -> Opts:

@@ -162,18 +162,35 @@ void dfree(void *p) {
 }
 
 // One auxiliary stream per device (default priority, created on first use,
-// kept for the life of the process): the smaller factorisation classes run
-// on it beside the largest, so their workgroups take the slots the largest
-// class leaves free in its last round.
+// kept until ras_pml_shutdown): the smaller factorisation classes run on it
+// beside the largest, so their workgroups take the slots the largest class
+// leaves free in its last round.
+std::mutex g_aux_mu;
+std::vector<hipStream_t> g_aux;
+
 hipStream_t aux_stream(int device) {
-    static std::mutex mu;
-    static std::vector<hipStream_t> streams;
-    std::lock_guard<std::mutex> g(mu);
+    std::lock_guard<std::mutex> g(g_aux_mu);
     if (device < 0) return nullptr;
-    if (streams.size() <= static_cast<size_t>(device)) streams.resize(device + 1, nullptr);
-    if (!streams[device] && hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking) != hipSuccess)
-        streams[device] = nullptr;
-    return streams[device];
+    if (g_aux.size() <= static_cast<size_t>(device)) g_aux.resize(device + 1, nullptr);
+    if (!g_aux[device] && hipStreamCreateWithFlags(&g_aux[device], hipStreamNonBlocking) != hipSuccess)
+        g_aux[device] = nullptr;
+    return g_aux[device];
+}
+
+// Destroys the auxiliary streams (each on its own device, after its work).
+void destroy_aux_streams() {
+    std::lock_guard<std::mutex> g(g_aux_mu);
+    int cur = -1;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (size_t d = 0; d < g_aux.size(); ++d) {
+        if (!g_aux[d]) continue;
+        if (hipSetDevice(static_cast<int>(d)) == hipSuccess) {
+            (void)hipStreamSynchronize(g_aux[d]);
+            (void)hipStreamDestroy(g_aux[d]);
+        }
+        g_aux[d] = nullptr;
+    }
+    if (have_cur) (void)hipSetDevice(cur);
 }
 
 // Waits for the handle's device, as hipFree would.
@@ -639,6 +656,10 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rt
                int *iters, double *relres, double *hist, hipStream_t st) {
     const int P = H->nprob;
     RCHK(ensure_krylov(H, m));
+    // the barrier-timeout flag of the fused Arnoldi step reports this call
+    // only (the barrier counters stay consistent after a timeout: every
+    // block still arrives)
+    if (H->arn_E > 0) HCHK(H, hipMemsetAsync(H->d_err, 0, sizeof(int), st));
     H->res_iters.assign(P, 0);
     H->res_relres.assign(P, 0.0);
     H->res_conv.assign(P, 0);
@@ -1550,5 +1571,11 @@ const char *ras_pml_strerror(int status) {
 }
 
 const char *ras_pml_last_error(ras_pml_t H) { return H ? H->last_error.c_str() : ""; }
+
+int ras_pml_shutdown(void) {
+    destroy_aux_streams();
+    (void)ras_pml_empty_cache(nullptr);
+    return RAS_OK;
+}
 
 }  // extern "C"

@@ -205,3 +205,9 @@ def test_width_rule_as_a_setup_option(L):
         rp.ras_pml_plan(80.0, 1 / 160, (160, 160), (4, 4), rp.RAS_WIDTH_RULE, 3, o)
     with pytest.raises(Exception):
         rp.ras_pml_plan(80.0, 1 / 160, (160, 160), (4, 4), -2, 3, rp.default_opts())
+
+
+def test_shutdown_needs_no_device(L):
+    """The exit hook's call: with nothing created it only returns."""
+    assert L.ras_pml_shutdown() == rp.RAS_OK
+    assert rp.ras_pml_cache_info() == (0, 0)

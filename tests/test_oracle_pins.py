@@ -523,3 +523,28 @@ def test_one_step_annihilates_the_residual_away_from_overlaps(case):
     # the plain (unweighted) additive sum has no such property
     r2 = b - R.A @ (u + R.apply(r, weighted=False))
     assert np.abs(r2[mask]).max() >= 1e-4 * sc
+
+
+@pytest.mark.slow
+def test_paper_source_radiates_where_the_gaussian_does_not():
+    """Source choice at k = 160, h = 1/320, 16 x 16 subdomains.  Section 4's
+    smoothed point source (width pi/(4k)) radiates: at 0.3 from the source the
+    field keeps more than 1e-2 of its peak (a cylindrical wave decays like
+    r^(-1/2)).  The Gaussian of width w = 0.05 radiates only a fraction of
+    order exp(-k^2 w^2 / 4) = exp(-16) of its local response u ~ -f/k^2, so
+    there the field is below 1e-5 of its peak."""
+    pb = geometry.config_problem("k160")
+    R = ras.RasPml(pb)
+    i0 = pb.G + pb.n_int // 2 - 1                  # the source's node (0-based unknown)
+    d = int(round(0.3 * pb.n_int))
+    ratio = {}
+    for name, f in (("paper", inputs.paper(pb.k, pb.n_int, pb.G)),
+                    ("gaussian", inputs.centre_gaussian(pb.n_int, pb.G, 0.05))):
+        b = fem.rhs(R.M1, f)
+        res = gmres.gmres(lambda x: R.A @ x, R.apply, b, rtol=1e-6, restart=100, maxit=500)
+        assert res.converged
+        u = np.abs(res.x).reshape(pb.Nc - 1, pb.Nc - 1)
+        assert np.unravel_index(u.argmax(), u.shape) == (i0, i0)
+        ratio[name] = u[i0, i0 + d] / u.max()
+    assert ratio["paper"] >= 1e-2, ratio
+    assert ratio["gaussian"] <= 1e-5, ratio
