@@ -225,6 +225,26 @@ int gmres_solve_batch(ras_pml_t H, const void *b, void *x, const double *rtol, i
 int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int maxit, int *iters,
                        double *relres, double *hist, void *stream);
 
+/* ras_pml_richardson for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc): same arguments,
+ * results and errors, computed by the same kernels in the same order (the
+ * results equal ras_pml_richardson's bit for bit), but every buffer of the
+ * solve -- the residual vector, the reduction partials and counters, the
+ * per-problem state and the residual history -- lives in one static device
+ * array of 64 MiB that the library holds on each device it runs on until
+ * the process ends; no hipMalloc, hipFree or other allocating call is made
+ * (host arrays are on the stack; the handle's own factors and local work
+ * vectors, allocated by setup, are used as they are).  Limits: at most 64
+ * problems per handle, and 16 * unknowns + 8 * problems * (maxit + 1) plus
+ * about 8 KB per problem must fit in the 64 MiB (k = 640 with 1.7 M unknowns
+ * and maxit 500 takes 27 MB); beyond them it returns RAS_EINVAL with a
+ * message.  Every call on a device shares that device's array, which keeps
+ * the last call's contents: calls that overlap in time on one device, on
+ * any handles or streams, race and must not be made.  Timing events
+ * (RAS_FLAG_TIMING) are not recorded.  Synchronises `stream`.            */
+int ras_pml_richardson_noalloc(ras_pml_t H, const void *b, void *x, double rtol, int maxit,
+                               int *iters, double *relres, double *hist, void *stream);
+
 /* Per-problem outcome of the last gmres_solve or ras_pml_richardson on a
  * batch handle. */
 int ras_pml_batch_result(ras_pml_t H, int p, int *iters, double *relres, int *converged);

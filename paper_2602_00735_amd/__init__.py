@@ -86,6 +86,7 @@ SYMBOLS = [
     ("gmres_solve", _I, [_P, _P, _P, _D, _I, _I, _IP, _DP, _DP, _P]),
     ("gmres_solve_batch", _I, [_P, _P, _P, _DP, _I, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
+    ("ras_pml_richardson_noalloc", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
     ("ras_pml_wsnet_create", _I, [_I, _IP, _I, ctypes.POINTER(_P)]),
@@ -350,6 +351,23 @@ def ras_pml_richardson(H: Handle, b, x, rtol=1e-6, maxit=500, stream=None, check
     hist = np.zeros(maxit + 1)
     rc = lib().ras_pml_richardson(H.ptr, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(it),
                                   ctypes.byref(rr), hist.ctypes.data_as(_DP), _stream(stream))
+    if check and rc not in (RAS_OK, RAS_ENOTCONV):
+        H._raise(rc)
+    return rc, it.value, rr.value, hist[:it.value + 1]
+
+
+def ras_pml_richardson_noalloc(H: Handle, b, x, rtol=1e-6, maxit=500, stream=None, check=True):
+    """ras_pml_richardson with every buffer in the library's static scratch
+    (no device allocation).  Returns (status, iters, relres, hist)."""
+    import numpy as np
+    _check_vec(b, H.ndof, "b")
+    _check_vec(x, H.ndof, "x")
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    rc = lib().ras_pml_richardson_noalloc(H.ptr, _ptr(b), _ptr(x), rtol, maxit, ctypes.byref(it),
+                                          ctypes.byref(rr), hist.ctypes.data_as(_DP),
+                                          _stream(stream))
     if check and rc not in (RAS_OK, RAS_ENOTCONV):
         H._raise(rc)
     return rc, it.value, rr.value, hist[:it.value + 1]

@@ -258,8 +258,8 @@ struct Timer {
     hipStream_t s;
     bool on;
     ras_pml_handle::EvPair p{};
-    Timer(ras_pml_handle *H_, int cat_, hipStream_t s_)
-        : H(H_), cat(cat_), s(s_), on((H_->flags & RAS_FLAG_TIMING) != 0) {
+    Timer(ras_pml_handle *H_, int cat_, hipStream_t s_, bool timed = true)
+        : H(H_), cat(cat_), s(s_), on(timed && (H_->flags & RAS_FLAG_TIMING) != 0) {
         if (on) {
             p = take_pair(H);
             (void)hipEventRecord(p.a, s);
@@ -623,16 +623,16 @@ int ensure_krylov(ras_pml_handle *H, int m) {
 int check_handle(ras_pml_handle *H) { return H ? RAS_OK : RAS_EINVAL; }
 
 int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st,
-             bool acc = false) {
+             bool acc = false, bool timed = true) {
     {
-        Timer t(H, C_SOLVE, st);
+        Timer t(H, C_SOLVE, st, timed);
         launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
                           H->nsub, active, v,
                           H->d_F, H->d_ybuf, H->d_xout, st);
     }
     HCHK(H, hipGetLastError());
     {
-        Timer t(H, C_SUM, st);
+        Timer t(H, C_SUM, st, timed);
         launch_pou_sum(H->fp64, H->d_probs, H->nprob, H->max_ndof, H->d_subs, active, H->d_pcnt,
                        H->d_pchunk, H->d_pw, H->d_xout, z, acc, st);
     }
@@ -842,16 +842,148 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rt
     return RAS_OK;
 }
 
+// Buffers of one fixed-point solve.  ras_pml_richardson takes them from
+// the handle (allocated on first use), ras_pml_richardson_noalloc from the
+// library's static scratch array; the host arrays hold nprob values.
+struct RichWork {
+    double2 *r;               // residual b - A x (all unknowns)
+    int *active;              // per problem: 1 while it iterates
+    RState *rs;               // per problem: state of the iteration
+    double *rhist;            // per problem: maxit + 1 relative residuals
+    double2 *redout;          // per problem: reduction result
+    double2 *partials;        // per problem: kRedBlocksHost partial sums
+    unsigned int *counters;   // per problem: arrivals (0 between reductions)
+    RState *h_rs;             // host: rs
+    double2 *h_red;           // host: redout
+    int *h_need;              // host: active
+    double *h_bnorm, *h_rel0; // host: ||b||, relative residual of x0
+    bool timed;               // record timing events (RAS_FLAG_TIMING)
+};
+
+// Deterministic per-problem reduction into W.h_red (synchronises).
+int reduce_sync_w(ras_pml_handle *H, const RichWork &W, const double2 *a, hipStream_t st) {
+    launch_reduce(H->d_probs, H->nprob, nullptr, a, nullptr, 0, W.redout, W.partials, W.counters,
+                  st);
+    HCHK(H, hipGetLastError());
+    HCHK(H, hipMemcpyAsync(W.h_red, W.redout, sizeof(double2) * H->nprob, hipMemcpyDeviceToHost,
+                           st));
+    HCHK(H, hipStreamSynchronize(st));
+    return RAS_OK;
+}
+
 // Algorithm 1 as an iteration: x <- x + B^{-1} (b - A x) for every problem
 // not yet converged.  The correction is summed straight into x (the PoU sum
 // in accumulate mode), so a step is one batched solve, one sum, one
 // residual and one reduction.  The stopping test runs on the device
 // (k_rich_update clears a finished problem's active flag, which every later
 // launch reads); the host enqueues steps ahead and looks at the flags every
-// kSyncSteps steps.
-int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol, int maxit,
-                    int *iters, double *relres, double *hist, hipStream_t st) {
+// kSyncSteps steps.  Allocates nothing (W holds every buffer).
+int richardson_impl(ras_pml_handle *H, const RichWork &W, const double2 *b, double2 *x,
+                    double rtol, int maxit, int *iters, double *relres, double *hist,
+                    hipStream_t st) {
     constexpr int kSyncSteps = 8;
+    const int P = H->nprob;
+    H->res_iters.assign(P, 0);
+    H->res_relres.assign(P, 0.0);
+    H->res_conv.assign(P, 0);
+    double *bnorm = W.h_bnorm, *rel0 = W.h_rel0;
+    int *need = W.h_need;
+    RCHK(reduce_sync_w(H, W, b, st));
+    for (int p = 0; p < P; ++p) {
+        bnorm[p] = std::sqrt(W.h_red[p].x);
+        if (!std::isfinite(bnorm[p])) {
+            H->last_error = "right-hand side is not finite";
+            return RAS_ENONFINITE;
+        }
+        if (bnorm[p] == 0.0) {
+            const DevProb &D = H->hprobs[p];
+            HCHK(H, hipMemsetAsync(x + D.dof_off, 0, sizeof(double2) * D.ndof, st));
+        }
+    }
+    launch_spmv(H->d_probs, P, H->max_ndof, nullptr, H->d_coef, H->ntot, x, b, W.r, st);
+    HCHK(H, hipGetLastError());
+    RCHK(reduce_sync_w(H, W, W.r, st));
+    int nneed = 0;
+    for (int p = 0; p < P; ++p) {
+        const double beta = std::sqrt(W.h_red[p].x);
+        if (!std::isfinite(beta)) {
+            H->last_error = "initial residual is not finite";
+            return RAS_ENONFINITE;
+        }
+        rel0[p] = bnorm[p] > 0.0 ? beta / bnorm[p] : 0.0;
+        need[p] = (bnorm[p] > 0.0 && beta > rtol * bnorm[p] && maxit > 0) ? 1 : 0;
+        nneed += need[p];
+        W.h_rs[p] = RState{bnorm[p] > 0.0 ? bnorm[p] : 1.0, rel0[p], 0, 0};
+    }
+    HCHK(H, hipMemcpyAsync(W.rs, W.h_rs, sizeof(RState) * P, hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(W.active, need, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    for (int it = 1; nneed > 0 && it <= maxit; ++it) {
+        RCHK(do_apply(H, W.r, x, W.active, st, true, W.timed));
+        launch_spmv(H->d_probs, P, H->max_ndof, W.active, H->d_coef, H->ntot, x, b, W.r, st);
+        launch_reduce(H->d_probs, P, nullptr, W.r, nullptr, 0, W.redout, W.partials, W.counters,
+                      st);
+        launch_rich_update(W.rs, W.active, W.redout, W.rhist, P, maxit, rtol, st);
+        HCHK(H, hipGetLastError());
+        if (it % kSyncSteps != 0 && it != maxit) continue;
+        HCHK(H, hipMemcpyAsync(need, W.active, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+        HCHK(H, hipStreamSynchronize(st));
+        nneed = 0;
+        for (int p = 0; p < P; ++p) nneed += need[p];
+    }
+    // per-problem outcome and histories
+    HCHK(H, hipMemcpyAsync(W.h_rs, W.rs, sizeof(RState) * P, hipMemcpyDeviceToHost, st));
+    int steps = 0;
+    HCHK(H, hipStreamSynchronize(st));
+    bool nonfinite = false;
+    for (int p = 0; p < P; ++p) {
+        const RState &R = W.h_rs[p];
+        H->res_iters[p] = R.iters;
+        H->res_relres[p] = R.nonfinite ? HUGE_VAL : R.relres;
+        H->res_conv[p] = (!R.nonfinite && R.relres <= rtol) || bnorm[p] == 0.0 ? 1 : 0;
+        nonfinite = nonfinite || R.nonfinite;
+        steps = std::max(steps, R.iters);
+    }
+    if (hist) {
+        // the worst problem after every step (a problem that stopped keeps
+        // its last value), read back one problem and one chunk at a time
+        for (int t = 0; t <= steps; ++t) hist[t] = 0.0;
+        constexpr int kChunk = 512;
+        double buf[kChunk];
+        for (int p = 0; p < P; ++p) {
+            const int ip = H->res_iters[p];
+            hist[0] = std::max(hist[0], rel0[p]);
+            for (int t0 = 1; t0 <= ip; t0 += kChunk) {
+                const int cnt = std::min(kChunk, ip - t0 + 1);
+                HCHK(H, hipMemcpy(buf, W.rhist + static_cast<size_t>(p) * (maxit + 1) + t0,
+                                  sizeof(double) * cnt, hipMemcpyDeviceToHost));
+                for (int u = 0; u < cnt; ++u) hist[t0 + u] = std::max(hist[t0 + u], buf[u]);
+            }
+            if (ip < steps) {
+                double lastv = rel0[p];
+                if (ip > 0)
+                    HCHK(H, hipMemcpy(&lastv, W.rhist + static_cast<size_t>(p) * (maxit + 1) + ip,
+                                      sizeof(double), hipMemcpyDeviceToHost));
+                for (int t = ip + 1; t <= steps; ++t) hist[t] = std::max(hist[t], lastv);
+            }
+        }
+    }
+    if (iters) *iters = steps;
+    if (relres) *relres = *std::max_element(H->res_relres.begin(), H->res_relres.end());
+    if (nonfinite) {                   // a diverging iteration overflows
+        H->last_error = "iterate is not finite";
+        return RAS_ENONFINITE;
+    }
+    for (int p = 0; p < P; ++p)
+        if (!H->res_conv[p]) {
+            H->last_error = "maximum number of iterations reached";
+            return RAS_ENOTCONV;
+        }
+    return RAS_OK;
+}
+
+// ras_pml_richardson's buffers: the handle's own, allocated on first use
+// (the history grows with maxit).
+int rich_work_handle(ras_pml_handle *H, int maxit, RichWork &W) {
     const int P = H->nprob;
     RCHK(ensure_krylov(H, 1));
     if (!H->d_rs) {
@@ -866,93 +998,81 @@ int richardson_impl(ras_pml_handle *H, const double2 *b, double2 *x, double rtol
         RCHK(dalloc(H, &H->d_rhist, sizeof(double) * static_cast<size_t>(P) * (maxit + 1)));
         H->rhist_cap = maxit;
     }
-    H->res_iters.assign(P, 0);
-    H->res_relres.assign(P, 0.0);
-    H->res_conv.assign(P, 0);
-    std::vector<double> bnorm(P);
-    std::vector<int> need(P, 0);
-    RCHK(reduce_sync(H, b, nullptr, 0, st));
-    for (int p = 0; p < P; ++p) {
-        bnorm[p] = std::sqrt(H->h_red[p].x);
-        if (!std::isfinite(bnorm[p])) {
-            H->last_error = "right-hand side is not finite";
-            return RAS_ENONFINITE;
+    W.r = H->d_r;
+    W.active = H->d_active;
+    W.rs = H->d_rs;
+    W.rhist = H->d_rhist;
+    W.redout = H->d_redout;
+    W.partials = H->d_partials;
+    W.counters = H->d_counters;
+    W.h_rs = H->h_rs;
+    W.h_red = H->h_red;
+    W.timed = true;
+    return RAS_OK;
+}
+
+// ---- ras_pml_richardson_noalloc: every buffer of the solve in one static
+// device array (each device that runs it holds its own copy until the
+// process ends).  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current.
+constexpr size_t kScratchBytes = static_cast<size_t>(64) << 20;
+constexpr int kNoAllocMaxProb = 64;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(ras_pml_handle *H, unsigned char **out) {
+    *out = nullptr;
+    if (H->device < 0 || H->device >= kMaxDevices) {
+        H->last_error = "device index beyond the scratch table";
+        return RAS_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[H->device]) {
+        int cur = -1;
+        HCHK(H, hipGetDevice(&cur));
+        if (cur != H->device) HCHK(H, hipSetDevice(H->device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != H->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || ptr == nullptr) {
+            H->last_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return RAS_EHIP;
         }
-        if (bnorm[p] == 0.0) {
-            const DevProb &D = H->hprobs[p];
-            HCHK(H, hipMemsetAsync(x + D.dof_off, 0, sizeof(double2) * D.ndof, st));
-        }
+        g_scratch_dev[H->device] = static_cast<unsigned char *>(ptr);
     }
-    launch_spmv(H->d_probs, P, H->max_ndof, nullptr, H->d_coef, H->ntot, x, b, H->d_r, st);
-    HCHK(H, hipGetLastError());
-    RCHK(reduce_sync(H, H->d_r, nullptr, 0, st));
-    std::vector<double> rel0(P);
-    int nneed = 0;
-    for (int p = 0; p < P; ++p) {
-        const double beta = std::sqrt(H->h_red[p].x);
-        if (!std::isfinite(beta)) {
-            H->last_error = "initial residual is not finite";
-            return RAS_ENONFINITE;
-        }
-        rel0[p] = bnorm[p] > 0.0 ? beta / bnorm[p] : 0.0;
-        need[p] = (bnorm[p] > 0.0 && beta > rtol * bnorm[p] && maxit > 0) ? 1 : 0;
-        nneed += need[p];
-        H->h_rs[p] = RState{bnorm[p] > 0.0 ? bnorm[p] : 1.0, rel0[p], 0, 0};
+    *out = g_scratch_dev[H->device];
+    return RAS_OK;
+}
+
+// Lays the buffers of one solve out in the scratch array (256-byte aligned
+// pieces); RAS_EINVAL when they do not fit.
+int rich_work_scratch(ras_pml_handle *H, unsigned char *base, int maxit, RichWork &W) {
+    const size_t P = static_cast<size_t>(H->nprob);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~static_cast<size_t>(255);
+        return base + o;
+    };
+    W.r = reinterpret_cast<double2 *>(take(sizeof(double2) * static_cast<size_t>(H->ntot)));
+    W.partials = reinterpret_cast<double2 *>(take(sizeof(double2) * P * kRedBlocksHost));
+    W.redout = reinterpret_cast<double2 *>(take(sizeof(double2) * P));
+    W.counters = reinterpret_cast<unsigned int *>(take(sizeof(unsigned int) * P));
+    W.rs = reinterpret_cast<RState *>(take(sizeof(RState) * P));
+    W.active = reinterpret_cast<int *>(take(sizeof(int) * P));
+    W.rhist = reinterpret_cast<double *>(take(sizeof(double) * P * (static_cast<size_t>(maxit) + 1)));
+    if (off > kScratchBytes) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "the fixed-point solve needs %zu bytes of scratch (%lld unknowns, %d "
+                      "problems, maxit %d); the static scratch holds %zu",
+                      off, H->ntot, H->nprob, maxit, kScratchBytes);
+        H->last_error = buf;
+        return RAS_EINVAL;
     }
-    HCHK(H, hipMemcpyAsync(H->d_rs, H->h_rs, sizeof(RState) * P, hipMemcpyHostToDevice, st));
-    HCHK(H, hipMemcpyAsync(H->d_active, need.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
-    for (int it = 1; nneed > 0 && it <= maxit; ++it) {
-        RCHK(do_apply(H, H->d_r, x, H->d_active, st, true));
-        launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, H->ntot, x, b, H->d_r, st);
-        launch_reduce(H->d_probs, P, nullptr, H->d_r, nullptr, 0, H->d_redout, H->d_partials,
-                      H->d_counters, st);
-        launch_rich_update(H->d_rs, H->d_active, H->d_redout, H->d_rhist, P, maxit, rtol, st);
-        HCHK(H, hipGetLastError());
-        if (it % kSyncSteps != 0 && it != maxit) continue;
-        HCHK(H, hipMemcpyAsync(need.data(), H->d_active, sizeof(int) * P, hipMemcpyDeviceToHost, st));
-        HCHK(H, hipStreamSynchronize(st));
-        nneed = 0;
-        for (int p = 0; p < P; ++p) nneed += need[p];
-    }
-    // per-problem outcome and histories
-    HCHK(H, hipMemcpyAsync(H->h_rs, H->d_rs, sizeof(RState) * P, hipMemcpyDeviceToHost, st));
-    int steps = 0;
-    HCHK(H, hipStreamSynchronize(st));
-    bool nonfinite = false;
-    for (int p = 0; p < P; ++p) {
-        const RState &R = H->h_rs[p];
-        H->res_iters[p] = R.iters;
-        H->res_relres[p] = R.nonfinite ? HUGE_VAL : R.relres;
-        H->res_conv[p] = (!R.nonfinite && R.relres <= rtol) || bnorm[p] == 0.0 ? 1 : 0;
-        nonfinite = nonfinite || R.nonfinite;
-        steps = std::max(steps, R.iters);
-    }
-    if (hist) {
-        std::vector<double> rh(static_cast<size_t>(P) * (maxit + 1));
-        if (steps > 0)
-            HCHK(H, hipMemcpy(rh.data(), H->d_rhist, sizeof(double) * rh.size(),
-                              hipMemcpyDeviceToHost));
-        for (int t = 0; t <= steps; ++t) {
-            double worst = 0.0;
-            for (int p = 0; p < P; ++p) {
-                const int tp = std::min(t, H->res_iters[p]);
-                const double v = tp == 0 ? rel0[p] : rh[static_cast<size_t>(p) * (maxit + 1) + tp];
-                worst = std::max(worst, v);
-            }
-            hist[t] = worst;
-        }
-    }
-    if (iters) *iters = steps;
-    if (relres) *relres = *std::max_element(H->res_relres.begin(), H->res_relres.end());
-    if (nonfinite) {                   // a diverging iteration overflows
-        H->last_error = "iterate is not finite";
-        return RAS_ENONFINITE;
-    }
-    for (int p = 0; p < P; ++p)
-        if (!H->res_conv[p]) {
-            H->last_error = "maximum number of iterations reached";
-            return RAS_ENOTCONV;
-        }
     return RAS_OK;
 }
 
@@ -974,6 +1094,10 @@ int setup_common(int nprob, const double *k, const double *h, const int *grid, c
     std::unique_ptr<ras_pml_handle> H(new (std::nothrow) ras_pml_handle());
     if (!H) return RAS_ENOMEM;
     H->plans.resize(nprob);
+    // per-problem results: sized here so that no solve allocates host memory
+    H->res_iters.reserve(nprob);
+    H->res_relres.reserve(nprob);
+    H->res_conv.reserve(nprob);
     for (int p = 0; p < nprob; ++p) {
         std::string err;
         int rc = plan_problem(k[p], h[p], grid + 2 * p, subs + 2 * p, overlap[p], pml[p], o,
@@ -1314,12 +1438,52 @@ int ras_pml_richardson(ras_pml_t H, const void *b, void *x, double rtol, int max
         return RAS_EINVAL;
     }
     try {
-        return richardson_impl(H, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
-                               maxit, iters, relres, hist, as_stream(stream));
+        RichWork W{};
+        RCHK(rich_work_handle(H, maxit, W));
+        std::vector<int> need(H->nprob, 0);
+        std::vector<double> bnorm(H->nprob), rel0(H->nprob);
+        W.h_need = need.data();
+        W.h_bnorm = bnorm.data();
+        W.h_rel0 = rel0.data();
+        return richardson_impl(H, W, static_cast<const double2 *>(b), static_cast<double2 *>(x),
+                               rtol, maxit, iters, relres, hist, as_stream(stream));
     } catch (const std::exception &e) {
         H->last_error = e.what();
         return RAS_ENOMEM;
     }
+}
+
+int ras_pml_richardson_noalloc(ras_pml_t H, const void *b, void *x, double rtol, int maxit,
+                               int *iters, double *relres, double *hist, void *stream) {
+    if (!H) return RAS_EINVAL;
+    if (!b || !x || b == x || !(rtol > 0.0) || maxit < 0) {
+        H->last_error = "invalid richardson arguments";
+        return RAS_EINVAL;
+    }
+    if (H->nprob > kNoAllocMaxProb) {
+        H->last_error = "ras_pml_richardson_noalloc takes at most 64 problems per handle";
+        return RAS_EINVAL;
+    }
+    unsigned char *base = nullptr;
+    RCHK(scratch_address(H, &base));
+    RichWork W{};
+    RCHK(rich_work_scratch(H, base, maxit, W));
+    const hipStream_t st = as_stream(stream);
+    // the reduction counters must start at zero; the rest is written before
+    // it is read (the array keeps the previous call's contents)
+    HCHK(H, hipMemsetAsync(W.counters, 0, sizeof(unsigned int) * H->nprob, st));
+    RState h_rs[kNoAllocMaxProb];
+    double2 h_red[kNoAllocMaxProb];
+    int need[kNoAllocMaxProb];
+    double bnorm[kNoAllocMaxProb], rel0[kNoAllocMaxProb];
+    W.h_rs = h_rs;
+    W.h_red = h_red;
+    W.h_need = need;
+    W.h_bnorm = bnorm;
+    W.h_rel0 = rel0;
+    W.timed = false;
+    return richardson_impl(H, W, static_cast<const double2 *>(b), static_cast<double2 *>(x), rtol,
+                           maxit, iters, relres, hist, st);
 }
 
 static int single_grid(ras_pml_t H, int *grid) {
