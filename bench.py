@@ -158,9 +158,9 @@ def main():
             tuning[name] = rp.ras_pml_tuning(Ht)
             Ht.close()
 
-    def one_solve(precision, timing=False, f=f):
-        opts = rp.default_opts(global_pml=G, precision=precision,
-                               flags=rp.RAS_FLAG_TIMING if timing else 0)
+    def one_solve(precision, timing=False, f=f, graph=False, repeat=False):
+        flags = (rp.RAS_FLAG_TIMING if timing else 0) | (rp.RAS_FLAG_GRAPH_STEPS if graph else 0)
+        opts = rp.default_opts(global_pml=G, precision=precision, flags=flags)
         if cache is not None:
             opts.tune_cache = os.fsencode(cache)
         t0 = time.perf_counter()
@@ -173,9 +173,20 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         stats = rp.ras_pml_get_stats(H)
+        res = dict(rc=rc, iters=it, relres=rr, setup_s=t1 - t0, solve_s=t2 - t1,
+                   total_s=t2 - t0, stats=stats, x=x, alloc_s=stats["alloc_ms"] / 1000.0)
+        if repeat:
+            # a second solve on the same handle (Krylov workspace and, with
+            # graph steps, the recorded graph already there)
+            x2 = torch.zeros_like(f)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            rc2, it2, _, _ = rp.gmres_solve(H, b, x2, rtol=1e-6, restart=100, maxit=500)
+            torch.cuda.synchronize()
+            res["repeat_solve_s"] = time.perf_counter() - t3
+            res["repeat_same"] = bool(rc2 == rc and it2 == it and torch.equal(x2, x))
         H.close()
-        return dict(rc=rc, iters=it, relres=rr, setup_s=t1 - t0, solve_s=t2 - t1,
-                    total_s=t2 - t0, stats=stats, x=x, alloc_s=stats["alloc_ms"] / 1000.0)
+        return res
 
     # ---------------------------------------------------------------- warmup
     for _ in range(args.warmup):
@@ -194,6 +205,28 @@ def main():
     # per-kernel breakdown: one more solve, untimed, with per-launch events
     st = one_solve(rp.RAS_MIXED, timing=True)["stats"]
     progress("timed steps done: %.4f s per solve" % (ms_per_step / 1000.0))
+
+    # ---------------------------------------------------------------- graph steps
+    # the same solve with every eight FGMRES steps replayed from a HIP graph
+    # (RAS_FLAG_GRAPH_STEPS), timed like the steps above, and a second solve
+    # on each handle (the eager and the graph-replayed one)
+    one_solve(rp.RAS_MIXED, graph=True)
+    ng = max(3, min(args.steps, 10))
+    gruns = [one_solve(rp.RAS_MIXED, graph=True, repeat=True) for _ in range(ng)]
+    eruns = [one_solve(rp.RAS_MIXED, repeat=True) for _ in range(3)]
+    g_ms = 1000.0 * float(np.median([r["total_s"] for r in gruns]))
+    graph_blk = {
+        "ms_per_step": round(g_ms, 3),
+        "solve_s": round(float(np.median([r["solve_s"] for r in gruns])), 5),
+        "repeat_solve_s": round(float(np.median([r["repeat_solve_s"] for r in gruns])), 5),
+        "eager_repeat_solve_s": round(float(np.median([r["repeat_solve_s"] for r in eruns])), 5),
+        "eager_solve_s": round(float(np.median([r["solve_s"] for r in runs])), 5),
+        "iters": gruns[-1]["iters"],
+        "identical_to_eager": bool(all(torch.equal(r["x"], mixed["x"]) for r in gruns)
+                                   and all(r["repeat_same"] for r in gruns + eruns)),
+        "note": "ms_per_step: median of setup + first solve (which records the graph) over "
+                "%d handles; repeat: a second solve on the same handle" % ng}
+    progress("graph-replayed steps done: %.4f s per solve" % (g_ms / 1000.0))
 
     # ---------------------------------------------------------------- roofline
     # the dominant kernel alone: back-to-back batched band solves on the
@@ -254,6 +287,7 @@ def main():
                       "givens": round(st["givens_ms"], 3)},
                   "setup_assemble_ms": round(st["setup_assemble_ms"], 3),
                   "setup_factor_ms": round(st["setup_factor_ms"], 3)},
+        "graph_steps": graph_blk,
         "tuning": {name: {"band_solve_deep_prefetch": t["solve_deep"],
                           "factor_classes": [{"tiles": g[0], "subdomains": g[1],
                                               "128_register_variant": g[2]} for g in t["ldlt"]]}

@@ -56,7 +56,10 @@ enum { RAS_BC_IMP = 0, RAS_BC_DRCH = 1 };          /* local boundary condition *
 enum { RAS_POU_LINEAR = 0, RAS_POU_BOOLEAN = 1 };  /* partition of unity       */
 enum { RAS_MIXED = 0, RAS_FP64 = 1 };              /* local factor precision   */
 enum { RAS_FLAG_TIMING = 1,                        /* record HIP events        */
-       RAS_FLAG_UNFUSED_ARNOLDI = 2 };             /* one launch per MGS step  */
+       RAS_FLAG_UNFUSED_ARNOLDI = 2,               /* one launch per MGS step  */
+       RAS_FLAG_GRAPH_STEPS = 4 };                 /* GMRES steps replayed
+                                                      from a HIP graph (see
+                                                      gmres_solve)             */
 
 typedef struct ras_pml_handle *ras_pml_t;
 
@@ -193,6 +196,12 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream);
  * For a batch handle every problem is solved independently with its own
  * stopping test; iters/relres then describe the slowest problem and
  * ras_pml_batch_result gives each one.  Synchronises `stream`.
+ * Steps are enqueued eight at a time between looks at the convergence
+ * flags; with RAS_FLAG_GRAPH_STEPS (and the fused Arnoldi step, without
+ * RAS_FLAG_TIMING) the eight steps are one launch of a HIP graph, recorded
+ * on the handle's own stream at the first solve (and again when restart or
+ * the Krylov workspace changes) and replayed: the same kernels with the same
+ * arguments as the eager steps, so the results are the same bit for bit.
  * Errors: RAS_EINVAL, RAS_ENONFINITE, RAS_ENOTCONV, RAS_EBREAKDOWN,
  * RAS_ENOMEM, RAS_EHIP.                                                    */
 int gmres_solve(ras_pml_t H, const void *b, void *x, double rtol, int restart, int maxit,
@@ -390,6 +399,24 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream);
  * cap_groups of them as (tiles per side, subdomains, 128-register variant
  * 0/1) triples in groups.  Errors: RAS_EINVAL.                             */
 int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, int *n_groups);
+
+/* Kernel variant choices of a handle (performance only: every variant
+ * computes the same values, bit for bit):
+ *   RAS_KNOB_SOLVE_DEEP   band-solve prefetch depth: 1 = 16 vectors (32 for
+ *                         a complex64 handle whose bands all have W <= 64),
+ *                         0 = half of that (default 1);
+ *   RAS_KNOB_SOLVE_QUEUE  band-solve dispatch: 0 = one wave per subdomain,
+ *                         largest first, placed by the hardware dispatcher;
+ *                         1 = one persistent wave per SIMD taking subdomains,
+ *                         largest first, from an atomic work counter (used
+ *                         only when there are more subdomains than SIMDs)
+ *                         (default 0).
+ * ras_pml_set_knob takes effect for the handle's later launches;
+ * ras_pml_autotune sets both from measurements.  Errors: RAS_EINVAL (no
+ * handle, unknown knob or value).                                          */
+enum { RAS_KNOB_SOLVE_DEEP = 0, RAS_KNOB_SOLVE_QUEUE = 1 };
+int ras_pml_set_knob(ras_pml_t H, int knob, int value);
+int ras_pml_get_knob(ras_pml_t H, int knob, int *value);
 
 const char *ras_pml_strerror(int status);
 const char *ras_pml_last_error(ras_pml_t H);

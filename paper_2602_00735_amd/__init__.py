@@ -21,6 +21,9 @@ RAS_POU_LINEAR, RAS_POU_BOOLEAN = 0, 1
 RAS_MIXED, RAS_FP64 = 0, 1
 RAS_FLAG_TIMING = 1
 RAS_FLAG_UNFUSED_ARNOLDI = 2
+RAS_FLAG_GRAPH_STEPS = 4
+RAS_KNOB_SOLVE_DEEP = 0
+RAS_KNOB_SOLVE_QUEUE = 1
 RAS_DESC_INTS = 24
 RAS_WIDTH_RULE = -1
 
@@ -87,6 +90,8 @@ SYMBOLS = [
     ("gmres_solve_batch", _I, [_P, _P, _P, _DP, _I, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_richardson_noalloc", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
+    ("ras_pml_set_knob", _I, [_P, _I, _I]),
+    ("ras_pml_get_knob", _I, [_P, _I, _IP]),
     ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
     ("ras_pml_wsnet_create", _I, [_I, _IP, _I, ctypes.POINTER(_P)]),
@@ -371,6 +376,21 @@ def ras_pml_richardson_noalloc(H: Handle, b, x, rtol=1e-6, maxit=500, stream=Non
     if check and rc not in (RAS_OK, RAS_ENOTCONV):
         H._raise(rc)
     return rc, it.value, rr.value, hist[:it.value + 1]
+
+
+def ras_pml_set_knob(H: Handle, knob, value):
+    """Kernel variant choice of a handle (RAS_KNOB_*)."""
+    rc = lib().ras_pml_set_knob(H.ptr, int(knob), int(value))
+    if rc:
+        H._raise(rc)
+
+
+def ras_pml_get_knob(H: Handle, knob):
+    v = ctypes.c_int(0)
+    rc = lib().ras_pml_get_knob(H.ptr, int(knob), ctypes.byref(v))
+    if rc:
+        H._raise(rc)
+    return v.value
 
 
 def ras_pml_width_rule(k, h, C, k0=150.0):

@@ -34,10 +34,10 @@ bool ldlt_mfma_default_occ(int NT);
 void launch_band_ldlt_mfma(int, bool, const DevSub *, const int *, int, const double2 *, void *,
                            int *, hipStream_t);
 void launch_band_solve(bool, bool, int, const DevProb *, const DevSub *, const int *, int,
-                       const int *,
-                       const double2 *, const void *, void *, void *, hipStream_t);
+                       const int *, const SolveSrc &, const void *, void *, void *,
+                       const SolveDispatch &, hipStream_t);
 void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
-                    const int *, const int *, const double *, const void *, double2 *, bool,
+                    const int *, const int *, const double *, const void *, const SumDst &, bool,
                     hipStream_t);
 void launch_export_local(bool, const DevSub *, int, int, const void *, double2 *, hipStream_t);
 void launch_spmv(const DevProb *, int, long long, const int *, const double2 *, long long,
@@ -51,8 +51,8 @@ void launch_normalize(const DevProb *, int, long long, const KState *, double2 *
 void launch_start_cycle(const DevProb *, int, long long, const KState *, const double2 *,
                         double2 *, hipStream_t);
 void launch_rich_update(RState *, int *, const double2 *, double *, int, int, double, hipStream_t);
-void launch_givens(KState *, int, int, int, double2 *, double *, double2 *, double2 *, double *,
-                   int *, hipStream_t);
+void launch_givens(KState *, int, int, double2 *, double *, double2 *, double2 *, double *, int *,
+                   hipStream_t);
 void launch_solve_y(const KState *, int, int, const double2 *, const double2 *, double2 *,
                     hipStream_t);
 void launch_update_x(const DevProb *, int, long long, const KState *, const int *, int,
@@ -60,10 +60,10 @@ void launch_update_x(const DevProb *, int, long long, const KState *, const int 
 int arnoldi_variants();
 int arnoldi_variant_e(int variant);
 int arnoldi_block_capacity(int variant, int *blocks_per_cu);
-hipError_t launch_arnoldi(int variant, int nblocks, const DevProb *, const KState *, const ArnoldiBlock *,
-                          const double2 *, long long, const double2 *, double2 *, int, int,
-                          double2 *, double2 *, unsigned long long *, unsigned long long, int *,
-                          int, hipStream_t);
+hipError_t launch_arnoldi(int variant, int nblocks, const DevProb *, const KState *,
+                          const ArnoldiBlock *, const double2 *, long long, const double2 *,
+                          double2 *, int, double2 *, double2 *, unsigned long long *,
+                          unsigned long long *, int *, int, hipStream_t);
 
 constexpr int kRedBlocksHost = 512;
 
@@ -89,6 +89,9 @@ struct ras_pml_handle {
     std::vector<int> lu_order;
     std::vector<std::array<int, 4>> lu_groups;
     bool solve_deep = true;    // band-solve prefetch depth variant
+    bool solve_queue = false;  // band-solve dispatch: persistent waves and a work queue
+    int solve_waves = 0;       // waves of the persistent band solve (one per SIMD)
+    bool graph_steps = false;  // GMRES steps replayed from a graph (RAS_FLAG_GRAPH_STEPS)
     std::string arch;          // gfx name of the device (tuning cache keys)
     std::string tune_cache;    // opts.tune_cache (empty: none)
     long long skipped_steps = 0;   // GMRES steps enqueued after every problem had stopped
@@ -109,6 +112,7 @@ struct ras_pml_handle {
     double2 *d_lst = nullptr;
     void *d_F = nullptr, *d_ybuf = nullptr, *d_xout = nullptr;
     int *d_status = nullptr;
+    unsigned int *d_queue = nullptr;   // work counter of the persistent band solve (2 words)
 
     // Krylov workspace
     int m_alloc = 0;
@@ -129,8 +133,16 @@ struct ras_pml_handle {
     ArnoldiBlock *d_ablocks = nullptr;
     double2 *d_part2 = nullptr;
     unsigned long long *d_bar = nullptr;
-    unsigned long long bar_base = 0;
+    size_t bar_words = 0;
+    unsigned long long *d_epoch = nullptr;   // barrier epoch reached (device)
+    bool bar_reset = false;    // a barrier wait ran out: clear the counters first
     int *d_err = nullptr;
+    // one graph of kGraphSteps FGMRES steps (recorded on cap_stream)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    int graph_m = 0;
+    const void *graph_V = nullptr;
     KState *h_ks = nullptr;        // pinned
     int *h_err = nullptr;          // pinned
     double2 *h_red = nullptr;      // pinned
@@ -298,10 +310,14 @@ ras_pml_handle::~ras_pml_handle() {
     void *ptrs[] = {d_probs, d_subs,  d_order, d_lu_order, d_pcnt, d_pchunk, d_pw,     d_coef,     d_lst,
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
-                    d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err, d_rs, d_rhist};
+                    d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err, d_rs, d_rhist,
+                    d_queue, d_epoch};
     bool any = false;
     for (void *p : ptrs) any = any || p != nullptr;
     if (any) idle_device(device);
+    if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    if (step_graph) (void)hipGraphDestroy(step_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *p : ptrs) dfree(p);
     if (h_ks) (void)hipHostFree(h_ks);
     if (h_rs) (void)hipHostFree(h_rs);
@@ -468,6 +484,13 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_ybuf, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_xout, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_status, sizeof(int) * H->nsub));
+    RCHK(dalloc(H, &H->d_queue, sizeof(unsigned int) * 2));
+    HCHK(H, hipMemsetAsync(H->d_queue, 0, sizeof(unsigned int) * 2, st));
+    {
+        int cus = 0;
+        HCHK(H, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, H->device));
+        H->solve_waves = 4 * cus;          // one wave per SIMD
+    }
     HCHK(H, hipMemcpyAsync(H->d_probs, H->hprobs.data(), sizeof(DevProb) * H->nprob,
                            hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_subs, H->hsubs.data(), sizeof(DevSub) * H->nsub,
@@ -570,13 +593,15 @@ int plan_arnoldi(ras_pml_handle *H) {
         RCHK(dalloc(H, &H->d_ablocks, sizeof(ArnoldiBlock) * tab.size()));
         RCHK(dalloc(H, &H->d_part2, sizeof(double2) * 2 * tab.size()));
         const size_t bar_words = 32 * (tab.size() / 16 + 2);
+        H->bar_words = bar_words;
         RCHK(dalloc(H, &H->d_bar, sizeof(unsigned long long) * bar_words));
+        RCHK(dalloc(H, &H->d_epoch, sizeof(unsigned long long)));
         RCHK(dalloc(H, &H->d_err, sizeof(int)));
         HCHK(H, hipMemcpy(H->d_ablocks, tab.data(), sizeof(ArnoldiBlock) * tab.size(),
                           hipMemcpyHostToDevice));
         HCHK(H, hipMemset(H->d_bar, 0, sizeof(unsigned long long) * bar_words));
+        HCHK(H, hipMemset(H->d_epoch, 0, sizeof(unsigned long long)));
         HCHK(H, hipMemset(H->d_err, 0, sizeof(int)));
-        H->bar_base = 0;
         H->arn_E = E;
         H->arn_var = var;
         return RAS_OK;
@@ -622,19 +647,23 @@ int ensure_krylov(ras_pml_handle *H, int m) {
 
 int check_handle(ras_pml_handle *H) { return H ? RAS_OK : RAS_EINVAL; }
 
+SolveDispatch solve_dispatch(const ras_pml_handle *H) {
+    return SolveDispatch{H->solve_queue ? H->d_queue : nullptr, H->solve_waves};
+}
+
 int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st,
              bool acc = false, bool timed = true) {
     {
         Timer t(H, C_SOLVE, st, timed);
         launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
-                          H->nsub, active, v,
-                          H->d_F, H->d_ybuf, H->d_xout, st);
+                          H->nsub, active, SolveSrc{v, nullptr, 0}, H->d_F, H->d_ybuf, H->d_xout,
+                          solve_dispatch(H), st);
     }
     HCHK(H, hipGetLastError());
     {
         Timer t(H, C_SUM, st, timed);
         launch_pou_sum(H->fp64, H->d_probs, H->nprob, H->max_ndof, H->d_subs, active, H->d_pcnt,
-                       H->d_pchunk, H->d_pw, H->d_xout, z, acc, st);
+                       H->d_pchunk, H->d_pw, H->d_xout, SumDst{z, nullptr, 0}, acc, st);
     }
     HCHK(H, hipGetLastError());
     return RAS_OK;
@@ -651,15 +680,135 @@ int reduce_sync(ras_pml_handle *H, const double2 *a, const double2 *b, int mode,
     return RAS_OK;
 }
 
+// Steps between the host's looks at the convergence flags, and the steps
+// one replay of the step graph runs.
+constexpr int kSyncSteps = 8;
+
+// The kernels of one FGMRES step (Section 4.1: one application of B^{-1},
+// then the Arnoldi process with modified Gram-Schmidt, then the Givens
+// update) for every problem still in its cycle.  The band solve, the PoU sum,
+// the fused Arnoldi step and the Givens update read the step index on the
+// device (each problem's step count kp; the Arnoldi barrier epoch from its
+// device word), so the same launches, with the same arguments, serve every
+// step: enqueued one by one, or recorded once into a graph and replayed.
+// The one-launch-per-projection path (arn_E == 0) needs the host's step
+// index j and is enqueued only.  timed: per-launch events (RAS_FLAG_TIMING).
+int enqueue_step(ras_pml_handle *H, int j, int m, hipStream_t st, bool timed) {
+    const long long n = H->ntot;
+    const int P = H->nprob;
+    {
+        Timer t(H, C_SOLVE, st, timed);
+        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
+                          H->nsub, H->d_active, SolveSrc{H->d_V, H->d_ks, n}, H->d_F, H->d_ybuf,
+                          H->d_xout, solve_dispatch(H), st);
+    }
+    HCHK(H, hipGetLastError());
+    {
+        Timer t(H, C_SUM, st, timed);
+        launch_pou_sum(H->fp64, H->d_probs, P, H->max_ndof, H->d_subs, H->d_active, H->d_pcnt,
+                       H->d_pchunk, H->d_pw, H->d_xout, SumDst{H->d_Z, H->d_ks, n}, false, st);
+    }
+    HCHK(H, hipGetLastError());
+    if (H->arn_E > 0) {
+        Timer t(H, C_MGS, st, timed);
+        const hipError_t e = launch_arnoldi(H->arn_var, H->arn_nblocks, H->d_probs, H->d_ks,
+                                            H->d_ablocks, H->d_coef, n, H->d_Z, H->d_V, m, H->d_H,
+                                            H->d_part2, H->d_bar, H->d_epoch, H->d_err, P, st);
+        if (e != hipSuccess) {
+            H->last_error = std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e);
+            return RAS_EHIP;
+        }
+    } else {
+        double2 *Vj1 = H->d_V + static_cast<long long>(j + 1) * n;
+        const double2 *Zj = H->d_Z + static_cast<long long>(j) * n;
+        {
+            Timer t(H, C_SPMV, st, timed);
+            launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, n, Zj, nullptr, Vj1,
+                        st);
+        }
+        HCHK(H, hipGetLastError());
+        Timer t(H, C_MGS, st, timed);
+        for (int i = 0; i <= j; ++i)
+            launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, i, i == 0 ? 0 : 1, m, H->d_H,
+                       H->d_partials, H->d_counters, st);
+        launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, j + 1, 2, m, H->d_H, H->d_partials,
+                   H->d_counters, st);
+        launch_normalize(H->d_probs, P, H->max_ndof, H->d_ks, Vj1, j, m, H->d_H, st);
+    }
+    HCHK(H, hipGetLastError());
+    {
+        Timer t(H, C_GIVENS, st, timed);
+        launch_givens(H->d_ks, P, m, H->d_H, H->d_cs, H->d_sn, H->d_g, H->d_hist, H->d_active, st);
+    }
+    HCHK(H, hipGetLastError());
+    return RAS_OK;
+}
+
+void destroy_step_graph(ras_pml_handle *H) {
+    if (H->step_exec) (void)hipGraphExecDestroy(H->step_exec);
+    if (H->step_graph) (void)hipGraphDestroy(H->step_graph);
+    H->step_exec = nullptr;
+    H->step_graph = nullptr;
+    H->graph_m = 0;
+    H->graph_V = nullptr;
+}
+
+// The graph of kSyncSteps FGMRES steps (fused Arnoldi path): recorded by
+// stream capture on the handle's own stream (a caller's stream may be the
+// legacy default stream, which cannot capture) the first time a solve needs
+// it, and again when the restart length or the Krylov workspace changes
+// (their buffers are part of the recorded launches).  No allocation, copy or
+// memset is recorded: only the kernels of enqueue_step.
+int ensure_step_graph(ras_pml_handle *H, int m) {
+    if (H->step_exec && H->graph_m == m && H->graph_V == H->d_V) return RAS_OK;
+    destroy_step_graph(H);
+    if (!H->cap_stream) HCHK(H, hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+    HCHK(H, hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = RAS_OK;
+    for (int s = 0; s < kSyncSteps && rc == RAS_OK; ++s) rc = enqueue_step(H, -1, m, H->cap_stream, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(H->cap_stream, &g);
+    if (rc != RAS_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        if (rc == RAS_OK) {
+            H->last_error = std::string("capture of the GMRES step graph: ") + hipGetErrorString(e);
+            rc = RAS_EHIP;
+        }
+        return rc;
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        H->last_error = std::string("instantiation of the GMRES step graph: ") +
+                        hipGetErrorString(e2);
+        return RAS_EHIP;
+    }
+    H->step_graph = g;
+    H->step_exec = x;
+    H->graph_m = m;
+    H->graph_V = H->d_V;
+    return RAS_OK;
+}
+
 // rtol: one tolerance per problem.
 int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rtol, int m, int maxit,
                int *iters, double *relres, double *hist, hipStream_t st) {
     const int P = H->nprob;
     RCHK(ensure_krylov(H, m));
     // the barrier-timeout flag of the fused Arnoldi step reports this call
-    // only (the barrier counters stay consistent after a timeout: every
-    // block still arrives)
-    if (H->arn_E > 0) HCHK(H, hipMemsetAsync(H->d_err, 0, sizeof(int), st));
+    // only; after a timeout the counters and the epoch start again from zero
+    if (H->arn_E > 0) {
+        if (H->bar_reset) {
+            HCHK(H, hipMemsetAsync(H->d_bar, 0, sizeof(unsigned long long) * H->bar_words, st));
+            HCHK(H, hipMemsetAsync(H->d_epoch, 0, sizeof(unsigned long long), st));
+            H->bar_reset = false;
+        }
+        HCHK(H, hipMemsetAsync(H->d_err, 0, sizeof(int), st));
+    }
+    const bool graph = H->graph_steps && H->arn_E > 0 && !(H->flags & RAS_FLAG_TIMING);
+    if (graph) RCHK(ensure_step_graph(H, m));
     H->res_iters.assign(P, 0);
     H->res_relres.assign(P, 0.0);
     H->res_conv.assign(P, 0);
@@ -708,7 +857,7 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rt
             K.kp = 0;
             K.in_cycle = need[p];
             K.breakdown = 0;
-            K.pad_ = 0;
+            K.mc = mc;
             for (int i = 0; i <= m; ++i) g0[static_cast<size_t>(p) * (m + 1) + i] = make_double2(0, 0);
             g0[static_cast<size_t>(p) * (m + 1)] = make_double2(beta[p], 0.0);
         }
@@ -720,57 +869,29 @@ int gmres_impl(ras_pml_handle *H, const double2 *b, double2 *x, const double *rt
         HCHK(H, hipGetLastError());
         // Steps are enqueued without waiting: the Givens kernel clears a
         // problem's in-cycle flag (and its active flag, read by the next
-        // step's launches) on convergence, breakdown or the cycle's end, and
-        // every later launch of the cycle skips that problem (the Arnoldi
-        // launch as a whole once no problem is left).  The host looks at the
-        // flags every kSyncSteps steps and stops enqueueing when none is set.
-        constexpr int kSyncSteps = 8;
+        // step's launches) on convergence, breakdown or the cycle's end (mc
+        // steps), and every later launch of the cycle skips that problem (the
+        // Arnoldi launch as a whole once no problem is left).  The host looks
+        // at the flags every kSyncSteps steps -- enqueued one by one, or one
+        // replay of the step graph -- and stops when none is set.
         int enqueued = 0;
-        for (int j = 0; j < mc; ++j) {
-            ++enqueued;
-            const long long n = H->ntot;
-            double2 *Vj = H->d_V + static_cast<long long>(j) * n;
-            double2 *Vj1 = H->d_V + static_cast<long long>(j + 1) * n;
-            double2 *Zj = H->d_Z + static_cast<long long>(j) * n;
-            RCHK(do_apply(H, Vj, Zj, H->d_active, st));
-            if (H->arn_E > 0) {
-                Timer t(H, C_MGS, st);
-                hipError_t e = launch_arnoldi(H->arn_var, H->arn_nblocks, H->d_probs, H->d_ks,
-                                              H->d_ablocks, H->d_coef, n, Zj, H->d_V, j, m, H->d_H,
-                                              H->d_part2, H->d_bar, H->bar_base, H->d_err, P, st);
-                if (e != hipSuccess) {
-                    H->last_error = std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e);
-                    return RAS_EHIP;
-                }
-                H->bar_base += static_cast<unsigned long long>(j + 2);
+        for (int j0 = 0; j0 < mc; j0 += kSyncSteps) {
+            if (graph) {
+                HCHK(H, hipGraphLaunch(H->step_exec, st));
+                enqueued += kSyncSteps;
             } else {
-                {
-                    Timer t(H, C_SPMV, st);
-                    launch_spmv(H->d_probs, P, H->max_ndof, H->d_active, H->d_coef, n, Zj, nullptr,
-                                Vj1, st);
+                const int j1 = std::min(mc, j0 + kSyncSteps);
+                for (int j = j0; j < j1; ++j) {
+                    RCHK(enqueue_step(H, j, m, st, true));
+                    ++enqueued;
                 }
-                HCHK(H, hipGetLastError());
-                Timer t(H, C_MGS, st);
-                for (int i = 0; i <= j; ++i)
-                    launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, i, i == 0 ? 0 : 1, m,
-                               H->d_H, H->d_partials, H->d_counters, st);
-                launch_mgs(H->d_probs, P, H->d_ks, Vj1, H->d_V, n, j, j + 1, 2, m, H->d_H,
-                           H->d_partials, H->d_counters, st);
-                launch_normalize(H->d_probs, P, H->max_ndof, H->d_ks, Vj1, j, m, H->d_H, st);
             }
-            HCHK(H, hipGetLastError());
-            {
-                Timer t(H, C_GIVENS, st);
-                launch_givens(H->d_ks, P, j, m, H->d_H, H->d_cs, H->d_sn, H->d_g, H->d_hist,
-                              H->d_active, st);
-            }
-            HCHK(H, hipGetLastError());
-            if ((j + 1) % kSyncSteps != 0 && j + 1 != mc) continue;
             HCHK(H, hipMemcpyAsync(H->h_ks, H->d_ks, sizeof(KState) * P, hipMemcpyDeviceToHost, st));
             if (H->arn_E > 0)
                 HCHK(H, hipMemcpyAsync(H->h_err, H->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
             HCHK(H, hipStreamSynchronize(st));
             if (H->arn_E > 0 && *H->h_err != 0) {
+                H->bar_reset = true;
                 H->last_error = "grid barrier of the fused Arnoldi step timed out";
                 return RAS_EHIP;
             }
@@ -881,7 +1002,6 @@ int reduce_sync_w(ras_pml_handle *H, const RichWork &W, const double2 *a, hipStr
 int richardson_impl(ras_pml_handle *H, const RichWork &W, const double2 *b, double2 *x,
                     double rtol, int maxit, int *iters, double *relres, double *hist,
                     hipStream_t st) {
-    constexpr int kSyncSteps = 8;
     const int P = H->nprob;
     H->res_iters.assign(P, 0);
     H->res_relres.assign(P, 0.0);
@@ -1109,6 +1229,7 @@ int setup_common(int nprob, const double *k, const double *h, const int *grid, c
     }
     H->fp64 = o.precision == RAS_FP64;
     H->flags = o.flags;
+    H->graph_steps = (o.flags & RAS_FLAG_GRAPH_STEPS) != 0;
     if (o.tune_cache) H->tune_cache = o.tune_cache;
     if (hipGetDevice(&H->device) != hipSuccess) {
         g_plan_error = "no HIP device";
@@ -1373,8 +1494,8 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
     {
         Timer t(H, C_SOLVE, st);
         launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
-                          H->nsub, nullptr,
-                          static_cast<const double2 *>(v), H->d_F, H->d_ybuf, H->d_xout, st);
+                          H->nsub, nullptr, SolveSrc{static_cast<const double2 *>(v), nullptr, 0},
+                          H->d_F, H->d_ybuf, H->d_xout, solve_dispatch(H), st);
     }
     HCHK(H, hipGetLastError());
     if (xloc == nullptr) return RAS_OK;        // the solves alone (timing)
@@ -1647,8 +1768,8 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
             for (int deep = 0; deep < 2; ++deep)
                 t[deep] = timeit([&] {
                     launch_band_solve(H->fp64, deep != 0, H->maxW, H->d_probs, H->d_subs,
-                                      H->d_order, H->nsub, nullptr, v, H->d_F, H->d_ybuf,
-                                      H->d_xout, st);
+                                      H->d_order, H->nsub, nullptr, SolveSrc{v, nullptr, 0},
+                                      H->d_F, H->d_ybuf, H->d_xout, solve_dispatch(H), st);
                 }, 3);
             H->solve_deep = t[1] <= t[0];
         }
@@ -1717,6 +1838,24 @@ int ras_pml_reset_stats(ras_pml_t H) {
     H->stats.setup_assemble_ms = a;
     H->stats.setup_factor_ms = f;
     return RAS_OK;
+}
+
+int ras_pml_set_knob(ras_pml_t H, int knob, int value) {
+    if (!H || (value != 0 && value != 1)) return RAS_EINVAL;
+    switch (knob) {
+        case RAS_KNOB_SOLVE_DEEP: H->solve_deep = value != 0; return RAS_OK;
+        case RAS_KNOB_SOLVE_QUEUE: H->solve_queue = value != 0; return RAS_OK;
+        default: H->last_error = "unknown knob"; return RAS_EINVAL;
+    }
+}
+
+int ras_pml_get_knob(ras_pml_t H, int knob, int *value) {
+    if (!H || !value) return RAS_EINVAL;
+    switch (knob) {
+        case RAS_KNOB_SOLVE_DEEP: *value = H->solve_deep ? 1 : 0; return RAS_OK;
+        case RAS_KNOB_SOLVE_QUEUE: *value = H->solve_queue ? 1 : 0; return RAS_OK;
+        default: H->last_error = "unknown knob"; return RAS_EINVAL;
+    }
 }
 
 const char *ras_pml_strerror(int status) {

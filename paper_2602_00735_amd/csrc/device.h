@@ -8,6 +8,32 @@
 
 namespace raspml {
 
+// Right-hand side of a batched band solve: v itself, or (ks non-null) for
+// each subdomain v + ks[problem].kp * stride -- the Krylov vector of its
+// problem's current GMRES step, read on the device so that the launch's
+// arguments do not change from step to step.
+struct SolveSrc {
+    const double2 *v;
+    const KState *ks;
+    long long stride;
+};
+
+// Destination of a PoU-weighted sum: z, or z + ks[problem].kp * stride.
+struct SumDst {
+    double2 *z;
+    const KState *ks;
+    long long stride;
+};
+
+// Dispatch of a batched band solve: one wave per subdomain (queue null or
+// waves >= subdomains), or `waves` persistent waves taking subdomains from
+// the atomic counter `queue` (two words, zero between launches).
+struct SolveDispatch {
+    unsigned int *queue;
+    int waves;
+};
+
+
 template <typename T>
 struct cplx {
     T re, im;

@@ -68,10 +68,11 @@ struct KState {
     double beta;       // ||r0|| of the current cycle
     double est;        // |g_{j+1}| after the last step
     double rtol;
-    int kp;            // Arnoldi steps taken in the current cycle
+    int kp;            // Arnoldi steps taken in the current cycle (the index
+                       // of the next step's Krylov vector)
     int in_cycle;      // 1 while the problem takes steps in this cycle
     int breakdown;     // Arnoldi broke down in this cycle
-    int pad_;
+    int mc;            // steps this cycle may take (<= restart)
 };
 
 // Per-problem state of the fixed-point iteration kept on the device.

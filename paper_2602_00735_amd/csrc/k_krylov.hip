@@ -224,12 +224,14 @@ __global__ void k_start_cycle(const DevProb *__restrict__ probs, const KState *_
 // hist (optional): est / ||b|| of step j at hist[p (m + 1) + j]; active
 // (optional): the problem's in-cycle flag after this step, for the next
 // step's launches.
-__global__ void k_givens(KState *__restrict__ ks, int nprob, int j, int m, double2 *__restrict__ H,
+// The step index j is the problem's step count kp (read on the device).
+__global__ void k_givens(KState *__restrict__ ks, int nprob, int m, double2 *__restrict__ H,
                          double *__restrict__ cs, double2 *__restrict__ sn,
                          double2 *__restrict__ gv, double *__restrict__ hist,
                          int *__restrict__ active) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob || ks[p].in_cycle == 0) return;
+    const int j = ks[p].kp;
     double2 *Hc = H + static_cast<long long>(p) * (m + 1) * m + static_cast<long long>(j) * (m + 1);
     double *c_ = cs + static_cast<long long>(p) * m;
     double2 *s_ = sn + static_cast<long long>(p) * m;
@@ -277,7 +279,7 @@ __global__ void k_givens(KState *__restrict__ ks, int nprob, int j, int m, doubl
     if (hist != nullptr) hist[static_cast<long long>(p) * (m + 1) + j] = est / K.bnorm;
     const bool brk = hn <= 1e-14 * sqrt(colnorm2);
     if (brk) K.breakdown = 1;
-    if (est <= K.rtol * K.bnorm || brk || j + 1 == m) K.in_cycle = 0;
+    if (est <= K.rtol * K.bnorm || brk || j + 1 >= K.mc) K.in_cycle = 0;
     if (active != nullptr) active[p] = K.in_cycle;
 }
 
@@ -370,18 +372,17 @@ __device__ __forceinline__ bool spin_until(unsigned long long *p, unsigned long 
     return true;
 }
 
-// Counts `n` arrivals of this block (n > 1: barriers a skipped step passes
-// without waiting) and releases the epoch `target` when they complete it.
-__device__ __forceinline__ void barrier_arrive(unsigned long long *bar, unsigned long long target,
-                                               unsigned long long n) {
+// Counts this block's arrival and releases the epoch `target` when it
+// completes it.
+__device__ __forceinline__ void barrier_arrive(unsigned long long *bar, unsigned long long target) {
     const int nb = gridDim.x;
     const int ngroups = (nb + kBarGroup - 1) / kBarGroup;
     const int g = blockIdx.x / kBarGroup;
     const unsigned long long gsize = min(kBarGroup, nb - g * kBarGroup);
-    const unsigned long long old = atomicAdd(bar + kBarStride * (g + 1), n);
-    if (old + n != target * gsize) return;                  // not the group's last arrival
-    const unsigned long long t = atomicAdd(bar, n);
-    if (t + n != target * static_cast<unsigned long long>(ngroups)) return;
+    const unsigned long long old = atomicAdd(bar + kBarStride * (g + 1), 1ull);
+    if (old + 1 != target * gsize) return;                  // not the group's last arrival
+    const unsigned long long t = atomicAdd(bar, 1ull);
+    if (t + 1 != target * static_cast<unsigned long long>(ngroups)) return;
     for (int q = 0; q < ngroups; ++q)
         __hip_atomic_store(bar + kBarStride * (q + 1) + 16, target, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -392,7 +393,7 @@ __device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned l
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_s_waitcnt(0);          // this block's published values are complete
-        barrier_arrive(bar, epoch, 1);
+        barrier_arrive(bar, epoch);
         unsigned long long *grel = bar + kBarStride * (blockIdx.x / kBarGroup + 1) + 16;
         if (!failed && !spin_until(grel, epoch)) {
             failed = true;
@@ -419,27 +420,30 @@ __device__ cplx<double> problem_sum(const double2 *__restrict__ part, const Arno
 // Each block keeps its slice of w (and the current v_i) in registers, so w is
 // never re-read; j + 2 grid barriers separate the reductions.  Problems not
 // in the cycle skip the arithmetic but take part in every barrier.
+//
+// The step index j is the step count kp of the problems still in the cycle
+// (they all take their steps together), and the barrier epoch reached so far
+// is kept on the device (*epoch): the launch's arguments are the same at
+// every step, so that steps can be replayed from a graph.  Every block reads
+// both at its start; block 0 advances the epoch by j + 2 after the last
+// barrier, when every block has read it.
 template <int E, bool KEEPV>
 __device__ __forceinline__ void arnoldi_step(
     const DevProb *__restrict__ probs, const KState *__restrict__ ks,
     const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef, long long ntot,
-    const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,
-    double2 *__restrict__ H, double2 *__restrict__ part2, unsigned long long *bar,
-    unsigned long long epoch0, int *err, int nprob) {
+    const double2 *__restrict__ Z, double2 *__restrict__ V, int m, double2 *__restrict__ H,
+    double2 *__restrict__ part2, unsigned long long *bar, unsigned long long *epoch, int *err,
+    int nprob) {
     __shared__ cplx<double> sh[kRedThreads];
     // No problem left in the cycle (the host enqueues steps ahead of the
     // convergence test): every block sees the same flags, so the whole grid
-    // skips the step and only advances the barrier counters by the step's
-    // j + 2 barriers, as if it had taken them.
-    bool any = false;
-    for (int q = 0; q < nprob; ++q) any = any || ks[q].in_cycle != 0;
-    if (!any) {
-        if (threadIdx.x == 0) {
-            const unsigned long long nbar = static_cast<unsigned long long>(j) + 2;
-            barrier_arrive(bar, epoch0 + nbar, nbar);
-        }
-        return;
-    }
+    // skips the step, barriers and epoch included.
+    int j = -1;
+    for (int q = 0; q < nprob; ++q)
+        if (ks[q].in_cycle != 0) j = max(j, ks[q].kp);
+    if (j < 0) return;
+    const unsigned long long epoch0 = peek(epoch);
+    const double2 *__restrict__ zj = Z + static_cast<long long>(j) * ntot;
     const ArnoldiBlock B = blocks[blockIdx.x];
     const int nblocks = gridDim.x;
     const int p = B.prob;
@@ -479,7 +483,7 @@ __device__ __forceinline__ void arnoldi_step(
         if constexpr (!KEEPV)
             if ((q & 1) == 1) __builtin_amdgcn_sched_barrier(0);
     }
-    unsigned long long epoch = 0;
+    unsigned long long ep = 0;            // barriers passed in this launch
     bool failed = false;                  // (thread 0) a poll of this launch ran out
     for (int i = 0; i <= j; ++i) {
         const double2 *vi = V + static_cast<long long>(i) * ntot;
@@ -495,8 +499,8 @@ __device__ __forceinline__ void arnoldi_step(
         double2 *part = part2 + static_cast<long long>(i & 1) * nblocks;
         const cplx<double> bs = block_sum(acc, sh);
         if (threadIdx.x == 0) put_agent(part + blockIdx.x, bs);
-        ++epoch;
-        grid_barrier(bar, epoch0 + epoch, err, failed);
+        ++ep;
+        grid_barrier(bar, epoch0 + ep, err, failed);
         const cplx<double> h = problem_sum(part, B, sh);
 #pragma unroll
         for (int q = 0; q < E; ++q) {
@@ -515,8 +519,10 @@ __device__ __forceinline__ void arnoldi_step(
     double2 *part = part2 + static_cast<long long>((j + 1) & 1) * nblocks;
     const cplx<double> bs = block_sum(cplx<double>{nrm, 0.0}, sh);
     if (threadIdx.x == 0) put_agent(part + blockIdx.x, cplx<double>{bs.re, 0.0});
-    ++epoch;
-    grid_barrier(bar, epoch0 + epoch, err, failed);
+    ++ep;
+    grid_barrier(bar, epoch0 + ep, err, failed);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(epoch, epoch0 + ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double hn = sqrt(problem_sum(part, B, sh).re);
     if (!on) return;
     const double s = hn > 0.0 ? 1.0 / hn : 0.0;
@@ -532,10 +538,10 @@ __device__ __forceinline__ void arnoldi_step(
 #define ARNOLDI_PARAMS                                                                          \
     const DevProb *__restrict__ probs, const KState *__restrict__ ks,                           \
         const ArnoldiBlock *__restrict__ blocks, const double2 *__restrict__ coef,              \
-        long long ntot, const double2 *__restrict__ zj, double2 *__restrict__ V, int j, int m,  \
+        long long ntot, const double2 *__restrict__ Z, double2 *__restrict__ V, int m,          \
         double2 *__restrict__ H, double2 *__restrict__ part2, unsigned long long *bar,          \
-        unsigned long long epoch0, int *err, int nprob
-#define ARNOLDI_ARGS probs, ks, blocks, coef, ntot, zj, V, j, m, H, part2, bar, epoch0, err, nprob
+        unsigned long long *epoch, int *err, int nprob
+#define ARNOLDI_ARGS probs, ks, blocks, coef, ntot, Z, V, m, H, part2, bar, epoch, err, nprob
 
 template <int E>
 __global__ __launch_bounds__(kRedThreads) void k_arnoldi(ARNOLDI_PARAMS) {
@@ -596,10 +602,10 @@ void launch_rich_update(RState *rs, int *active, const double2 *red, double *his
                        rtol);
 }
 
-void launch_givens(KState *ks, int nprob, int j, int m, double2 *H, double *cs, double2 *sn,
+void launch_givens(KState *ks, int nprob, int m, double2 *H, double *cs, double2 *sn,
                    double2 *g, double *hist, int *active, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, dim3((nprob + 63) / 64), dim3(64), 0, s, ks, nprob, j, m, H, cs,
-                       sn, g, hist, active);
+    hipLaunchKernelGGL(k_givens, dim3((nprob + 63) / 64), dim3(64), 0, s, ks, nprob, m, H, cs, sn,
+                       g, hist, active);
 }
 
 void launch_solve_y(const KState *ks, int nprob, int m, const double2 *H, const double2 *g,
@@ -647,12 +653,12 @@ int arnoldi_block_capacity(int variant, int *blocks_per_cu) {
 
 hipError_t launch_arnoldi(int variant, int nblocks, const DevProb *probs, const KState *ks,
                           const ArnoldiBlock *blocks, const double2 *coef, long long ntot,
-                          const double2 *zj, double2 *V, int j, int m, double2 *H, double2 *part2,
-                          unsigned long long *bar, unsigned long long epoch0, int *err, int nprob,
+                          const double2 *Z, double2 *V, int m, double2 *H, double2 *part2,
+                          unsigned long long *bar, unsigned long long *epoch, int *err, int nprob,
                           hipStream_t s) {
     void *args[] = {(void *)&probs, (void *)&ks, (void *)&blocks, (void *)&coef, (void *)&ntot,
-                    (void *)&zj, (void *)&V, (void *)&j, (void *)&m, (void *)&H, (void *)&part2,
-                    (void *)&bar, (void *)&epoch0, (void *)&err, (void *)&nprob};
+                    (void *)&Z, (void *)&V, (void *)&m, (void *)&H, (void *)&part2,
+                    (void *)&bar, (void *)&epoch, (void *)&err, (void *)&nprob};
     return hipLaunchCooperativeKernel(arnoldi_fn(variant), dim3(nblocks), dim3(kRedThreads), args, 0,
                                       s);
 }

@@ -261,31 +261,70 @@ __device__ __forceinline__ void solve_subdomain(const DevProb *__restrict__ prob
 // for W up to 128 still solves its subdomains with W <= 64 in the
 // one-register form (uniform branch per subdomain).  W > 64 takes the pair
 // layout in complex64 (W is even) and the split layout in complex128.
-template <typename T, bool TWO, int PD>
+//
+// Right-hand side: v, or (ks non-null) v + ks[problem].kp * vstride, the
+// Krylov vector of the problem's current GMRES step, so that the launch's
+// arguments stay the same from step to step (replay from a graph).
+//
+// Dispatch: QUEUE = false, one wave per subdomain, launched in the order of
+// `order` (largest first), the hardware dispatcher handing each wave to the
+// next free SIMD; QUEUE = true, a persistent grid of at most one wave per
+// SIMD, each wave taking the next subdomain of `order` from an atomic
+// counter until none is left (largest first: a list schedule).  The last
+// wave to finish resets the two counter words to zero for the next launch.
+template <typename T, bool TWO, int PD, bool QUEUE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_band_solve(
     const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
-    const int *__restrict__ order, const int *__restrict__ active, const double2 *__restrict__ v,
-    const cplx<T> *__restrict__ F, cplx<T> *__restrict__ ybuf, cplx<T> *__restrict__ xout) {
+    const int *__restrict__ order, int nsub, const int *__restrict__ active,
+    const double2 *__restrict__ v, const KState *__restrict__ ks, long long vstride,
+    const cplx<T> *__restrict__ F, cplx<T> *__restrict__ ybuf, cplx<T> *__restrict__ xout,
+    unsigned int *__restrict__ queue) {
     __shared__ cplx<T> hist[128];               // outputs, by row mod 128
     __shared__ cplx<T> inc[64];                 // right-hand side of the current block
-    const DevSub S = subs[order[blockIdx.x]];
-    if (active != nullptr && active[S.prob] == 0) return;
-    constexpr int WIDE = sizeof(T) == 4 ? RING_PAIR : RING_SPLIT;
-    if (TWO && S.W > 64)
-        solve_subdomain<T, WIDE, PD>(probs, S, v, F, ybuf, xout, hist, inc);
-    else
-        solve_subdomain<T, RING_ONE, PD>(probs, S, v, F, ybuf, xout, hist, inc);
+    auto one = [&](int item) {
+        const DevSub S = subs[order[item]];
+        if (active != nullptr && active[S.prob] == 0) return;
+        const double2 *vs = ks != nullptr ? v + static_cast<long long>(ks[S.prob].kp) * vstride : v;
+        constexpr int WIDE = sizeof(T) == 4 ? RING_PAIR : RING_SPLIT;
+        if (TWO && S.W > 64)
+            solve_subdomain<T, WIDE, PD>(probs, S, vs, F, ybuf, xout, hist, inc);
+        else
+            solve_subdomain<T, RING_ONE, PD>(probs, S, vs, F, ybuf, xout, hist, inc);
+    };
+    if constexpr (!QUEUE) {
+        one(blockIdx.x);
+    } else {
+        for (;;) {
+            int item = 0;
+            if (threadIdx.x == 0) item = static_cast<int>(atomicAdd(queue, 1u));
+            item = __shfl(item, 0);
+            if (item >= nsub) break;
+            one(item);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (threadIdx.x == 0) {
+            const unsigned int done = atomicAdd(queue + 1, 1u);
+            if (done == gridDim.x - 1) {       // every wave has taken its last item
+                __hip_atomic_store(queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(queue + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
 }
 
 // z = sum over subdomains covering the node of chi_x * chi_y * x_local
 // (acc != 0: z += that sum, the fixed-point update of Algorithm 1).
+// (ks non-null: into z + ks[problem].kp * zstride, the Krylov vector of the
+// problem's current step.)
 template <typename T>
 __global__ void k_pou_sum(const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
                           const int *__restrict__ active, const int *__restrict__ pcnt,
                           const int *__restrict__ pchunk, const double *__restrict__ pw,
-                          const cplx<T> *__restrict__ xout, double2 *__restrict__ z, int acc) {
+                          const cplx<T> *__restrict__ xout, double2 *__restrict__ z,
+                          const KState *__restrict__ ks, long long zstride, int acc) {
     const DevProb P = probs[blockIdx.y];
     if (active != nullptr && active[blockIdx.y] == 0) return;
+    if (ks != nullptr) z += static_cast<long long>(ks[blockIdx.y].kp) * zstride;
     const long long idx = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= P.ndof) return;
     const int i = static_cast<int>(idx % P.n1) + 1;
@@ -326,11 +365,19 @@ __global__ void k_export_local(const DevSub *__restrict__ subs, const cplx<T> *_
 
 template <typename T, bool TWO, int PD>
 void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order, int nsub,
-                      const int *active, const double2 *v, const void *F, void *ybuf, void *xout,
-                      hipStream_t st) {
-    hipLaunchKernelGGL((k_band_solve<T, TWO, PD>), dim3(nsub), dim3(64), 0, st, probs, subs, order,
-                       active, v, static_cast<const cplx<T> *>(F), static_cast<cplx<T> *>(ybuf),
-                       static_cast<cplx<T> *>(xout));
+                      const int *active, const SolveSrc &src, const void *F, void *ybuf,
+                      void *xout, const SolveDispatch &dsp, hipStream_t st) {
+    const cplx<T> *Fc = static_cast<const cplx<T> *>(F);
+    cplx<T> *yb = static_cast<cplx<T> *>(ybuf);
+    cplx<T> *xo = static_cast<cplx<T> *>(xout);
+    if (dsp.queue != nullptr && dsp.waves > 0 && dsp.waves < nsub)
+        hipLaunchKernelGGL((k_band_solve<T, TWO, PD, true>), dim3(dsp.waves), dim3(64), 0, st,
+                           probs, subs, order, nsub, active, src.v, src.ks, src.stride, Fc, yb,
+                           xo, dsp.queue);
+    else
+        hipLaunchKernelGGL((k_band_solve<T, TWO, PD, false>), dim3(nsub), dim3(64), 0, st, probs,
+                           subs, order, nsub, active, src.v, src.ks, src.stride, Fc, yb, xo,
+                           dsp.queue);
 }
 
 }  // namespace
@@ -339,13 +386,17 @@ void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order
 // complex64 batch with W <= 64, whose lanes hold one slot each), else half
 // of that; the default is deep, the autotuner measures both.  (In the pair
 // layout a vector takes four registers per lane: 32 would not fit.)  F must carry 64 KB of slack past the last
-// factor (the prefetch runs past each stream's end).
+// factor (the prefetch runs past each stream's end).  dsp: hardware
+// dispatch of one wave per subdomain, or a persistent grid of dsp.waves
+// waves taking subdomains from the counter dsp.queue (two words, zero
+// between launches) when fewer waves than subdomains are asked for.
 void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, const DevSub *subs,
-                       const int *order, int nsub, const int *active, const double2 *v,
-                       const void *F, void *ybuf, void *xout, hipStream_t st) {
+                       const int *order, int nsub, const int *active, const SolveSrc &src,
+                       const void *F, void *ybuf, void *xout, const SolveDispatch &dsp,
+                       hipStream_t st) {
     const bool two = maxW > 64;
 #define RAS_SOLVE(T, TWO, PD) \
-    launch_solve_cfg<T, TWO, PD>(probs, subs, order, nsub, active, v, F, ybuf, xout, st)
+    launch_solve_cfg<T, TWO, PD>(probs, subs, order, nsub, active, src, F, ybuf, xout, dsp, st)
     if (fp64) {
         if (two) {
             if (deep) RAS_SOLVE(double, true, 16); else RAS_SOLVE(double, true, 8);
@@ -364,14 +415,17 @@ void launch_band_solve(bool fp64, bool deep, int maxW, const DevProb *probs, con
 
 void launch_pou_sum(bool fp64, const DevProb *probs, int nprob, long long max_ndof,
                     const DevSub *subs, const int *active, const int *pcnt, const int *pchunk,
-                    const double *pw, const void *xout, double2 *z, bool acc, hipStream_t st) {
+                    const double *pw, const void *xout, const SumDst &dst, bool acc,
+                    hipStream_t st) {
     dim3 grid(static_cast<unsigned>((max_ndof + 255) / 256), nprob);
     if (fp64)
         hipLaunchKernelGGL(k_pou_sum<double>, grid, dim3(256), 0, st, probs, subs, active, pcnt,
-                           pchunk, pw, static_cast<const cplx<double> *>(xout), z, acc ? 1 : 0);
+                           pchunk, pw, static_cast<const cplx<double> *>(xout), dst.z, dst.ks,
+                           dst.stride, acc ? 1 : 0);
     else
         hipLaunchKernelGGL(k_pou_sum<float>, grid, dim3(256), 0, st, probs, subs, active, pcnt,
-                           pchunk, pw, static_cast<const cplx<float> *>(xout), z, acc ? 1 : 0);
+                           pchunk, pw, static_cast<const cplx<float> *>(xout), dst.z, dst.ks,
+                           dst.stride, acc ? 1 : 0);
 }
 
 void launch_export_local(bool fp64, const DevSub *subs, int nsub, int max_n, const void *xout,

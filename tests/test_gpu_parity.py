@@ -1050,3 +1050,93 @@ def test_apply_captured_in_graph(precision):
         rp.ras_pml_apply(H, v2, z2)
         torch.cuda.synchronize()
         assert torch.equal(z2, ref2)
+
+
+# ---------------------------------------------------------------- graph-replayed steps
+def run_gmres(H, b, rtols, restart, maxit):
+    x = torch.zeros_like(b)
+    if H.nprob == 1:
+        rc, it, rr, hist = rp.gmres_solve(H, b, x, rtol=rtols[0], restart=restart, maxit=maxit)
+    else:
+        rc, it, rr, hist = rp.gmres_solve_batch(H, b, x, rtols, restart=restart, maxit=maxit)
+    per = [rp.ras_pml_batch_result(H, p) for p in range(H.nprob)]
+    return rc, it, np.asarray(rr).tolist(), np.asarray(hist).copy(), host(x), per
+
+
+def assert_same_solve(a, e):
+    assert (a[0], list(np.atleast_1d(a[1])), a[5]) == (e[0], list(np.atleast_1d(e[1])), e[5])
+    assert a[2] == e[2]
+    assert np.array_equal(a[3], e[3])
+    assert np.array_equal(a[4], e[4])
+
+
+def batch3_handle(precision, flags=0):
+    base = [PROBLEMS["k20"], PROBLEMS["ragged"], PROBLEMS["k40_two_slot"]]
+    pbs = [Problem(k=p.k, n_int=p.n_int, G=p.kappa, Px=p.Px, Py=p.Py, delta=p.delta,
+                   kappa=p.kappa, sigma=10 * p.k) for p in base]
+    o = rp.default_opts(precision=precision, flags=flags)
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs], o)
+    b = np.concatenate([fem.rhs(ras.RasPml(p).M1, inputs.centre_gaussian(p.n_int, p.G, 0.1))
+                        for p in pbs])
+    return H, dev(b)
+
+
+@pytest.mark.parametrize("name,precision,restart,maxit", [
+    ("k20", rp.RAS_MIXED, 100, 500),          # one cycle, ends inside a replay
+    ("k40_two_slot", rp.RAS_FP64, 5, 500),     # restart below the steps of one replay
+    ("ragged", rp.RAS_MIXED, 100, 13),         # maxit cuts the cycle inside a replay
+    ("nt8", rp.RAS_MIXED, 16, 500),            # several cycles of two replays each
+    ("batch3", rp.RAS_FP64, 10, 300),          # three problems, one tolerance each
+])
+def test_gmres_graph_replayed_steps_equal_eager_steps(name, precision, restart, maxit):
+    """RAS_FLAG_GRAPH_STEPS: the steps replayed from the recorded graph give
+    the eager steps' results bit for bit (the same kernels with the same
+    arguments read the step index on the device), also when a cycle ends
+    inside a replay, and on a second solve that replays the same graph."""
+    res = []
+    for flags in (0, rp.RAS_FLAG_GRAPH_STEPS):
+        if name == "batch3":
+            H, b = batch3_handle(precision, flags)
+            rt = [1e-4, 1e-8, 1e-6]
+        else:
+            pb = PROBLEMS[name]
+            H = setup_gpu(pb, precision, flags=flags)
+            b = dev(fem.rhs(oracle_for(name).M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+            rt = [1e-6]
+        res.append(run_gmres(H, b, rt, restart, maxit))
+        if flags:
+            res.append(run_gmres(H, b, rt, restart, maxit))
+        H.close()
+    eager, graph, again = res
+    assert np.max(eager[1]) > 0
+    assert_same_solve(graph, eager)
+    assert_same_solve(again, eager)
+
+
+def test_persistent_band_solve_equals_hardware_dispatch():
+    """The band solve's persistent variant (one wave per SIMD taking
+    subdomains from an atomic counter, largest first) gives the same local
+    solutions bit for bit, on a batch with more subdomains than SIMDs, and
+    leaves its counter ready for the next launch (repeated applies agree)."""
+    pbs = [p for p, _ in config4_items()]
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1.0 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs],
+                               rp.default_opts(precision=rp.RAS_MIXED))
+    nsub = H.nsub
+    v = torch.from_numpy(inputs.random_vector(H.ndof, 11)).to("cuda")
+    out = {}
+    for queue in (0, 1):
+        rp.ras_pml_set_knob(H, rp.RAS_KNOB_SOLVE_QUEUE, queue)
+        assert rp.ras_pml_get_knob(H, rp.RAS_KNOB_SOLVE_QUEUE) == queue
+        z = [torch.zeros_like(v) for _ in range(3)]
+        for zz in z:
+            rp.ras_pml_apply(H, v, zz)
+        out[queue] = [host(zz) for zz in z]
+    assert nsub > 1024
+    for q in (0, 1):
+        for zz in out[q]:
+            assert np.array_equal(zz, out[0][0])
+    H.close()
