@@ -60,6 +60,10 @@ def log_width(k, h):
     return int(math.ceil(math.log(k) / (k * h) - 1e-12))
 
 
+# factorisation kernel variants as ras_pml_tuning numbers them
+LU_VARIANTS = ("mfma", "mfma_register_capped", "valu_one_column")
+
+
 def progress(msg):
     """A line on stderr when a phase of the run ends."""
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
@@ -156,6 +160,7 @@ def main():
             Ht = rp.ras_pml_setup(k, h, grid, subs, L, L, rp.default_opts(global_pml=G, precision=prec))
             rp.ras_pml_autotune(Ht, cache)
             tuning[name] = rp.ras_pml_tuning(Ht)
+            tuning[name]["times_ms"] = rp.ras_pml_tune_report(Ht)
             Ht.close()
 
     def one_solve(precision, timing=False, f=f, graph=False, repeat=False):
@@ -289,8 +294,10 @@ def main():
                   "setup_factor_ms": round(st["setup_factor_ms"], 3)},
         "graph_steps": graph_blk,
         "tuning": {name: {"band_solve_deep_prefetch": t["solve_deep"],
+                          "band_solve_queue": t["solve_queue"],
                           "factor_classes": [{"tiles": g[0], "subdomains": g[1],
-                                              "128_register_variant": g[2]} for g in t["ldlt"]]}
+                                              "variant": LU_VARIANTS[g[2]]} for g in t["ldlt"]],
+                          "times_ms": t["times_ms"]}
                    for name, t in tuning.items()},
         "roofline": {"kernel": "k_band_solve (batched forward/backward band sweeps)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

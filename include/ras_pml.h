@@ -376,29 +376,44 @@ int ras_pml_set_cache_limit(long long bytes);
 int ras_pml_cache_info(long long *cached_bytes, long long *live_bytes);
 int ras_pml_fill_idle_cache(int byte);
 
-/* Autotuner (performance only: every variant computes the same values).
- * Times, on this handle's own factors and subdomain tables, the kernel
- * variants whose best choice depends on the band width and the number of
- * subdomains, and keeps the faster for the handle's later calls:
- *   - per complex64 factorisation window class (tiles per side): the
- *     128-register variant (four workgroups per CU) or the unconstrained
- *     one, one class at a time with the others at their current choice,
- *     each timed as the whole factorisation (the classes run side by side;
- *     re-runs it, the factor is unchanged);
- *   - the band-solve prefetch depth (16 or 8 vectors; 32 or 16 for a
- *     complex64 handle whose bands all have W <= 64).
+/* Autotuner (performance only).  Times, on this handle's own factors and
+ * subdomain tables, the kernel variants whose best choice depends on the
+ * band width and the number of subdomains, and keeps the fastest for the
+ * handle's later calls:
+ *   - per factorisation window class (tiles of 16 per side, both
+ *     precisions): the blocked kernel with the matrix-core trailing update,
+ *     unconstrained (variant 0) or held to the register budget of four
+ *     (complex64) / two (complex128) workgroups per CU (variant 1), or the
+ *     one-column kernel on the vector ALUs (variant 2); one class at a time
+ *     with the others at their current choice, each timed as the whole
+ *     factorisation (the classes run side by side).  The variants round
+ *     differently (the blocked ones alike): the factor is formed again with
+ *     the chosen variants, as a setup with these choices forms it;
+ *   - the band solve's prefetch depth (RAS_KNOB_SOLVE_DEEP) and, with more
+ *     subdomains than SIMDs, its dispatch (RAS_KNOB_SOLVE_QUEUE); these
+ *     compute the same values bit for bit.
  * cache_path (nullable): the choices are merged into this flat JSON file,
  * keyed "arch/precision/kernel/class/count" (counts rounded up to a power
  * of two), for ras_pml_opts.tune_cache.  Allocates one temporary vector;
  * synchronises `stream`.  Errors: RAS_EINVAL (no handle, or the cache file
- * cannot be written), RAS_ENOMEM, RAS_EHIP.                                */
+ * cannot be written), RAS_ENOMEM, RAS_EHIP, RAS_EZEROPIVOT (a chosen
+ * variant met a zero pivot).                                              */
 int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream);
 
-/* Current variant choices: *solve_deep (1: deep prefetch); *n_groups window
- * classes of the complex64 factorisation (0 in the FP64 path), the first
- * cap_groups of them as (tiles per side, subdomains, 128-register variant
- * 0/1) triples in groups.  Errors: RAS_EINVAL.                             */
+/* Current variant choices: *solve_deep (1: deep prefetch); *n_groups
+ * factorisation window classes, the first cap_groups of them as (tiles per
+ * side, subdomains, variant 0/1/2 as in ras_pml_autotune) triples in
+ * groups.  Errors: RAS_EINVAL.                                             */
 int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, int *n_groups);
+
+/* Timings of the last ras_pml_autotune on this handle (milliseconds, best
+ * of its runs): for each factorisation window class in the order of
+ * ras_pml_tuning, the whole factorisation with that class at variant 0, 1
+ * and 2; then the band solve at (dispatch, prefetch) = (hardware, half),
+ * (hardware, deep), (queue, half), (queue, deep), 1e30 where not measured.
+ * *n = 3 * classes + 4 (0 before any autotune); the first cap values go to
+ * ms.  Errors: RAS_EINVAL.                                                */
+int ras_pml_tune_report(ras_pml_t H, double *ms, int cap, int *n);
 
 /* Kernel variant choices of a handle (performance only: every variant
  * computes the same values, bit for bit):

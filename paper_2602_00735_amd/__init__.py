@@ -91,6 +91,7 @@ SYMBOLS = [
     ("ras_pml_richardson", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_richardson_noalloc", _I, [_P, _P, _P, _D, _I, _IP, _DP, _DP, _P]),
     ("ras_pml_set_knob", _I, [_P, _I, _I]),
+    ("ras_pml_tune_report", _I, [_P, _DP, _I, _IP]),
     ("ras_pml_get_knob", _I, [_P, _I, _IP]),
     ("ras_pml_width_rule", _I, [_D, _D, _D, _D, _IP]),
     ("ras_pml_batch_result", _I, [_P, _I, _IP, _DP, _IP]),
@@ -507,15 +508,37 @@ def ras_pml_autotune(H: Handle, cache_path=None, stream=None):
 
 
 def ras_pml_tuning(H: Handle) -> dict:
-    """{"solve_deep": bool, "ldlt": [(tiles, subdomains, occupancy_variant), ...]}"""
+    """{"solve_deep": bool, "solve_queue": bool, "ldlt": [(tiles, subdomains, variant), ...]}
+    (variant 0: matrix-core kernel, 1: the same held to the occupancy register
+    budget, 2: one-column vector-ALU kernel)"""
     deep, ng = ctypes.c_int(0), ctypes.c_int(0)
     cap = 16
     buf = (ctypes.c_int * (3 * cap))()
     rc = lib().ras_pml_tuning(H.ptr, ctypes.byref(deep), buf, cap, ctypes.byref(ng))
     if rc:
         H._raise(rc)
-    groups = [(buf[3 * i], buf[3 * i + 1], bool(buf[3 * i + 2])) for i in range(min(cap, ng.value))]
-    return {"solve_deep": bool(deep.value), "ldlt": groups}
+    groups = [(buf[3 * i], buf[3 * i + 1], int(buf[3 * i + 2])) for i in range(min(cap, ng.value))]
+    return {"solve_deep": bool(deep.value),
+            "solve_queue": bool(ras_pml_get_knob(H, RAS_KNOB_SOLVE_QUEUE)), "ldlt": groups}
+
+
+def ras_pml_tune_report(H: Handle) -> dict:
+    """Timings (ms) of the last autotune: {"ldlt": [(tiles, [t0, t1, t2]), ...],
+    "solve": {"hardware_half": t, "hardware_deep": t, "queue_half": t, "queue_deep": t}}
+    (None where not measured)."""
+    n = ctypes.c_int(0)
+    buf = (ctypes.c_double * 64)()
+    rc = lib().ras_pml_tune_report(H.ptr, buf, 64, ctypes.byref(n))
+    if rc:
+        H._raise(rc)
+    vals = [None if v >= 1e29 else round(v, 4) for v in buf[:min(64, n.value)]]
+    if not vals:
+        return {}
+    groups = ras_pml_tuning(H)["ldlt"]
+    ldlt = [(g[0], vals[3 * i:3 * i + 3]) for i, g in enumerate(groups)]
+    sv = vals[3 * len(groups):3 * len(groups) + 4]
+    return {"ldlt": ldlt, "solve": dict(zip(("hardware_half", "hardware_deep", "queue_half",
+                                             "queue_deep"), sv))}
 
 
 def ras_pml_strerror(status: int) -> str:

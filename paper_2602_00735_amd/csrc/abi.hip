@@ -30,8 +30,8 @@ void launch_rhs(const DevProb *, int, long long, const double2 *, double2 *, hip
 void launch_band_ldlt(bool, int, const DevSub *, const int *, int, const double2 *, void *, int *,
                       hipStream_t);
 int ldlt_mfma_tiles(int W);
-bool ldlt_mfma_default_occ(int NT);
-void launch_band_ldlt_mfma(int, bool, const DevSub *, const int *, int, const double2 *, void *,
+bool ldlt_mfma_default_occ(bool, int NT);
+void launch_band_ldlt_mfma(bool, int, bool, const DevSub *, const int *, int, const double2 *, void *,
                            int *, hipStream_t);
 void launch_band_solve(bool, bool, int, const DevProb *, const DevSub *, const int *, int,
                        const int *, const SolveSrc &, const void *, void *, void *,
@@ -83,15 +83,16 @@ struct ras_pml_handle {
     std::vector<DevProb> hprobs;
     std::vector<DevSub> hsubs;
     std::vector<int> order;
-    // complex64 factorisation: subdomains grouped by window size (tiles per
-    // side), largest first within a group; {tiles, first, count, occupancy
-    // variant} per group
+    // factorisation: subdomains grouped by window size (tiles per side),
+    // largest first within a group; {tiles, first, count, kernel variant
+    // (LU_*), largest W} per group
     std::vector<int> lu_order;
-    std::vector<std::array<int, 4>> lu_groups;
+    std::vector<std::array<int, 5>> lu_groups;
     bool solve_deep = true;    // band-solve prefetch depth variant
     bool solve_queue = false;  // band-solve dispatch: persistent waves and a work queue
     int solve_waves = 0;       // waves of the persistent band solve (one per SIMD)
     bool graph_steps = false;  // GMRES steps replayed from a graph (RAS_FLAG_GRAPH_STEPS)
+    std::vector<double> tune_ms;   // the last autotune's timings (ras_pml_tune_report)
     std::string arch;          // gfx name of the device (tuning cache keys)
     std::string tune_cache;    // opts.tune_cache (empty: none)
     long long skipped_steps = 0;   // GMRES steps enqueued after every problem had stopped
@@ -335,12 +336,18 @@ namespace {
 
 void apply_cache(ras_pml_handle *H, const char *path);
 
-// The complex64 factorisation of every window class with each class's
-// register variant (lu_groups[i][3]): the largest class on the caller's
-// stream, the others beside it on the auxiliary stream (fork and join
-// through events), so that their workgroups take the slots the largest
-// class leaves free in its last round.
-int factorise_c64(ras_pml_handle *H, hipStream_t st) {
+// Factorisation kernel of a window class: the blocked one with the
+// matrix-core trailing update, unconstrained or held to the register budget
+// that lets four (complex64) or two (complex128) workgroups share a CU, or
+// the one-column kernel on the vector ALUs (rank-1 update per column).
+enum { LU_MFMA = 0, LU_MFMA_CAPPED = 1, LU_VALU = 2, LU_NVARIANTS = 3 };
+
+// The factorisation of every window class with its kernel variant
+// (lu_groups[i][3]): the largest class on the caller's stream, the others
+// beside it on the auxiliary stream (fork and join through events), so that
+// their workgroups take the slots the largest class leaves free in its last
+// round.
+int factorise(ras_pml_handle *H, hipStream_t st) {
     hipStream_t aux = H->lu_groups.size() > 1 ? aux_stream(H->device) : nullptr;
     hipEvent_t fork{}, join{};
     if (aux) {
@@ -355,8 +362,13 @@ int factorise_c64(ras_pml_handle *H, hipStream_t st) {
     }
     for (size_t i = 0; i < H->lu_groups.size(); ++i) {
         const auto &g = H->lu_groups[i];
-        launch_band_ldlt_mfma(g[0], g[3] != 0, H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
-                              H->d_F, H->d_status, i == 0 || !aux ? st : aux);
+        const hipStream_t s = i == 0 || !aux ? st : aux;
+        if (g[3] == LU_VALU)
+            launch_band_ldlt(H->fp64, g[4], H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
+                             H->d_F, H->d_status, s);
+        else
+            launch_band_ldlt_mfma(H->fp64, g[0], g[3] == LU_MFMA_CAPPED, H->d_subs,
+                                  H->d_lu_order + g[1], g[2], H->d_lst, H->d_F, H->d_status, s);
     }
     hipError_t e = hipGetLastError();
     if (aux && e == hipSuccess) {
@@ -441,16 +453,18 @@ int build(ras_pml_handle *H, hipStream_t st) {
     std::iota(H->order.begin(), H->order.end(), 0);
     std::stable_sort(H->order.begin(), H->order.end(),
                      [&](int a, int b) { return H->hsubs[a].n > H->hsubs[b].n; });
-    if (!H->fp64) {
+    {
         H->lu_order = H->order;
         auto tiles = [&](int j) { return ldlt_mfma_tiles(H->hsubs[j].W); };
         std::stable_sort(H->lu_order.begin(), H->lu_order.end(),
                          [&](int a, int b) { return tiles(a) > tiles(b); });
         for (int i = 0; i < H->nsub;) {
-            int e = i;
-            while (e < H->nsub && tiles(H->lu_order[e]) == tiles(H->lu_order[i])) ++e;
+            int e = i, wmax = 0;
+            while (e < H->nsub && tiles(H->lu_order[e]) == tiles(H->lu_order[i]))
+                wmax = std::max(wmax, H->hsubs[H->lu_order[e++]].W);
             const int nt = tiles(H->lu_order[i]);
-            H->lu_groups.push_back({nt, i, e - i, ldlt_mfma_default_occ(nt) ? 1 : 0});
+            H->lu_groups.push_back(
+                {nt, i, e - i, ldlt_mfma_default_occ(H->fp64, nt) ? LU_MFMA_CAPPED : LU_MFMA, wmax});
             i = e;
         }
     }
@@ -474,7 +488,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_probs, sizeof(DevProb) * H->nprob));
     RCHK(dalloc(H, &H->d_subs, sizeof(DevSub) * H->nsub));
     RCHK(dalloc(H, &H->d_order, sizeof(int) * H->nsub));
-    if (!H->fp64) RCHK(dalloc(H, &H->d_lu_order, sizeof(int) * H->nsub));
+    RCHK(dalloc(H, &H->d_lu_order, sizeof(int) * H->nsub));
     RCHK(dalloc(H, &H->d_pcnt, sizeof(int) * pcnt.size()));
     RCHK(dalloc(H, &H->d_pchunk, sizeof(int) * pchunk.size()));
     RCHK(dalloc(H, &H->d_pw, sizeof(double) * pw.size()));
@@ -497,9 +511,8 @@ int build(ras_pml_handle *H, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_order, H->order.data(), sizeof(int) * H->nsub,
                            hipMemcpyHostToDevice, st));
-    if (!H->fp64)
-        HCHK(H, hipMemcpyAsync(H->d_lu_order, H->lu_order.data(), sizeof(int) * H->nsub,
-                               hipMemcpyHostToDevice, st));
+    HCHK(H, hipMemcpyAsync(H->d_lu_order, H->lu_order.data(), sizeof(int) * H->nsub,
+                           hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_pcnt, pcnt.data(), sizeof(int) * pcnt.size(),
                            hipMemcpyHostToDevice, st));
     HCHK(H, hipMemcpyAsync(H->d_pchunk, pchunk.data(), sizeof(int) * pchunk.size(),
@@ -520,13 +533,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
     launch_local_stencil(H->d_probs, H->d_subs, H->nsub, H->max_n, H->d_lst, st);
     HCHK(H, hipGetLastError());
     if (timing) HCHK(H, hipEventRecord(e1, st));
-    if (H->fp64) {
-        launch_band_ldlt(true, H->maxW, H->d_subs, H->d_order, H->nsub, H->d_lst, H->d_F,
-                         H->d_status, st);
-        HCHK(H, hipGetLastError());
-    } else {
-        RCHK(factorise_c64(H, st));
-    }
+    RCHK(factorise(H, st));
     if (timing) HCHK(H, hipEventRecord(e2, st));
     std::vector<int> status(H->nsub);
     HCHK(H, hipMemcpyAsync(status.data(), H->d_status, sizeof(int) * H->nsub,
@@ -1261,9 +1268,14 @@ int pow2_bucket(int n) {
     return b;
 }
 
-std::string lu_key(const ras_pml_handle *H, const std::array<int, 4> &g) {
-    return H->arch + "/c64/ldlt/tiles=" + std::to_string(g[0]) + "/count=" +
-           std::to_string(pow2_bucket(g[2]));
+std::string lu_key(const ras_pml_handle *H, const std::array<int, 5> &g) {
+    return H->arch + (H->fp64 ? "/c128" : "/c64") + "/ldlt/tiles=" + std::to_string(g[0]) +
+           "/count=" + std::to_string(pow2_bucket(g[2]));
+}
+
+std::string queue_key(const ras_pml_handle *H) {
+    return H->arch + (H->fp64 ? "/c128" : "/c64") + "/solve_queue/maxW=" +
+           std::to_string(H->maxW) + "/nsub=" + std::to_string(pow2_bucket(H->nsub));
 }
 
 std::string solve_key(const ras_pml_handle *H) {
@@ -1333,8 +1345,12 @@ void apply_cache(ras_pml_handle *H, const char *path) {
     const auto c = read_cache(path);
     if (c.empty()) return;
     if (H->arch.empty()) H->arch = device_arch();
-    for (auto &g : H->lu_groups) g[3] = cache_lookup(c, lu_key(H, g), g[3]) != 0;
+    for (auto &g : H->lu_groups) {
+        const int v = cache_lookup(c, lu_key(H, g), g[3]);
+        if (v >= 0 && v < LU_NVARIANTS) g[3] = v;
+    }
     H->solve_deep = cache_lookup(c, solve_key(H), H->solve_deep) != 0;
+    H->solve_queue = cache_lookup(c, queue_key(H), H->solve_queue) != 0;
 }
 
 }  // namespace
@@ -1743,19 +1759,34 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         return best;
     };
     int rc = RAS_OK;
-    // factorisation classes (complex64): both register budgets, one class at
-    // a time with the others at their current choice, each timed as the whole
-    // factorisation (the classes run side by side there); the factor they
-    // write is the same
-    if (!H->fp64)
-        for (auto &g : H->lu_groups) {
-            float t[2];
-            for (int occ = 0; occ < 2; ++occ) {
-                g[3] = occ;
-                t[occ] = timeit([&] { (void)factorise_c64(H, st); }, 2);
-            }
-            g[3] = t[1] <= t[0] ? 1 : 0;
+    H->tune_ms.clear();
+    // factorisation classes: the three kernel variants, one class at a time
+    // with the others at their current choice, each timed as the whole
+    // factorisation (the classes run side by side there); then the factor is
+    // formed again with the chosen variants (the matrix-core and the
+    // one-column kernels round differently), as a setup with these choices
+    // forms it
+    for (auto &g : H->lu_groups) {
+        float t[LU_NVARIANTS];
+        for (int v = 0; v < LU_NVARIANTS; ++v) {
+            g[3] = v;
+            t[v] = timeit([&] { (void)factorise(H, st); }, 2);
         }
+        g[3] = static_cast<int>(std::min_element(t, t + LU_NVARIANTS) - t);
+        H->tune_ms.insert(H->tune_ms.end(), t, t + LU_NVARIANTS);
+    }
+    {
+        RCHK(factorise(H, st));
+        std::vector<int> status(H->nsub);
+        HCHK(H, hipMemcpyAsync(status.data(), H->d_status, sizeof(int) * H->nsub,
+                               hipMemcpyDeviceToHost, st));
+        HCHK(H, hipStreamSynchronize(st));
+        for (int s = 0; s < H->nsub; ++s)
+            if (status[s] >= 0) {
+                H->last_error = "autotune: a chosen factorisation variant met a zero pivot";
+                return RAS_EZEROPIVOT;
+            }
+    }
     // band solve: both prefetch depths on a zero right-hand side (the kernel
     // has no data-dependent control flow)
     double2 *v = nullptr;
@@ -1763,16 +1794,32 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         H->last_error = "autotune: no memory for the test vector";
         rc = RAS_ENOMEM;
     } else {
-        float t[2];
+        // prefetch depth x dispatch (the persistent queue only matters with
+        // more subdomains than SIMDs)
+        float t[2][2] = {{1e30f, 1e30f}, {1e30f, 1e30f}};
+        const int nq = H->nsub > H->solve_waves ? 2 : 1;
         if (hipMemsetAsync(v, 0, sizeof(double2) * H->ntot, st) == hipSuccess) {
-            for (int deep = 0; deep < 2; ++deep)
-                t[deep] = timeit([&] {
-                    launch_band_solve(H->fp64, deep != 0, H->maxW, H->d_probs, H->d_subs,
-                                      H->d_order, H->nsub, nullptr, SolveSrc{v, nullptr, 0},
-                                      H->d_F, H->d_ybuf, H->d_xout, solve_dispatch(H), st);
-                }, 3);
-            H->solve_deep = t[1] <= t[0];
+            for (int q = 0; q < nq; ++q)
+                for (int deep = 0; deep < 2; ++deep)
+                    t[q][deep] = timeit([&] {
+                        launch_band_solve(H->fp64, deep != 0, H->maxW, H->d_probs, H->d_subs,
+                                          H->d_order, H->nsub, nullptr, SolveSrc{v, nullptr, 0},
+                                          H->d_F, H->d_ybuf, H->d_xout,
+                                          SolveDispatch{q ? H->d_queue : nullptr, H->solve_waves},
+                                          st);
+                    }, 3);
+            int bq = 0, bd = 1;
+            for (int q = 0; q < nq; ++q)
+                for (int deep = 0; deep < 2; ++deep)
+                    if (t[q][deep] < t[bq][bd]) {
+                        bq = q;
+                        bd = deep;
+                    }
+            H->solve_deep = bd != 0;
+            H->solve_queue = bq != 0;
         }
+        for (int q = 0; q < 2; ++q)
+            for (int deep = 0; deep < 2; ++deep) H->tune_ms.push_back(t[q][deep]);
         (void)hipStreamSynchronize(st);
         (void)hipFree(v);
     }
@@ -1786,14 +1833,21 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
     if (rc != RAS_OK) return rc;
     if (cache_path) {
         auto c = read_cache(cache_path);
-        if (!H->fp64)
-            for (const auto &g : H->lu_groups) cache_set(c, lu_key(H, g), g[3]);
+        for (const auto &g : H->lu_groups) cache_set(c, lu_key(H, g), g[3]);
         cache_set(c, solve_key(H), H->solve_deep ? 1 : 0);
+        cache_set(c, queue_key(H), H->solve_queue ? 1 : 0);
         if (!write_cache(cache_path, c)) {
             H->last_error = std::string("autotune: cannot write ") + cache_path;
             return RAS_EINVAL;
         }
     }
+    return RAS_OK;
+}
+
+int ras_pml_tune_report(ras_pml_t H, double *ms, int cap, int *n) {
+    if (!H || !n || (cap > 0 && !ms)) return RAS_EINVAL;
+    *n = static_cast<int>(H->tune_ms.size());
+    for (int i = 0; i < std::min(cap, *n); ++i) ms[i] = H->tune_ms[i];
     return RAS_OK;
 }
 

@@ -1,5 +1,5 @@
-// Blocked band factorisation A_j = L_j D_j L_j^T (complex64, no pivoting)
-// with the trailing update on the matrix cores (setup).
+// Blocked band factorisation A_j = L_j D_j L_j^T (complex64 or complex128,
+// no pivoting) with the trailing update on the matrix cores (setup).
 //
 // Same factor as the one-column kernel (Section 2's local solves; A_j is
 // complex symmetric, U = D L^T), organised in panels of 16 columns:
@@ -9,9 +9,10 @@
 //      update;
 //   2. L, its row copy and D^{-1} of the 16 columns are written out;
 //   3. the rest of the window takes the rank-16 update C -= L W^T with
-//      W = L D, as complex 16x16 tiles: 16 v_mfma_f32_16x16x4f32 per tile
-//      (real and imaginary parts in four real products).  Only tiles on or
-//      below the diagonal are updated: the window stays symmetric.
+//      W = L D, as complex 16x16 tiles: 16 v_mfma_f32_16x16x4f32 (complex64)
+//      or v_mfma_f64_16x16x4f64 (complex128) per tile (real and imaginary
+//      parts in four real products).  Only tiles on or below the diagonal
+//      are updated: the window stays symmetric.
 // The window covers M = 16 NT rows and columns, NT = ceil((W + 15) / 16),
 // enough to hold every row a panel column reaches (W - 1 below its
 // diagonal).  Its NT (NT + 1) / 2 tiles on and below the diagonal live in
@@ -35,7 +36,37 @@ namespace raspml {
 
 namespace {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
+// Precision traits: the 16x16x4 matrix-core product, which takes
+// A[l & 15][l >> 4] and B[l >> 4][l & 15] from lane l in both precisions and
+// leaves D[row0(l) + rs r][l & 15] in accumulator r -- rows 4 (l >> 4) .. + 3
+// in complex64 (v_mfma_f32_16x16x4f32), rows (l >> 4) + {0, 4, 8, 12} in
+// complex128 (v_mfma_f64_16x16x4f64; measured lane by lane); the pivot
+// reciprocal (v_rcp_f32 within 1 ulp for complex64 factors, a correctly
+// rounded division for complex128) and the relative pivot test.
+template <typename T>
+struct Prec;
+template <>
+struct Prec<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ int row0(int lane) { return 4 * (lane >> 4); }
+    static constexpr int rs = 1;
+    static constexpr float tol = 1e-6f;
+};
+template <>
+struct Prec<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ int row0(int lane) { return lane >> 4; }
+    static constexpr int rs = 4;
+    static constexpr double tol = 1e-14;
+};
 
 constexpr int kLdsStride = 17;   // complex values per LDS panel row (16 + 1 pad)
 
@@ -55,16 +86,17 @@ __device__ __forceinline__ void lds_barrier() {
 // (d = n_fast + 1; entries 1 and 3 vanish when r starts a fast line).
 // Identity past the matrix end.  Branch-free: one clamped load, always
 // issued, so that its wait can sit at the first use of the value.
-__device__ __forceinline__ cplx<float> band_entry(const double2 *__restrict__ lst, int n, int nf,
-                                                  int r, int q) {
+template <typename T>
+__device__ __forceinline__ cplx<T> band_entry(const double2 *__restrict__ lst, int n, int nf,
+                                              int r, int q) {
     const int hi = max(r, q), lo = min(r, q), d = hi - lo;
     const int e = d == 0 ? 0 : d == 1 ? 1 : d == nf ? 2 : 3;
     const bool wrap = (hi % nf) == 0;
     const bool in = hi < n;
     const bool coupled = in && (d == 0 || d == nf || ((d == 1 || d == nf + 1) && !wrap));
     const double2 v = lst[4LL * min(lo, n - 1) + e];
-    const float id = (!in && d == 0) ? 1.0f : 0.0f;
-    return cplx<float>{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
+    const T id = (!in && d == 0) ? T(1) : T(0);
+    return cplx<T>{coupled ? static_cast<T>(v.x) : id, coupled ? static_cast<T>(v.y) : T(0)};
 }
 
 // What one panel needs from the stencil, staged in LDS a panel ahead so that
@@ -92,14 +124,15 @@ __device__ __forceinline__ double2 stage_load(const double2 *__restrict__ lst, i
     const int e = d == 0 ? 0 : d == 1 ? 1 : d == nf ? 2 : 3;
     return lst[4LL * min(a.q, n - 1) + e];
 }
-__device__ __forceinline__ cplx<float> stage_value(int n, int nf, const StageRef &a, double2 v) {
+template <typename T>
+__device__ __forceinline__ cplx<T> stage_value(int n, int nf, const StageRef &a, double2 v) {
     const int d = a.r - a.q;
     const bool wrap = (a.r % nf) == 0;
     const bool in = a.r < n;
     const bool coupled = in && (d == 0 || d == nf || ((d == 1 || d == nf + 1) && !wrap));
-    const float id = (!in && d == 0) ? 1.0f : 0.0f;
-    const cplx<float> x{coupled ? static_cast<float>(v.x) : id, coupled ? static_cast<float>(v.y) : 0.0f};
-    return a.diag ? cplx<float>{sqrtf(cabs2(x)), 0.0f} : x;
+    const T id = (!in && d == 0) ? T(1) : T(0);
+    const cplx<T> x{coupled ? static_cast<T>(v.x) : id, coupled ? static_cast<T>(v.y) : T(0)};
+    return a.diag ? cplx<T>{sqrt(cabs2(x)), T(0)} : x;
 }
 
 // Rows of the panel factorisation: NW = 1 + ceil((M - 64) / 48) waves take
@@ -116,43 +149,43 @@ constexpr int panel_waves() { return M <= 64 ? 1 : 1 + (M - 64 + 47) / 48; }
 // for the first 16 rows, whose L goes to LT (every part reads those rows of
 // LP first).  Zero on and above the diagonal.  dg: lane k < 16 holds
 // |A_j(c0 + k, c0 + k)| for the pivot test.  The reciprocal of the pivot is
-// v_rcp_f32 based (within 1 ulp; complex64 factors).
-template <int M>
-__device__ __forceinline__ int factor_panel(cplx<float> *LP, cplx<float> *LT, cplx<float> *WB,
-                                            float dg, int c0, cplx<float> *__restrict__ Dinv,
-                                            int bad, int part) {
+// Prec<T>::rcp of |d|^2.
+template <typename T, int M>
+__device__ __forceinline__ int factor_panel(cplx<T> *LP, cplx<T> *LT, cplx<T> *WB, T dg, int c0,
+                                            cplx<T> *__restrict__ Dinv, int bad, int part) {
     const int lane = threadIdx.x & 63;
     const int row = part == 0 ? lane : lane < 16 ? lane : 64 + 48 * (part - 1) + lane - 16;
     const bool have = row < M;
-    cplx<float> x[16];
-    const cplx<float> *src = LP + min(row, M - 1) * kLdsStride;
+    const cplx<T> zero{T(0), T(0)};
+    cplx<T> x[16];
+    const cplx<T> *src = LP + min(row, M - 1) * kLdsStride;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = csel(have, src[k], cplx<float>{0.0f, 0.0f});
+    for (int k = 0; k < 16; ++k) x[k] = csel(have, src[k], zero);
     // lanes with nothing to store write the spare row M of LP / WB
-    cplx<float> *dl = lane < 16 ? (part == 0 ? LT + row * kLdsStride : LP + M * kLdsStride)
-                                : LP + min(row, M) * kLdsStride;
-    cplx<float> *dw = WB + (lane < 16 ? M : min(row, M)) * kLdsStride;
-    float pa = 0.0f;                // lane k: |d_k|^2, tested after the loop
-    cplx<float> dinv{0.0f, 0.0f};   // lane k: 1 / d_k
+    cplx<T> *dl = lane < 16 ? (part == 0 ? LT + row * kLdsStride : LP + M * kLdsStride)
+                            : LP + min(row, M) * kLdsStride;
+    cplx<T> *dw = WB + (lane < 16 ? M : min(row, M)) * kLdsStride;
+    T pa = T(0);                    // lane k: |d_k|^2, tested after the loop
+    cplx<T> dinv = zero;            // lane k: 1 / d_k
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        const cplx<float> w = x[k];                      // W[row, k] for row > k
-        const cplx<float> d = readlane(w, k);
-        const float m2 = cabs2(d);
+        const cplx<T> w = x[k];                          // W[row, k] for row > k
+        const cplx<T> d = readlane(w, k);
+        const T m2 = cabs2(d);
         pa = writelane(pa, m2, k);
-        const float rm = __builtin_amdgcn_rcpf(m2);
-        const cplx<float> inv{d.re * rm, -d.im * rm};
+        const T rm = Prec<T>::rcp(m2);
+        const cplx<T> inv{d.re * rm, -d.im * rm};
         dinv = writelane(dinv, inv, k);
-        const cplx<float> l = cmul(w, inv);
+        const cplx<T> l = cmul(w, inv);
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) x[j] = cfms(x[j], l, readlane(w, j));
         const bool below = row > k;
-        dl[k] = csel(below, l, cplx<float>{0.0f, 0.0f});
-        dw[k] = csel(below, w, cplx<float>{0.0f, 0.0f});
+        dl[k] = csel(below, l, zero);
+        dw[k] = csel(below, w, zero);
     }
     if (part == 0 && lane < 16) Dinv[c0 + lane] = dinv;
-    const float ad = sqrtf(pa);
-    const bool fail = lane < 16 && !(ad > 1e-6f * dg && ad < 1e30f);
+    const T ad = sqrt(pa);
+    const bool fail = lane < 16 && !(ad > Prec<T>::tol * dg && ad < T(1e30));
     const unsigned long long fm = __ballot(fail);
     if (bad < 0 && fm != 0) bad = c0 + __builtin_ctzll(fm);
     return bad;
@@ -174,29 +207,29 @@ __device__ __forceinline__ void lower_tile(int u, int &d, int &q) {
     q = left;
 }
 
-// OCC: the kernel is held to 128 registers, so that four workgroups (one
-// subdomain each) share a CU (at k = 640 all 1024 subdomains are then
-// resident at once; from NT = 6 on the window spills a little to fit).
-// Without it the compiler's own budget applies (146 registers at NT = 7:
-// three workgroups per CU, no spills).  Which is faster depends on the
-// window and the number of subdomains; the default is OCC up to NT = 7 and
-// the autotuner measures both.
-template <int NT, bool OCC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC ? 4 : 1))) void
-k_band_ldlt_mfma(const DevSub *__restrict__ subs,
-                                                        const int *__restrict__ order,
-                                                        const double2 *__restrict__ lst_all,
-                                                        cplx<float> *__restrict__ F,
-                                                        int *__restrict__ status) {
+// OCC: the kernel is held to the register budget of four workgroups per CU
+// (complex64: 128 registers; at k = 640 all 1024 subdomains are then
+// resident at once; from NT = 6 on the window spills a little to fit) or of
+// two (complex128: 256 registers).  Without it the compiler's own budget
+// applies (complex64: 146 registers at NT = 7, three workgroups per CU, no
+// spills).  Which is faster depends on the window and the number of
+// subdomains; the autotuner measures both.
+template <typename T, int NT, bool OCC>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(OCC ? (sizeof(T) == 4 ? 4 : 2) : 1))) void
+k_band_ldlt_mfma(const DevSub *__restrict__ subs, const int *__restrict__ order,
+                 const double2 *__restrict__ lst_all, cplx<T> *__restrict__ F,
+                 int *__restrict__ status) {
+    typedef typename Prec<T>::v4 v4;
     constexpr int M = 16 * NT;
     constexpr int NL = NT * (NT + 1) / 2;   // tiles on and below the diagonal
     constexpr int NS = (NL + 3) / 4;        // tile slots per wave
     static_assert(panel_waves<M>() <= 4, "panel rows per wave");
     // row M of LP and WB is a spare row for lanes with nothing to store
-    __shared__ cplx<float> LP[(M + 1) * kLdsStride];   // published panel, then L (rows 16..)
-    __shared__ cplx<float> LT[16 * kLdsStride];        // L of the panel's first 16 rows
-    __shared__ cplx<float> WB[(M + 1) * kLdsStride];   // W = L D (rows 16..)
-    __shared__ cplx<float> STG[2][80];                 // stencil staged per panel parity
+    __shared__ cplx<T> LP[(M + 1) * kLdsStride];   // published panel, then L (rows 16..)
+    __shared__ cplx<T> LT[16 * kLdsStride];        // L of the panel's first 16 rows
+    __shared__ cplx<T> WB[(M + 1) * kLdsStride];   // W = L D (rows 16..)
+    __shared__ cplx<T> STG[2][80];                 // stencil staged per panel parity
 
     const int sid = order[blockIdx.x];
     const DevSub S = subs[sid];
@@ -206,11 +239,13 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     const int fwave = blockIdx.x & 3;
     const int part = (wave - fwave) & 3;   // panel part of this wave
     const double2 *lst = lst_all + 4 * S.loc_off;
-    cplx<float> *L = F + S.fac_off;
-    cplx<float> *Rw = L + static_cast<long long>(npad) * W;   // rows of L, last first
-    cplx<float> *Dinv = Rw + static_cast<long long>(npad) * W;
-    const int ti = 4 * (lane >> 4), tj = lane & 15;   // accumulator element (ti + r, tj)
-    const cplx<float> zero{0.0f, 0.0f};
+    cplx<T> *L = F + S.fac_off;
+    cplx<T> *Rw = L + static_cast<long long>(npad) * W;   // rows of L, last first
+    cplx<T> *Dinv = Rw + static_cast<long long>(npad) * W;
+    // accumulator r of a tile holds its element (ti + RS r, tj)
+    constexpr int RS = Prec<T>::rs;
+    const int ti = Prec<T>::row0(lane), tj = lane & 15;
+    const cplx<T> zero{T(0), T(0)};
 
     // Row r < W of R has no columns before 0 at positions r+1 .. W-1.
     for (int i = tid; i < W * W; i += 256) {
@@ -221,7 +256,7 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     // slot s of this wave holds lower tile u = 4 s + wave: diagonal d, ring
     // slot q; at panel p its logical column is J = (q - p) mod (NT - d) and
     // its row I = J + d.  Window at panel 0: rows 16 I.., columns 16 J..
-    v4f cre[NS], cim[NS];
+    v4 cre[NS], cim[NS];
     int dg_[NS], jc_[NS];            // diagonal and current logical column of each slot
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -232,8 +267,8 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
         jc_[s] = q;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const cplx<float> v =
-                valid ? band_entry(lst, n, nf, 16 * (q + d) + ti + r, 16 * q + tj) : zero;
+            const cplx<T> v =
+                valid ? band_entry<T>(lst, n, nf, 16 * (q + d) + ti + RS * r, 16 * q + tj) : zero;
             cre[s][r] = v.re;
             cim[s][r] = v.im;
         }
@@ -245,7 +280,7 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     const int si = min(tid, 79);
     {
         const StageRef a = stage_ref(si, 0, M, nf);
-        const cplx<float> v = stage_value(n, nf, a, stage_load(lst, n, nf, a));
+        const cplx<T> v = stage_value<T>(n, nf, a, stage_load(lst, n, nf, a));
         if (tid < 80) STG[0][tid] = v;
     }
     lds_barrier();
@@ -253,14 +288,14 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
         const int buf = (c0 >> 4) & 1;
         // the next panel's entries: loaded now, stored at the end of the panel
         const double2 rnext = stage_load(lst, n, nf, stage_ref(si, c0 + 16, M, nf));
-        const float dg = STG[buf][64 + tj].re;
+        const T dg = STG[buf][64 + tj].re;
         // 1. publish logical tile column 0 (J == 0 on every diagonal)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (dg_[s] >= 0 && jc_[s] == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    LP[(16 * dg_[s] + ti + r) * kLdsStride + tj] = cplx<float>{cre[s][r], cim[s][r]};
+                    LP[(16 * dg_[s] + ti + RS * r) * kLdsStride + tj] = cplx<T>{cre[s][r], cim[s][r]};
             }
         }
         lds_barrier();
@@ -268,7 +303,7 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
         // parts 0 .. NW-1 on waves fwave, fwave+1, ... (mod 4): the choice
         // rotates with the workgroup so that the workgroups sharing a CU
         // tend to factorise on different SIMDs
-        if (part < panel_waves<M>()) bad = factor_panel<M>(LP, LT, WB, dg, c0, Dinv, bad, part);
+        if (part < panel_waves<M>()) bad = factor_panel<T, M>(LP, LT, WB, dg, c0, Dinv, bad, part);
         lds_barrier();
         // 3. columns c0 .. c0+15 of L (slot order) and their entries in the
         //    rows of L; row r's entry of column c sits at position c mod W
@@ -286,7 +321,7 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
                     // one LDS read through a select of the two LDS arrays, the
                     // zero selected as a value (a select with a local would make a
                     // generic pointer and flat loads that wait on the stores)
-                    const cplx<float> v = (rr < 16 ? LT : LP)[rr * kLdsStride + k];
+                    const cplx<T> v = (rr < 16 ? LT : LP)[rr * kLdsStride + k];
                     L[static_cast<long long>(c) * W + pos] = csel(r == c, zero, v);
                 }
             }
@@ -320,31 +355,31 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const int col = 4 * kk + (lane >> 4);
-                        const cplx<float> l = LP[(16 * I + tj) * kLdsStride + col];
-                        const cplx<float> w = WB[(16 * J + tj) * kLdsStride + col];
-                        cre[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.re, w.re, cre[s], 0, 0, 0);
-                        cre[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(l.im, w.im, cre[s], 0, 0, 0);
-                        cim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.re, w.im, cim[s], 0, 0, 0);
-                        cim[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(-l.im, w.re, cim[s], 0, 0, 0);
+                        const cplx<T> l = LP[(16 * I + tj) * kLdsStride + col];
+                        const cplx<T> w = WB[(16 * J + tj) * kLdsStride + col];
+                        cre[s] = Prec<T>::mfma(-l.re, w.re, cre[s]);
+                        cre[s] = Prec<T>::mfma(l.im, w.im, cre[s]);
+                        cim[s] = Prec<T>::mfma(-l.re, w.im, cim[s]);
+                        cim[s] = Prec<T>::mfma(-l.im, w.re, cim[s]);
                     }
                 } else {
                     // next window: row NT - 1, column NT - 1 - d, from the
-                    // staged couplings of the entering rows; entry (ti + r,
-                    // tj) of the tile lies dd = 16 d + ti + r - tj below the
+                    // staged couplings of the entering rows; entry (ti + RS r,
+                    // tj) of the tile lies dd = 16 d + ti + RS r - tj below the
                     // diagonal
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int dd = 16 * d + tdiff + r;
+                        const int dd = 16 * d + tdiff + RS * r;
                         const int e = dd == 0 ? 0 : dd == 1 ? 1 : dd == nf ? 2 : dd == nf + 1 ? 3 : -1;
-                        const cplx<float> v = STG[buf][4 * (ti + r) + max(e, 0)];
-                        cre[s][r] = e >= 0 ? v.re : 0.0f;
-                        cim[s][r] = e >= 0 ? v.im : 0.0f;
+                        const cplx<T> v = STG[buf][4 * (ti + RS * r) + max(e, 0)];
+                        cre[s][r] = e >= 0 ? v.re : T(0);
+                        cim[s][r] = e >= 0 ? v.im : T(0);
                     }
                 }
             }
         }
         {
-            const cplx<float> v = stage_value(n, nf, stage_ref(si, c0 + 16, M, nf), rnext);
+            const cplx<T> v = stage_value<T>(n, nf, stage_ref(si, c0 + 16, M, nf), rnext);
             if (tid < 80) STG[buf ^ 1][tid] = v;
         }
         lds_barrier();
@@ -352,15 +387,30 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs,
     if (part == 0 && lane == 0) status[sid] = bad;
 }
 
-template <int NT>
+template <typename T, int NT>
 void launch_nt(bool occ, const DevSub *subs, const int *order, int count, const double2 *lst,
                void *F, int *status, hipStream_t st) {
     if (occ)
-        hipLaunchKernelGGL((k_band_ldlt_mfma<NT, true>), dim3(count), dim3(256), 0, st, subs, order,
-                           lst, static_cast<cplx<float> *>(F), status);
+        hipLaunchKernelGGL((k_band_ldlt_mfma<T, NT, true>), dim3(count), dim3(256), 0, st, subs,
+                           order, lst, static_cast<cplx<T> *>(F), status);
     else
-        hipLaunchKernelGGL((k_band_ldlt_mfma<NT, false>), dim3(count), dim3(256), 0, st, subs,
-                           order, lst, static_cast<cplx<float> *>(F), status);
+        hipLaunchKernelGGL((k_band_ldlt_mfma<T, NT, false>), dim3(count), dim3(256), 0, st, subs,
+                           order, lst, static_cast<cplx<T> *>(F), status);
+}
+
+template <typename T>
+void launch_t(int NT, bool occ, const DevSub *subs, const int *order, int count,
+              const double2 *lst, void *F, int *status, hipStream_t st) {
+    switch (NT) {
+        case 2: launch_nt<T, 2>(occ, subs, order, count, lst, F, status, st); break;
+        case 3: launch_nt<T, 3>(occ, subs, order, count, lst, F, status, st); break;
+        case 4: launch_nt<T, 4>(occ, subs, order, count, lst, F, status, st); break;
+        case 5: launch_nt<T, 5>(occ, subs, order, count, lst, F, status, st); break;
+        case 6: launch_nt<T, 6>(occ, subs, order, count, lst, F, status, st); break;
+        case 7: launch_nt<T, 7>(occ, subs, order, count, lst, F, status, st); break;
+        case 8: launch_nt<T, 8>(occ, subs, order, count, lst, F, status, st); break;
+        default: launch_nt<T, 9>(occ, subs, order, count, lst, F, status, st); break;
+    }
 }
 
 }  // namespace
@@ -369,21 +419,15 @@ void launch_nt(bool occ, const DevSub *subs, const int *order, int count, const 
 int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }
 
 // Default register budget of a window class (see k_band_ldlt_mfma).
-bool ldlt_mfma_default_occ(int NT) { return NT <= 7; }
+bool ldlt_mfma_default_occ(bool fp64, int NT) { return fp64 ? true : NT <= 7; }
 
 // count subdomains order[0 .. count) that all have ldlt_mfma_tiles(W) == NT.
-void launch_band_ldlt_mfma(int NT, bool occ, const DevSub *subs, const int *order, int count,
-                           const double2 *lst, void *F, int *status, hipStream_t st) {
-    switch (NT) {
-        case 2: launch_nt<2>(occ, subs, order, count, lst, F, status, st); break;
-        case 3: launch_nt<3>(occ, subs, order, count, lst, F, status, st); break;
-        case 4: launch_nt<4>(occ, subs, order, count, lst, F, status, st); break;
-        case 5: launch_nt<5>(occ, subs, order, count, lst, F, status, st); break;
-        case 6: launch_nt<6>(occ, subs, order, count, lst, F, status, st); break;
-        case 7: launch_nt<7>(occ, subs, order, count, lst, F, status, st); break;
-        case 8: launch_nt<8>(occ, subs, order, count, lst, F, status, st); break;
-        default: launch_nt<9>(occ, subs, order, count, lst, F, status, st); break;
-    }
+void launch_band_ldlt_mfma(bool fp64, int NT, bool occ, const DevSub *subs, const int *order,
+                           int count, const double2 *lst, void *F, int *status, hipStream_t st) {
+    if (fp64)
+        launch_t<double>(NT, occ, subs, order, count, lst, F, status, st);
+    else
+        launch_t<float>(NT, occ, subs, order, count, lst, F, status, st);
 }
 
 }  // namespace raspml
