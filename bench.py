@@ -678,13 +678,25 @@ def batch32(dev, no_fp64):
     f = torch.from_numpy(np.concatenate(fs)).to(dev)
     res = {"problems": 32, "unknowns": int(f.numel()),
            "subdomains": int(sum(P * Q for P, Q in subs))}
+    import tempfile
     for name, prec in (("mixed", rp.RAS_MIXED), ("fp64", rp.RAS_FP64)):
         if name == "fp64" and no_fp64:
             continue
+        # the tuner on this batch (bands 36..68: window classes of 3..5
+        # tiles), its timings reported; the timed runs use its choices
+        cache = os.path.join(tempfile.gettempdir(), "ras_pml_tune_batch32_%s_%d.json"
+                             % (name, os.getpid()))
+        Ht = rp.ras_pml_setup_batch(ks, hs, grids, subs, ovs, ovs, rp.default_opts(precision=prec))
+        rp.ras_pml_autotune(Ht, cache)
+        tun = rp.ras_pml_tuning(Ht)
+        times = rp.ras_pml_tune_report(Ht)
+        Ht.close()
+        opts = rp.default_opts(precision=prec)
+        opts.tune_cache = os.fsencode(cache)
         for rep in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            H = rp.ras_pml_setup_batch(ks, hs, grids, subs, ovs, ovs, rp.default_opts(precision=prec))
+            H = rp.ras_pml_setup_batch(ks, hs, grids, subs, ovs, ovs, opts)
             b = torch.empty_like(f)
             x = torch.zeros_like(f)
             rp.ras_pml_rhs(H, f, b)
@@ -701,7 +713,14 @@ def batch32(dev, no_fp64):
                      "status": rc,
                      "iters_max": max(p[0] for p in per), "iters_min": min(p[0] for p in per),
                      "all_converged": all(p[2] for p in per),
-                     "relres_max": max(p[1] for p in per)}
+                     "relres_max": max(p[1] for p in per),
+                     "tuning": {"band_solve_deep_prefetch": tun["solve_deep"],
+                                "band_solve_queue": tun["solve_queue"],
+                                "factor_classes": [{"tiles": g[0], "subdomains": g[1],
+                                                    "variant": LU_VARIANTS[g[2]]}
+                                                   for g in tun["ldlt"]],
+                                "times_ms": times}}
+        os.remove(cache)
     return res
 
 

@@ -36,12 +36,18 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
     return static_cast<bf16>(u >> 16);
 }
 // out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
-// NT: output channel tiles.  OUT_F32: write the first `creal` channels as
-// fp32 (the network's head).  gate (nullable, shaped as the output): values
-// are kept only where the gate is positive (the ReLU mask of the tensor
-// whose gradient this is; a post-ReLU value is positive exactly when its
-// bits are non-zero).
-template <int NT, bool OUT_F32>
+// NT: output channel tiles; PT: tiles of 16 output pixels per wave (the
+// weights of a tap are loaded once for all of them).  The matrix-core
+// product is D[co][p] = W^T X^T: A is the weight block (lane: output channel
+// lane & 15, input channels 4 (lane >> 4) .. + 3), B the gathered input
+// (lane: pixel lane & 15, the same four input channels, one 8-byte load),
+// so each lane ends with four consecutive output channels of one pixel and
+// writes them with one 8-byte store.  OUT_F32: write the first `creal`
+// (<= 4) channels as fp32 (the network's head).  gate (nullable, shaped as
+// the output): values are kept only where the gate is positive (the ReLU
+// mask of the tensor whose gradient this is; a post-ReLU value is positive
+// exactly when its bits are non-zero).
+template <int NT, int PT, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
                                                  const bf16 *__restrict__ Wp, void *__restrict__ Y,
                                                  const bf16 *__restrict__ gate, int B, int H, int W,
@@ -49,56 +55,91 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
     constexpr int CPout = 16 * NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int M = B * H * W;                // M * 64 < 2^31 (checked at creation)
-    const int p0 = (blockIdx.x * 4 + wave) * 16;
-    if (p0 >= M) return;                    // no barrier in this kernel
+    const int pw0 = (blockIdx.x * 4 + wave) * 16 * PT;
+    if (pw0 >= M) return;                   // no barrier in this kernel
     const int i = lane & 15, kq = lane >> 4;
-    const int p = p0 + i;
-    const bool pin = p < M;
-    const int pc = pin ? p : M - 1;
-    const int x = pc % W, y = (pc / W) % H;
-    // border flags of the pixel, then each tap is a uniform offset from it
-    const bool xlo = x > 0, xhi = x < W - 1, ylo = y > 0, yhi = y < H - 1;
-    const bf16 *xc = X + pc * CPin + 4 * kq;
-    v4f c[NT];
+    // the lane's pixel in each tile, its border flags (each tap is then a
+    // uniform offset from it)
+    const bf16 *xc[PT];
+    unsigned char fl[PT];                   // bit0 x>0, bit1 x<W-1, bit2 y>0, bit3 y<H-1, bit4 in
 #pragma unroll
-    for (int t = 0; t < NT; ++t) c[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < PT; ++u) {
+        const int p = pw0 + 16 * u + i;
+        const bool pin = p < M;
+        const int pc = pin ? p : M - 1;
+        const int x = pc % W, y = (pc / W) % H;
+        fl[u] = static_cast<unsigned char>((x > 0) | ((x < W - 1) << 1) | ((y > 0) << 2) |
+                                           ((y < H - 1) << 3) | (pin << 4));
+        xc[u] = X + pc * CPin + 4 * kq;
+    }
+    v4f c[PT][NT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
     const int KC = CPin >> 4;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const bool ok = pin && (dy < 0 ? ylo : (dy > 0 ? yhi : true)) &&
-                        (dx < 0 ? xlo : (dx > 0 ? xhi : true));
-        const bf16 *xr = xc + (ok ? (dy * W + dx) * CPin : 0);
+        const unsigned need = 16u | (dx < 0 ? 1u : dx > 0 ? 2u : 0u) | (dy < 0 ? 4u : dy > 0 ? 8u : 0u);
+        const int off = (dy * W + dx) * CPin;
         const bf16 *wb = Wp + tap * KC * NT * 256 + i * 16 + 4 * kq;
         for (int kc = 0; kc < KC; ++kc) {
-            v4s a = *reinterpret_cast<const v4s *>(xr + 16 * kc);
-            if (!ok) a = v4s{0, 0, 0, 0};
+            v4s wt[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const v4s bb = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
-                c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, c[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
+#pragma unroll
+            for (int u = 0; u < PT; ++u) {
+                const bool ok = (fl[u] & need) == need;
+                v4s a = *reinterpret_cast<const v4s *>(xc[u] + (ok ? off : 0) + 16 * kc);
+                if (!ok) a = v4s{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    c[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[t], a, c[u][t], 0, 0, 0);
             }
         }
     }
-    // lane holds D[4 kq + r][i] of every tile: pixel p0 + 4 kq + r, channel 16 t + i
+    // lane holds D[4 kq + r][i] of every tile: channel 16 t + 4 kq + r of pixel
+    // pw0 + 16 u + i
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int u = 0; u < PT; ++u) {
+        const int po = pw0 + 16 * u + i;
+        if (po >= M) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int po = p0 + 4 * kq + r;
-            if (po >= M) continue;
-            float v = c[t][r];
-            if (relu) v = fmaxf(v, 0.f);
-            const int ch = 16 * t + i;
+        for (int t = 0; t < NT; ++t) {
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = relu ? fmaxf(c[u][t][r], 0.f) : c[u][t][r];
+            const int ch = 16 * t + 4 * kq;
             if (OUT_F32) {
-                if (ch < creal) static_cast<float *>(Y)[po * creal + ch] = v;
+                float *yf = static_cast<float *>(Y) + static_cast<long long>(po) * creal;
+                if (t == 0 && kq == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < creal) yf[r] = v[r];
+                }
             } else {
-                bf16 *yb = static_cast<bf16 *>(Y) + po * CPout + ch;
-                if (acc) v += bf2f(*yb);
-                if (gate != nullptr && gate[po * CPout + ch] == 0) v = 0.f;
-                *yb = f2bf(v);
+                bf16 *yb = static_cast<bf16 *>(Y) + static_cast<long long>(po) * CPout + ch;
+                if (acc) {
+                    const uint2 q = *reinterpret_cast<const uint2 *>(yb);
+                    v[0] += __uint_as_float(q.x << 16);
+                    v[1] += __uint_as_float(q.x & 0xFFFF0000u);
+                    v[2] += __uint_as_float(q.y << 16);
+                    v[3] += __uint_as_float(q.y & 0xFFFF0000u);
+                }
+                if (gate != nullptr) {
+                    const uint2 q = *reinterpret_cast<const uint2 *>(gate + static_cast<long long>(po) * CPout + ch);
+                    if ((q.x & 0xFFFFu) == 0) v[0] = 0.f;
+                    if ((q.x >> 16) == 0) v[1] = 0.f;
+                    if ((q.y & 0xFFFFu) == 0) v[2] = 0.f;
+                    if ((q.y >> 16) == 0) v[3] = 0.f;
+                }
+                *reinterpret_cast<uint2 *>(yb) =
+                    uint2{static_cast<unsigned>(f2bf(v[0])) | (static_cast<unsigned>(f2bf(v[1])) << 16),
+                          static_cast<unsigned>(f2bf(v[2])) | (static_cast<unsigned>(f2bf(v[3])) << 16)};
             }
         }
+    }
 }
 
 // Partial weight gradient of one pixel chunk:
@@ -273,99 +314,164 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restric
                 pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = c[tap][t][r];
 }
 
-// g[idx] = sum over blocks of part[blk][idx]: 32 slices of the blocks are
-// summed in order by 32 threads, then the slice sums in slice order
-// (the same order at every launch: deterministic).
-__global__ __launch_bounds__(256) void k_sum_partials(const float *__restrict__ part, int nblk,
-                                                      int n, float *__restrict__ g) {
-    __shared__ float red[8][33];
-    const int sl = threadIdx.x & 31, o = threadIdx.x >> 5;     // slice, output in block
-    const int idx = blockIdx.x * 8 + o;
+// g[idx] = sum over blocks of part[blk][idx], in two stages with a fixed
+// order (deterministic): slice s of the blocks, [s per, (s + 1) per), is
+// summed in block order into tmp[s][idx]; then the slices in slice order.
+// Consecutive threads take consecutive idx, so every load is coalesced.
+constexpr int kSumSlices = 32;
+__global__ __launch_bounds__(256) void k_sum_slices(const float *__restrict__ part, int nblk,
+                                                    int n, int per, float *__restrict__ tmp) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    const int k0 = blockIdx.y * per, k1 = min(k0 + per, nblk);
     float s = 0.f;
-    if (idx < n)
-        for (int k = sl; k < nblk; k += 32) s += part[static_cast<long long>(k) * n + idx];
-    red[o][sl] = s;
-    __syncthreads();
-    if (sl == 0 && idx < n) {
-        float t = 0.f;
-        for (int j = 0; j < 32; ++j) t += red[o][j];
-        g[idx] = t;
+    for (int k = k0; k < k1; ++k) s += part[static_cast<long long>(k) * n + idx];
+    tmp[static_cast<long long>(blockIdx.y) * n + idx] = s;
+}
+__global__ __launch_bounds__(256) void k_sum_tmp(const float *__restrict__ tmp, int n,
+                                                 float *__restrict__ g) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kSumSlices; ++k) s += tmp[static_cast<long long>(k) * n + idx];
+    g[idx] = s;
+}
+
+// Eight bfloat16 values (16 bytes) <-> floats, for the elementwise kernels:
+// every thread moves 16 bytes per tensor (channels are a multiple of 16).
+struct bf8 {
+    float f[8];
+};
+__device__ __forceinline__ bf8 ld8(const bf16 *p) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    const unsigned u[4] = {q.x, q.y, q.z, q.w};
+    bf8 r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r.f[2 * k] = __uint_as_float(u[k] << 16);
+        r.f[2 * k + 1] = __uint_as_float(u[k] & 0xFFFF0000u);
+    }
+    return r;
+}
+__device__ __forceinline__ void st8(bf16 *p, const bf8 &v) {
+    unsigned u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        u[k] = static_cast<unsigned>(f2bf(v.f[2 * k])) |
+               (static_cast<unsigned>(f2bf(v.f[2 * k + 1])) << 16);
+    *reinterpret_cast<uint4 *>(p) = uint4{u[0], u[1], u[2], u[3]};
+}
+// Zero the values whose gate bits are zero (a post-ReLU value is positive
+// exactly when its bits are non-zero).
+__device__ __forceinline__ void gate8(bf8 &v, const bf16 *g) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(g);
+    const unsigned u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if ((u[k] & 0xFFFFu) == 0) v.f[2 * k] = 0.f;
+        if ((u[k] >> 16) == 0) v.f[2 * k + 1] = 0.f;
     }
 }
 
-// 2 x 2 mean: Y (B, H/2, W/2, C) from X (B, H, W, C).
+// 2 x 2 mean: Y (B, H/2, W/2, C) from X (B, H, W, C); eight channels per
+// thread.
 __global__ void k_pool2(const bf16 *__restrict__ X, bf16 *__restrict__ Y, int B, int H, int W,
                         int C) {
-    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
+    const int C8 = C >> 3;
+    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C8;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const int c = static_cast<int>(o % C);
-    const long long pix = o / C;
+    const int c = static_cast<int>(o % C8) * 8;
+    const long long pix = o / C8;
     const int x = static_cast<int>(pix % (W / 2)), y = static_cast<int>((pix / (W / 2)) % (H / 2));
     const long long b = pix / (static_cast<long long>(W / 2) * (H / 2));
     const long long base = ((b * H + 2 * y) * W + 2 * x) * C + c;
-    const float s = bf2f(X[base]) + bf2f(X[base + C]) + bf2f(X[base + static_cast<long long>(W) * C]) +
-                    bf2f(X[base + static_cast<long long>(W) * C + C]);
-    Y[o] = f2bf(0.25f * s);
+    const bf8 a0 = ld8(X + base), a1 = ld8(X + base + C), a2 = ld8(X + base + static_cast<long long>(W) * C),
+              a3 = ld8(X + base + static_cast<long long>(W) * C + C);
+    bf8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.f[k] = 0.25f * (a0.f[k] + a1.f[k] + a2.f[k] + a3.f[k]);
+    st8(Y + pix * C + c, r);
 }
 
 // dX (B, H, W, C) = dY (B, H/2, W/2, C) / 4 spread over each block, plus
-// `add`, kept where `gate` (nullable) is positive.
+// `add`, kept where `gate` (nullable) is positive; eight channels per thread.
 __global__ void k_pool2_bwd(const bf16 *__restrict__ dY, const bf16 *__restrict__ add,
                             const bf16 *__restrict__ gate, bf16 *__restrict__ dX, int B, int H,
                             int W, int C) {
-    const long long n = static_cast<long long>(B) * H * W * C;
+    const int C8 = C >> 3;
+    const long long n = static_cast<long long>(B) * H * W * C8;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const int c = static_cast<int>(o % C);
-    const long long pix = o / C;
+    const int c = static_cast<int>(o % C8) * 8;
+    const long long pix = o / C8;
     const int x = static_cast<int>(pix % W), y = static_cast<int>((pix / W) % H);
     const long long b = pix / (static_cast<long long>(W) * H);
-    float v = 0.25f * bf2f(dY[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
-    if (add != nullptr) v += bf2f(add[o]);
-    if (gate != nullptr && gate[o] == 0) v = 0.f;
-    dX[o] = f2bf(v);
+    const long long e = pix * C + c;
+    bf8 v = ld8(dY + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v.f[k] *= 0.25f;
+    if (add != nullptr) {
+        const bf8 a = ld8(add + e);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v.f[k] += a.f[k];
+    }
+    if (gate != nullptr) gate8(v, gate + e);
+    st8(dX + e, v);
 }
 
-// S (B, H, W, C) = nearest upsampling of Yc (B, H/2, W/2, C) + E.
+// S (B, H, W, C) = nearest upsampling of Yc (B, H/2, W/2, C) + E; eight
+// channels per thread.
 __global__ void k_up2_add(const bf16 *__restrict__ Yc, const bf16 *__restrict__ E,
                           bf16 *__restrict__ S, int B, int H, int W, int C) {
-    const long long n = static_cast<long long>(B) * H * W * C;
+    const int C8 = C >> 3;
+    const long long n = static_cast<long long>(B) * H * W * C8;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const int c = static_cast<int>(o % C);
-    const long long pix = o / C;
+    const int c = static_cast<int>(o % C8) * 8;
+    const long long pix = o / C8;
     const int x = static_cast<int>(pix % W), y = static_cast<int>((pix / W) % H);
     const long long b = pix / (static_cast<long long>(W) * H);
-    const float v = bf2f(Yc[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]) + bf2f(E[o]);
-    S[o] = f2bf(v);
+    const long long e = pix * C + c;
+    bf8 v = ld8(Yc + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+    const bf8 a = ld8(E + e);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v.f[k] += a.f[k];
+    st8(S + e, v);
 }
 
 // dYc (B, H/2, W/2, C) = sum of dS over each 2 x 2 block, kept where `gate`
-// (nullable, shaped as dYc) is positive.
+// (nullable, shaped as dYc) is positive; eight channels per thread.
 __global__ void k_up2_bwd(const bf16 *__restrict__ dS, const bf16 *__restrict__ gate,
                           bf16 *__restrict__ dYc, int B, int H, int W, int C) {
-    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
+    const int C8 = C >> 3;
+    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C8;
     const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (o >= n) return;
-    const int c = static_cast<int>(o % C);
-    const long long pix = o / C;
+    const int c = static_cast<int>(o % C8) * 8;
+    const long long pix = o / C8;
     const int x = static_cast<int>(pix % (W / 2)), y = static_cast<int>((pix / (W / 2)) % (H / 2));
     const long long b = pix / (static_cast<long long>(W / 2) * (H / 2));
     const long long base = ((b * H + 2 * y) * W + 2 * x) * C + c;
-    float s = bf2f(dS[base]) + bf2f(dS[base + C]) + bf2f(dS[base + static_cast<long long>(W) * C]) +
-              bf2f(dS[base + static_cast<long long>(W) * C + C]);
-    if (gate != nullptr && gate[o] == 0) s = 0.f;
-    dYc[o] = f2bf(s);
+    const bf8 a0 = ld8(dS + base), a1 = ld8(dS + base + C), a2 = ld8(dS + base + static_cast<long long>(W) * C),
+              a3 = ld8(dS + base + static_cast<long long>(W) * C + C);
+    bf8 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.f[k] = a0.f[k] + a1.f[k] + a2.f[k] + a3.f[k];
+    if (gate != nullptr) gate8(r, gate + pix * C + c);
+    st8(dYc + pix * C + c, r);
 }
 
 // Two-channel fp32 grid (B, G, G, 2) -> bf16 input with 16 channels.
 __global__ void k_pack_input(const float *__restrict__ x, bf16 *__restrict__ X, long long npix) {
-    const long long o = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (o >= npix * 16) return;
-    const long long p = o >> 4;
-    const int c = static_cast<int>(o & 15);
-    X[o] = c < 2 ? f2bf(x[2 * p + c]) : bf16(0);
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float2 v = *reinterpret_cast<const float2 *>(x + 2 * p);
+    const unsigned u = static_cast<unsigned>(f2bf(v.x)) | (static_cast<unsigned>(f2bf(v.y)) << 16);
+    uint4 *q = reinterpret_cast<uint4 *>(X + 16 * p);
+    q[0] = uint4{u, 0u, 0u, 0u};
+    q[1] = uint4{0u, 0u, 0u, 0u};
 }
 
 // Squared error: per-block partial sums (double) and the gradient of the
@@ -477,24 +583,33 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 
 // ---------------------------------------------------------------- launchers
 // B * H * W < 2^31 (the network object checks it at creation).
+// Pixel tiles per wave: four (a workgroup takes 256 pixels) where there are
+// enough pixels to fill the chip that way, else one.
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
-    const dim3 grid(blocks(M, 64)), blk(256);
+    const bool wide = M >= 256LL * 1024;
+    const dim3 grid(blocks(M, wide ? 256 : 64)), blk(256);
     const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
                *g = static_cast<const bf16 *>(gate);
-#define RAS_CONV(NT, F32)                                                                        \
-    hipLaunchKernelGGL((k_conv3x3<NT, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W, CPin,        \
+#define RAS_CONV(NT, PT, F32)                                                                    \
+    hipLaunchKernelGGL((k_conv3x3<NT, PT, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W, CPin,    \
                        relu ? 1 : 0, acc ? 1 : 0, creal)
+#define RAS_CONV_PT(NT, F32)                       \
+    do {                                           \
+        if (wide) RAS_CONV(NT, 4, F32);            \
+        else RAS_CONV(NT, 1, F32);                 \
+    } while (0)
     if (out_f32) {
-        RAS_CONV(1, true);
+        RAS_CONV_PT(1, true);
     } else if (CPout == 16) {
-        RAS_CONV(1, false);
+        RAS_CONV_PT(1, false);
     } else if (CPout == 32) {
-        RAS_CONV(2, false);
+        RAS_CONV_PT(2, false);
     } else {
-        RAS_CONV(4, false);
+        RAS_CONV_PT(4, false);
     }
+#undef RAS_CONV_PT
 #undef RAS_CONV
 }
 
@@ -506,8 +621,16 @@ int warm_wgrad_blocks(long long M, int *chunk) {
     return static_cast<int>((M + c - 1) / c);
 }
 
-void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int H, int W,
-                int CPin, int CPout, hipStream_t s) {
+// g = sum of the nblk partial gradients (n values each), tmp: kSumSlices * n.
+void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipStream_t s) {
+    const int per = (nblk + kSumSlices - 1) / kSumSlices;
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks(n, 256), kSumSlices), dim3(256), 0, s, part, nblk, n,
+                       per, tmp);
+    hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(n, 256)), dim3(256), 0, s, tmp, n, g);
+}
+
+void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
+                int W, int CPin, int CPout, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
     int chunk = 0;
     const int nblk = warm_wgrad_blocks(M, &chunk);
@@ -520,7 +643,7 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int
         else
             hipLaunchKernelGGL(k_conv3x3_wgrad_k16<2>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
                                W, chunk);
-        hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, 4 * nblk, n, g);
+        sum_partials(part, 4 * nblk, n, tmp, g, s);
         return;
     }
 #define RAS_WG(NT, KC)                                                                           \
@@ -540,35 +663,35 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int
         RAS_WG_KC(4);
 #undef RAS_WG_KC
 #undef RAS_WG
-    hipLaunchKernelGGL(k_sum_partials, dim3(blocks(n, 8)), dim3(256), 0, s, part, nblk, n, g);
+    sum_partials(part, nblk, n, tmp, g, s);
 }
 
 
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s) {
-    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
+    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * (C / 8);
     hipLaunchKernelGGL(k_pool2, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(X),
                        static_cast<bf16 *>(Y), B, H, W, C);
 }
 void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
                    int W, int C, hipStream_t s) {
-    const long long n = static_cast<long long>(B) * H * W * C;
+    const long long n = static_cast<long long>(B) * H * W * (C / 8);
     hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks(n, 256)), dim3(256), 0, s,
                        static_cast<const bf16 *>(dY), static_cast<const bf16 *>(add),
                        static_cast<const bf16 *>(gate), static_cast<bf16 *>(dX), B, H, W, C);
 }
 void warm_up_add(const void *Yc, const void *E, void *S, int B, int H, int W, int C, hipStream_t s) {
-    const long long n = static_cast<long long>(B) * H * W * C;
+    const long long n = static_cast<long long>(B) * H * W * (C / 8);
     hipLaunchKernelGGL(k_up2_add, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(Yc),
                        static_cast<const bf16 *>(E), static_cast<bf16 *>(S), B, H, W, C);
 }
 void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int W, int C,
                  hipStream_t s) {
-    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * C;
+    const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * (C / 8);
     hipLaunchKernelGGL(k_up2_bwd, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(dS),
                        static_cast<const bf16 *>(gate), static_cast<bf16 *>(dYc), B, H, W, C);
 }
 void warm_pack_input(const float *x, void *X, long long npix, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_input, dim3(blocks(npix * 16, 256)), dim3(256), 0, s, x,
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks(npix, 256)), dim3(256), 0, s, x,
                        static_cast<bf16 *>(X), npix);
 }
 void warm_mse(const float *y, const float *t, long long npix, double *partial, int nblk, void *dY,

@@ -33,8 +33,8 @@ namespace raspml {
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
 int warm_wgrad_blocks(long long M, int *chunk);
-void warm_wgrad(const void *X, const void *dZ, float *part, float *g, int B, int H, int W,
-                int CPin, int CPout, hipStream_t s);
+void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
+                int W, int CPin, int CPout, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
 void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
                    int W, int C, hipStream_t s);
@@ -71,7 +71,7 @@ struct ras_pml_wsnet {
     void *gy = nullptr, *gp[5] = {}, *gs[4] = {};
     void *dz = nullptr;                 // the current layer's output gradient, ReLU-masked
     float *y = nullptr, *stage = nullptr;
-    float *part = nullptr;
+    float *part = nullptr, *psum = nullptr;   // weight-gradient partials, slice sums
     double *lpart = nullptr, *loss = nullptr;
     long long step = 0;
     std::vector<void *> allocs;
@@ -134,14 +134,14 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     // tensor it belongs to, into dz, which the next layer's weight gradient
     // and input gradient then read.
     // head (no ReLU): gradient of d0
-    warm_wgrad(N->d[0], N->gy, N->part, N->g[9], B, G, G, C[0], 16, st);
+    warm_wgrad(N->d[0], N->gy, N->part, N->psum, N->g[9], B, G, G, C[0], 16, st);
     warm_conv(N->gy, N->wb[9], N->dz, N->d[0], B, G, G, 16, C[0], false, false, false, 0, st);
     // decoder, level 0 up to 3
     const int din[4] = {C[0], C[1], C[2], C[3]};
     const int dout[4] = {C[0], C[0], C[1], C[2]};
     for (int l = 0; l <= 3; ++l) {
         const int S = N->side(l), L = 5 + (3 - l);
-        warm_wgrad(N->s[l], N->dz, N->part, N->g[L], B, S, S, din[l], dout[l], st);
+        warm_wgrad(N->s[l], N->dz, N->part, N->psum, N->g[L], B, S, S, din[l], dout[l], st);
         warm_conv(N->dz, N->wb[L], N->gs[l], nullptr, B, S, S, dout[l], din[l], false, false, false, 0,
                   st);
         const void *below = l < 3 ? N->d[l + 1] : N->e[4];   // the tensor one level down
@@ -150,12 +150,12 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     // encoder, level 4 down to 1; the skip gradient of s_{l-1} joins e_{l-1}
     for (int l = 4; l >= 1; --l) {
         const int S = N->side(l);
-        warm_wgrad(N->p[l], N->dz, N->part, N->g[l], B, S, S, C[l - 1], C[l], st);
+        warm_wgrad(N->p[l], N->dz, N->part, N->psum, N->g[l], B, S, S, C[l - 1], C[l], st);
         warm_conv(N->dz, N->wb[l], N->gp[l], nullptr, B, S, S, C[l], C[l - 1], false, false, false, 0,
                   st);
         warm_pool_bwd(N->gp[l], N->gs[l - 1], N->e[l - 1], N->dz, B, 2 * S, 2 * S, C[l - 1], st);
     }
-    warm_wgrad(N->xin, N->dz, N->part, N->g[0], B, G, G, 16, C[0], st);
+    warm_wgrad(N->xin, N->dz, N->part, N->psum, N->g[0], B, G, G, 16, C[0], st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -211,13 +211,14 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     const int cin[kLayers] = {2, c[0], c[1], c[2], c[3], c[4], c[2], c[1], c[0], c[0]};
     const int cout[kLayers] = {c[0], c[1], c[2], c[3], c[4], c[2], c[1], c[0], c[0], 2};
     const int lvl[kLayers] = {0, 1, 2, 3, 4, 3, 2, 1, 0, 0};
-    size_t part_max = 0;
+    size_t part_max = 0, np_max = 0;
     for (int L = 0; L < kLayers; ++L) {
         N->cin[L] = cin[L];
         N->cout[L] = cout[L];
         N->lvl[L] = lvl[L];
         const size_t nw = 9 * static_cast<size_t>(cin[L]) * cout[L];
         const size_t np = 9 * static_cast<size_t>(N->cip(L)) * N->cop(L);
+        np_max = std::max(np_max, np);
         if (!N->alloc(&N->w[L], nw * 4) || !N->alloc(&N->m[L], nw * 4) || !N->alloc(&N->v[L], nw * 4) ||
             !N->alloc(&N->g[L], np * 4) || !N->alloc(&N->wf[L], np * 2) || !N->alloc(&N->wb[L], np * 2))
             return RAS_ENOMEM;
@@ -249,7 +250,8 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     ok = ok && N->alloc(&N->dz, static_cast<size_t>(batch_max) * dz_max * 2);
     const size_t npix = static_cast<size_t>(batch_max) * grid * grid;
     ok = ok && N->alloc(&N->y, npix * 2 * 4) && N->alloc(&N->stage, npix * 2 * 4) &&
-         N->alloc(&N->part, part_max * 4) && N->alloc(&N->lpart, kMseBlocks * 8) &&
+         N->alloc(&N->part, part_max * 4) && N->alloc(&N->psum, 32 * np_max * 4) &&
+         N->alloc(&N->lpart, kMseBlocks * 8) &&
          N->alloc(&N->loss, 8);
     if (!ok) return RAS_ENOMEM;
     *out = N.release();
