@@ -62,6 +62,8 @@ def log_width(k, h):
 
 # factorisation kernel variants as ras_pml_tuning numbers them
 LU_VARIANTS = ("mfma", "mfma_register_capped", "valu_one_column")
+# fused Arnoldi variants as RAS_KNOB_ARNOLDI numbers them
+ARNOLDI_VARIANTS = {0: "e8", 1: "e16", 2: "lean_e12", -1: "first_that_fits", -2: "unfused"}
 
 
 def progress(msg):
@@ -295,6 +297,7 @@ def main():
         "graph_steps": graph_blk,
         "tuning": {name: {"band_solve_deep_prefetch": t["solve_deep"],
                           "band_solve_queue": t["solve_queue"],
+                          "arnoldi_variant": ARNOLDI_VARIANTS.get(t["arnoldi"], t["arnoldi"]),
                           "factor_classes": [{"tiles": g[0], "subdomains": g[1],
                                               "variant": LU_VARIANTS[g[2]]} for g in t["ldlt"]],
                           "times_ms": t["times_ms"]}

@@ -391,7 +391,10 @@ int ras_pml_fill_idle_cache(int byte);
  *     the chosen variants, as a setup with these choices forms it;
  *   - the band solve's prefetch depth (RAS_KNOB_SOLVE_DEEP) and, with more
  *     subdomains than SIMDs, its dispatch (RAS_KNOB_SOLVE_QUEUE); these
- *     compute the same values bit for bit.
+ *     compute the same values bit for bit;
+ *   - the fused Arnoldi step's variant (RAS_KNOB_ARNOLDI), timed on the
+ *     handle's Krylov workspace (allocated for 22 vectors if smaller); the
+ *     variants differ only in the rounding of their reductions.
  * cache_path (nullable): the choices are merged into this flat JSON file,
  * keyed "arch/precision/kernel/class/count" (counts rounded up to a power
  * of two), for ras_pml_opts.tune_cache.  Allocates one temporary vector;
@@ -410,8 +413,9 @@ int ras_pml_tuning(ras_pml_t H, int *solve_deep, int *groups, int cap_groups, in
  * of its runs): for each factorisation window class in the order of
  * ras_pml_tuning, the whole factorisation with that class at variant 0, 1
  * and 2; then the band solve at (dispatch, prefetch) = (hardware, half),
- * (hardware, deep), (queue, half), (queue, deep), 1e30 where not measured.
- * *n = 3 * classes + 4 (0 before any autotune); the first cap values go to
+ * (hardware, deep), (queue, half), (queue, deep); then one fused Arnoldi
+ * step (step index 20) in variants 0, 1, 2; 1e30 where not measured.
+ * *n = 3 * classes + 7 (0 before any autotune); the first cap values go to
  * ms.  Errors: RAS_EINVAL.                                                */
 int ras_pml_tune_report(ras_pml_t H, double *ms, int cap, int *n);
 
@@ -426,10 +430,19 @@ int ras_pml_tune_report(ras_pml_t H, double *ms, int cap, int *n);
  *                         largest first, from an atomic work counter (used
  *                         only when there are more subdomains than SIMDs)
  *                         (default 0).
+ *   RAS_KNOB_ARNOLDI      fused Arnoldi step variant (gmres_solve): 0 = 8
+ *                         unknowns per thread, 1 = 16, both keeping v_i in
+ *                         registers across the grid barrier, 2 = 12 with v_i
+ *                         read again (fewer registers, more blocks per CU);
+ *                         -1 = the first whose grid stays co-resident
+ *                         (default); a variant whose grid would not stay
+ *                         co-resident is passed over.  Reading it gives the
+ *                         variant in use (-2: the one-launch-per-projection
+ *                         path), or the preference before the first solve.
  * ras_pml_set_knob takes effect for the handle's later launches;
- * ras_pml_autotune sets both from measurements.  Errors: RAS_EINVAL (no
- * handle, unknown knob or value).                                          */
-enum { RAS_KNOB_SOLVE_DEEP = 0, RAS_KNOB_SOLVE_QUEUE = 1 };
+ * ras_pml_autotune sets all three from measurements.  Errors: RAS_EINVAL
+ * (no handle, unknown knob or value).                                      */
+enum { RAS_KNOB_SOLVE_DEEP = 0, RAS_KNOB_SOLVE_QUEUE = 1, RAS_KNOB_ARNOLDI = 2 };
 int ras_pml_set_knob(ras_pml_t H, int knob, int value);
 int ras_pml_get_knob(ras_pml_t H, int knob, int *value);
 

@@ -24,6 +24,7 @@ RAS_FLAG_UNFUSED_ARNOLDI = 2
 RAS_FLAG_GRAPH_STEPS = 4
 RAS_KNOB_SOLVE_DEEP = 0
 RAS_KNOB_SOLVE_QUEUE = 1
+RAS_KNOB_ARNOLDI = 2
 RAS_DESC_INTS = 24
 RAS_WIDTH_RULE = -1
 
@@ -519,7 +520,8 @@ def ras_pml_tuning(H: Handle) -> dict:
         H._raise(rc)
     groups = [(buf[3 * i], buf[3 * i + 1], int(buf[3 * i + 2])) for i in range(min(cap, ng.value))]
     return {"solve_deep": bool(deep.value),
-            "solve_queue": bool(ras_pml_get_knob(H, RAS_KNOB_SOLVE_QUEUE)), "ldlt": groups}
+            "solve_queue": bool(ras_pml_get_knob(H, RAS_KNOB_SOLVE_QUEUE)),
+            "arnoldi": ras_pml_get_knob(H, RAS_KNOB_ARNOLDI), "ldlt": groups}
 
 
 def ras_pml_tune_report(H: Handle) -> dict:
@@ -537,8 +539,10 @@ def ras_pml_tune_report(H: Handle) -> dict:
     groups = ras_pml_tuning(H)["ldlt"]
     ldlt = [(g[0], vals[3 * i:3 * i + 3]) for i, g in enumerate(groups)]
     sv = vals[3 * len(groups):3 * len(groups) + 4]
+    av = vals[3 * len(groups) + 4:3 * len(groups) + 7]
     return {"ldlt": ldlt, "solve": dict(zip(("hardware_half", "hardware_deep", "queue_half",
-                                             "queue_deep"), sv))}
+                                             "queue_deep"), sv)),
+            "arnoldi": dict(zip(("e8", "e16", "lean_e12"), av))}
 
 
 def ras_pml_strerror(status: int) -> str:

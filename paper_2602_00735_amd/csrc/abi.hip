@@ -131,6 +131,7 @@ struct ras_pml_handle {
     // fused Arnoldi step (cooperative launch); E = 0 selects the
     // one-launch-per-projection path
     int arn_E = -1, arn_nblocks = 0, arn_var = 0;   // fused Arnoldi: unknowns per thread, variant
+    int arn_pref = -1;         // preferred fused-Arnoldi variant (-1: the first that fits)
     ArnoldiBlock *d_ablocks = nullptr;
     double2 *d_part2 = nullptr;
     unsigned long long *d_bar = nullptr;
@@ -561,9 +562,37 @@ int build(ras_pml_handle *H, hipStream_t st) {
     return RAS_OK;
 }
 
+void destroy_step_graph(ras_pml_handle *H);
+
+// Whether fused-Arnoldi variant `var` keeps every block of this handle's
+// grid co-resident; *blocks: the grid.
+bool arnoldi_fits(const ras_pml_handle *H, int var, int cus, int *blocks) {
+    int per_cu = 0;
+    if (arnoldi_block_capacity(var, &per_cu) != 0 || per_cu < 1) return false;
+    const long long slice = 256LL * arnoldi_variant_e(var);
+    long long need = 0;
+    for (const DevProb &P : H->hprobs) need += (P.ndof + slice - 1) / slice;
+    *blocks = static_cast<int>(need);
+    return need <= static_cast<long long>(per_cu) * cus;
+}
+
 // Choose the register slice per thread (E unknowns) so that every block of
-// the fused Arnoldi step is co-resident, and build the block table.
+// the fused Arnoldi step is co-resident, and build the block table: the
+// variant H->arn_pref when it fits (RAS_KNOB_ARNOLDI, the tuning cache),
+// else the first that fits.  Releases an earlier plan's buffers (the device
+// is idle first) and the step graph, which records the launch.
 int plan_arnoldi(ras_pml_handle *H) {
+    if (H->d_ablocks) {
+        idle_device(H->device);
+        void *old[] = {H->d_ablocks, H->d_part2, H->d_bar, H->d_epoch, H->d_err};
+        for (void *q : old) dfree(q);
+        H->d_ablocks = nullptr;
+        H->d_part2 = nullptr;
+        H->d_bar = nullptr;
+        H->d_epoch = nullptr;
+        H->d_err = nullptr;
+    }
+    destroy_step_graph(H);
     H->arn_E = 0;
     if (H->flags & RAS_FLAG_UNFUSED_ARNOLDI) return RAS_OK;
     int dev = 0, cus = 0;
@@ -572,15 +601,12 @@ int plan_arnoldi(ras_pml_handle *H) {
     int coop = 0;
     HCHK(H, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return RAS_OK;
-    for (int var = 0; var < arnoldi_variants(); ++var) {
+    for (int k = -1; k < arnoldi_variants(); ++k) {
+        const int var = k < 0 ? H->arn_pref : k;
+        int need = 0;
+        if (var < 0 || !arnoldi_fits(H, var, cus, &need)) continue;
         const int E = arnoldi_variant_e(var);
-        int per_cu = 0;
-        if (arnoldi_block_capacity(var, &per_cu) != 0 || per_cu < 1) continue;
-        const long long cap = static_cast<long long>(per_cu) * cus;
         const long long slice = 256LL * E;
-        long long need = 0;
-        for (const DevProb &P : H->hprobs) need += (P.ndof + slice - 1) / slice;
-        if (need > cap) continue;
         std::vector<ArnoldiBlock> tab;
         for (int p = 0; p < H->nprob; ++p) {
             const DevProb &P = H->hprobs[p];
@@ -1273,6 +1299,11 @@ std::string lu_key(const ras_pml_handle *H, const std::array<int, 5> &g) {
            "/count=" + std::to_string(pow2_bucket(g[2]));
 }
 
+std::string arnoldi_key(const ras_pml_handle *H) {
+    return H->arch + "/c128/arnoldi/nprob=" + std::to_string(H->nprob) + "/ndof=" +
+           std::to_string(pow2_bucket(static_cast<int>(std::min<long long>(H->ntot, 1LL << 30))));
+}
+
 std::string queue_key(const ras_pml_handle *H) {
     return H->arch + (H->fp64 ? "/c128" : "/c64") + "/solve_queue/maxW=" +
            std::to_string(H->maxW) + "/nsub=" + std::to_string(pow2_bucket(H->nsub));
@@ -1351,6 +1382,8 @@ void apply_cache(ras_pml_handle *H, const char *path) {
     }
     H->solve_deep = cache_lookup(c, solve_key(H), H->solve_deep) != 0;
     H->solve_queue = cache_lookup(c, queue_key(H), H->solve_queue) != 0;
+    const int av = cache_lookup(c, arnoldi_key(H), H->arn_pref);
+    if (av >= -1 && av < arnoldi_variants()) H->arn_pref = av;
 }
 
 }  // namespace
@@ -1820,6 +1853,47 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         }
         for (int q = 0; q < 2; ++q)
             for (int deep = 0; deep < 2; ++deep) H->tune_ms.push_back(t[q][deep]);
+    }
+    // fused Arnoldi variants: each whose grid stays co-resident, timed as
+    // one step at step index 20 on zero vectors of the handle's own Krylov
+    // workspace (best of three; the work does not depend on the values);
+    // the device state it leaves is reset by the next solve's cycle start
+    double arn_t[3] = {1e30, 1e30, 1e30};
+    if (rc == RAS_OK && !(H->flags & RAS_FLAG_UNFUSED_ARNOLDI)) {
+        constexpr int jt = 20;
+        rc = ensure_krylov(H, std::max(H->m_alloc, jt + 2));
+        int cus = 0;
+        if (rc == RAS_OK && H->arn_E > 0 &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, H->device) ==
+                hipSuccess) {
+            std::vector<KState> ks(H->nprob);
+            for (KState &K : ks) K = KState{1.0, 1.0, 1.0, 0.0, jt, 1, 0, jt + 2};
+            const long long n = H->ntot;
+            HCHK(H, hipMemcpyAsync(H->d_ks, ks.data(), sizeof(KState) * ks.size(),
+                                   hipMemcpyHostToDevice, st));
+            HCHK(H, hipMemsetAsync(H->d_V, 0, sizeof(double2) * n * (jt + 2), st));
+            HCHK(H, hipMemsetAsync(H->d_Z, 0, sizeof(double2) * n * (jt + 1), st));
+            const int m = H->m_alloc;
+            for (int v = 0; v < arnoldi_variants() && rc == RAS_OK; ++v) {
+                int blocks = 0;
+                if (!arnoldi_fits(H, v, cus, &blocks)) continue;
+                H->arn_pref = v;
+                rc = plan_arnoldi(H);
+                if (rc != RAS_OK || H->arn_var != v) continue;
+                arn_t[v] = timeit([&] {
+                    (void)launch_arnoldi(H->arn_var, H->arn_nblocks, H->d_probs, H->d_ks,
+                                         H->d_ablocks, H->d_coef, n, H->d_Z, H->d_V, m, H->d_H,
+                                         H->d_part2, H->d_bar, H->d_epoch, H->d_err, H->nprob, st);
+                }, 3);
+            }
+            if (rc == RAS_OK) {
+                H->arn_pref = static_cast<int>(std::min_element(arn_t, arn_t + 3) - arn_t);
+                rc = plan_arnoldi(H);
+            }
+        }
+    }
+    {
+        for (double a : arn_t) H->tune_ms.push_back(a);
         (void)hipStreamSynchronize(st);
         (void)hipFree(v);
     }
@@ -1836,6 +1910,7 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         for (const auto &g : H->lu_groups) cache_set(c, lu_key(H, g), g[3]);
         cache_set(c, solve_key(H), H->solve_deep ? 1 : 0);
         cache_set(c, queue_key(H), H->solve_queue ? 1 : 0);
+        if (H->arn_E > 0) cache_set(c, arnoldi_key(H), H->arn_pref);
         if (!write_cache(cache_path, c)) {
             H->last_error = std::string("autotune: cannot write ") + cache_path;
             return RAS_EINVAL;
@@ -1895,7 +1970,17 @@ int ras_pml_reset_stats(ras_pml_t H) {
 }
 
 int ras_pml_set_knob(ras_pml_t H, int knob, int value) {
-    if (!H || (value != 0 && value != 1)) return RAS_EINVAL;
+    if (!H) return RAS_EINVAL;
+    if (knob == RAS_KNOB_ARNOLDI) {
+        if (value < -1 || value >= arnoldi_variants()) {
+            H->last_error = "fused Arnoldi variant out of range";
+            return RAS_EINVAL;
+        }
+        H->arn_pref = value;
+        // planned already (Krylov workspace allocated): plan again now
+        return H->arn_E >= 0 ? plan_arnoldi(H) : RAS_OK;
+    }
+    if (value != 0 && value != 1) return RAS_EINVAL;
     switch (knob) {
         case RAS_KNOB_SOLVE_DEEP: H->solve_deep = value != 0; return RAS_OK;
         case RAS_KNOB_SOLVE_QUEUE: H->solve_queue = value != 0; return RAS_OK;
@@ -1908,6 +1993,9 @@ int ras_pml_get_knob(ras_pml_t H, int knob, int *value) {
     switch (knob) {
         case RAS_KNOB_SOLVE_DEEP: *value = H->solve_deep ? 1 : 0; return RAS_OK;
         case RAS_KNOB_SOLVE_QUEUE: *value = H->solve_queue ? 1 : 0; return RAS_OK;
+        case RAS_KNOB_ARNOLDI:    // the variant in use once planned, else the preference
+            *value = H->arn_E > 0 ? H->arn_var : H->arn_E == 0 ? -2 : H->arn_pref;
+            return RAS_OK;
         default: H->last_error = "unknown knob"; return RAS_EINVAL;
     }
 }

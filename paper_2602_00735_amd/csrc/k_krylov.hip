@@ -403,14 +403,30 @@ __device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned l
     __syncthreads();
 }
 
-// Sum the problem's per-block partials in index order (every block of the
-// problem obtains the same value).
+// Block sum for the fused step: each wave reduces its lanes with DPP moves
+// (no LDS round trip), the four wave sums meet in LDS and every thread adds
+// them in wave order (fixed order: deterministic).  sh4 alternates between
+// two buffers of four values from call to call (`par`), so one barrier per
+// call suffices: a buffer is written again only two calls later, after
+// every thread has passed the barrier of the call in between.
+__device__ __forceinline__ cplx<double> block_sum_dpp(cplx<double> v, cplx<double> (*sh4)[4],
+                                                      int &par) {
+    const cplx<double> w = wave_sum(v);
+    cplx<double> *b = sh4[par];
+    par ^= 1;
+    if ((threadIdx.x & 63) == 0) b[threadIdx.x >> 6] = w;
+    __syncthreads();
+    return cadd(cadd(b[0], b[1]), cadd(b[2], b[3]));
+}
+
+// Sum the problem's per-block partials in index order within each thread,
+// then over the block (every block of the problem obtains the same value).
 __device__ cplx<double> problem_sum(const double2 *__restrict__ part, const ArnoldiBlock &B,
-                                    cplx<double> *sh) {
+                                    cplx<double> (*sh4)[4], int &par) {
     cplx<double> acc{0, 0};
     for (int e = threadIdx.x; e < B.nblk; e += kRedThreads)
         acc = cadd(acc, get_agent(part + B.first_blk + e));
-    return block_sum(acc, sh);
+    return block_sum_dpp(acc, sh4, par);
 }
 
 // One Arnoldi step for every problem in one launch:
@@ -434,7 +450,9 @@ __device__ __forceinline__ void arnoldi_step(
     const double2 *__restrict__ Z, double2 *__restrict__ V, int m, double2 *__restrict__ H,
     double2 *__restrict__ part2, unsigned long long *bar, unsigned long long *epoch, int *err,
     int nprob) {
-    __shared__ cplx<double> sh[kRedThreads];
+    static_assert(kRedThreads == 256, "four waves per block");
+    __shared__ cplx<double> sh4[2][4];
+    int par = 0;
     // No problem left in the cycle (the host enqueues steps ahead of the
     // convergence test): every block sees the same flags, so the whole grid
     // skips the step, barriers and epoch included.
@@ -497,11 +515,11 @@ __device__ __forceinline__ void arnoldi_step(
             acc = cdotacc(acc, vq, w[q]);
         }
         double2 *part = part2 + static_cast<long long>(i & 1) * nblocks;
-        const cplx<double> bs = block_sum(acc, sh);
+        const cplx<double> bs = block_sum_dpp(acc, sh4, par);
         if (threadIdx.x == 0) put_agent(part + blockIdx.x, bs);
         ++ep;
         grid_barrier(bar, epoch0 + ep, err, failed);
-        const cplx<double> h = problem_sum(part, B, sh);
+        const cplx<double> h = problem_sum(part, B, sh4, par);
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int o = threadIdx.x + q * kRedThreads;
@@ -517,13 +535,13 @@ __device__ __forceinline__ void arnoldi_step(
 #pragma unroll
     for (int q = 0; q < E; ++q) nrm = fma(w[q].re, w[q].re, fma(w[q].im, w[q].im, nrm));
     double2 *part = part2 + static_cast<long long>((j + 1) & 1) * nblocks;
-    const cplx<double> bs = block_sum(cplx<double>{nrm, 0.0}, sh);
+    const cplx<double> bs = block_sum_dpp(cplx<double>{nrm, 0.0}, sh4, par);
     if (threadIdx.x == 0) put_agent(part + blockIdx.x, cplx<double>{bs.re, 0.0});
     ++ep;
     grid_barrier(bar, epoch0 + ep, err, failed);
     if (blockIdx.x == 0 && threadIdx.x == 0)
         __hip_atomic_store(epoch, epoch0 + ep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double hn = sqrt(problem_sum(part, B, sh).re);
+    const double hn = sqrt(problem_sum(part, B, sh4, par).re);
     if (!on) return;
     const double s = hn > 0.0 ? 1.0 / hn : 0.0;
     double2 *vn = V + static_cast<long long>(j + 1) * ntot;

@@ -241,8 +241,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ 
 // four pixels then lie in one image row, so for each kernel row the six
 // input values x-1 .. x+4 serve the three horizontal taps (6 loads instead
 // of 12), and each wave takes all nine taps for its own pixels (no output
-// gradient is loaded twice).  Every wave writes its own partial sums:
-//   part[4 blk + wave][tap][ci][co].
+// gradient is loaded twice).  The four waves' sums are added in LDS in wave
+// order and the block writes one partial: part[blk][tap][ci][co].
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restrict__ X,
                                                            const bf16 *__restrict__ dZ,
@@ -304,14 +304,177 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restric
             }
         }
     }
-    float *pw = part + (static_cast<long long>(blockIdx.x) * 4 + wave) * 9 * CPin * CPout;
+    // waves 1..3 leave their sums in LDS, wave 0 adds them in wave order
+    constexpr int NV = 9 * NT * 4;                     // values per lane
+    __shared__ float red[3][NV][64];
+    if (wave > 0) {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[wave - 1][(tap * NT + t) * 4 + r][lane] = c[tap][t][r];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = c[tap][t][r];
+            for (int r = 0; r < 4; ++r) {
+                const int q = (tap * NT + t) * 4 + r;
+                const float v = ((c[tap][t][r] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
+                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = v;
+            }
+}
+
+// Weight gradient with the rows staged in LDS (any channel counts that are
+// multiples of 16, widths that are multiples of 4):
+//   part[blk][tap][ci][co] = sum over the block's rows of
+//                            sum_x X[y + dy][x + dx][ci] dZ[y][x][co].
+// A block takes consecutive image rows.  Per row, the three input rows
+// y - 1 .. y + 1 sit in LDS transposed to [ci][x + 1] (a sliding window:
+// moving to the next row of the same image loads one new input row; rows
+// outside the image and the columns x = -1, x >= W are zero), and the
+// output-gradient row in [co][x].  Both are loaded with 16-byte reads (four
+// pixels by eight channels per item) and written transposed.  Each wave owns
+// the (tap, channel block) row tiles wave, wave + 4, ...; for every group of
+// 16 pixels a tile takes its A operand (channel ci = 16 kc + lane & 15,
+// pixels x0 + 4 (lane >> 4) + dx .. + 3) from one 8-byte and one 4-byte LDS
+// read (the six values x - 1 .. x + 4 cover the three horizontal taps) and
+// its B operand (output gradient) from one 8-byte read.
+template <int NT, int KC>
+__global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
+                                                    const bf16 *__restrict__ dZ,
+                                                    float *__restrict__ part, int B, int H, int W,
+                                                    int rows_per_blk) {
+    constexpr int CPin = 16 * KC, CPout = 16 * NT;
+    constexpr int ntile = 9 * KC, MAXT = (ntile + 3) / 4;
+    extern __shared__ __align__(16) unsigned char wg_lds[];
+    const int W16 = (W + 15) & ~15;
+    const int XP = W16 + 4;                    // input row: x at index x + 1
+    bf16 *Xs = reinterpret_cast<bf16 *>(wg_lds);          // [3][CPin][XP]
+    bf16 *Zs = Xs + 3 * CPin * XP;                         // [CPout][W16]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int R = B * H;
+    const int r0 = blockIdx.x * rows_per_blk, r1 = min(r0 + rows_per_blk, R);
+    {   // zeros everywhere: the halo columns and the padding stay zero
+        unsigned *z = reinterpret_cast<unsigned *>(wg_lds);
+        const int nw = (3 * CPin * XP + CPout * W16) / 2;
+        for (int k = tid; k < nw; k += 256) z[k] = 0u;
+    }
+    v4f c[MAXT][NT];
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    // one input row (image b, row yy; zeros outside the image) into slot sl
+    auto stage_x = [&](int b, int yy, int sl) {
+        bf16 *dst = Xs + sl * CPin * XP;
+        const bool in = yy >= 0 && yy < H;
+        const int nq = W >> 2, items = nq * (CPin >> 3);
+        for (int it = tid; it < items; it += 256) {
+            const int q = it % nq, c8 = (it / nq) * 8;
+            uint4 v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[e] = in ? *reinterpret_cast<const uint4 *>(
+                                X + (static_cast<long long>(b * H + yy) * W + 4 * q + e) * CPin + c8)
+                          : uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned u[4] = {v[e].x, v[e].y, v[e].z, v[e].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    dst[(c8 + 2 * k) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] & 0xFFFFu);
+                    dst[(c8 + 2 * k + 1) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] >> 16);
+                }
+            }
+        }
+    };
+    // the output-gradient row (image b, row y) into Zs, four pixels per write
+    auto stage_z = [&](int b, int y) {
+        const int nq = W >> 2, items = nq * (CPout >> 3);
+        for (int it = tid; it < items; it += 256) {
+            const int q = it % nq, c8 = (it / nq) * 8;
+            uint4 v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                v[e] = *reinterpret_cast<const uint4 *>(
+                    dZ + (static_cast<long long>(b * H + y) * W + 4 * q + e) * CPout + c8);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                unsigned h[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const unsigned w = (k >> 1) == 0 ? v[e].x : (k >> 1) == 1 ? v[e].y
+                                     : (k >> 1) == 2 ? v[e].z : v[e].w;
+                    h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+                }
+                *reinterpret_cast<uint2 *>(Zs + (c8 + k) * W16 + 4 * q) =
+                    uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+            }
+        }
+    };
+    int pb = -1, py = -2;                      // image and row of the previous step
+    for (int r = r0; r < r1; ++r) {
+        const int b = r / H, y = r % H;
+        __syncthreads();                       // the previous row's reads are done
+        if (b == pb && y == py + 1) {
+            stage_x(b, y + 1, (y + 1 + 3) % 3);
+        } else {
+            for (int d = -1; d <= 1; ++d) stage_x(b, y + d, (y + d + 3) % 3);
+        }
+        stage_z(b, y);
+        pb = b;
+        py = y;
+        __syncthreads();
+        for (int x0 = 0; x0 < W16; x0 += 16) {
+            v4s bz[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * W16 + x0 + 4 * kq);
+#pragma unroll
+            for (int s2 = 0; s2 < MAXT; ++s2) {
+                const int T = wave + 4 * s2;
+                if (T >= ntile) continue;
+                const int tap = T / KC, kc = T % KC;
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const bf16 *row = Xs + ((y + dy + 3) % 3) * CPin * XP + (16 * kc + i) * XP + x0 + 4 * kq;
+                // six values x - 1 .. x + 4 (indices x .. x + 5 of the padded row)
+                const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(row);
+                const unsigned hi = *reinterpret_cast<const unsigned *>(row + 4);
+                const int sh = 16 * (dx + 1);
+                const unsigned long long w =
+                    sh == 0 ? lo : (lo >> sh) | (static_cast<unsigned long long>(hi) << (64 - sh));
+                v4s a;
+                a[0] = static_cast<short>(w & 0xFFFFu);
+                a[1] = static_cast<short>((w >> 16) & 0xFFFFu);
+                a[2] = static_cast<short>((w >> 32) & 0xFFFFu);
+                a[3] = static_cast<short>((w >> 48) & 0xFFFFu);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    c[s2][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[s2][t], 0, 0, 0);
+            }
+        }
+    }
+    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
+#pragma unroll
+    for (int s2 = 0; s2 < MAXT; ++s2) {
+        const int T = wave + 4 * s2;
+        if (T >= ntile) continue;
+        const int tap = T / KC, kc = T % KC;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ci = 16 * kc + 4 * kq + r, co = 16 * t + i;
+                pw[(tap * CPin + ci) * CPout + co] = c[s2][t][r];
+            }
+    }
 }
 
 // g[idx] = sum over blocks of part[blk][idx], in two stages with a fixed
@@ -501,12 +664,20 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y,
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_double(const double *__restrict__ partial, int n, double scale,
-                             double *__restrict__ out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// out = scale * sum of the n partials: one block, each thread a strided
+// subset in order, then a tree in LDS (fixed order: deterministic).
+__global__ __launch_bounds__(256) void k_sum_double(const double *__restrict__ partial, int n,
+                                                    double scale, double *__restrict__ out) {
+    __shared__ double red[256];
     double s = 0.0;
-    for (int k = 0; k < n; ++k) s += partial[k];
-    *out = s * scale;
+    for (int k = threadIdx.x; k < n; k += 256) s += partial[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // Adam on the fp32 master weights W[tap][ci][co] (real channel counts) with
@@ -629,6 +800,23 @@ void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipS
     hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(n, 256)), dim3(256), 0, s, tmp, n, g);
 }
 
+// Blocks of the row-staged weight gradient: about 512 (fewer, so the
+// partials stay small, for layers with many channel tiles), at most one per
+// image row.  Its LDS bytes for a row width W.
+int warm_wgrad_rows_blocks(int B, int H, int CPin, int CPout, int *rows_per_blk) {
+    const int R = B * H;
+    const int tiles = (CPin / 16) * (CPout / 16);
+    const int want = tiles >= 8 ? 128 : tiles >= 4 ? 256 : 512;
+    const int rpb = (R + want - 1) / want;
+    *rows_per_blk = rpb;
+    return (R + rpb - 1) / rpb;
+}
+size_t warm_wgrad_rows_lds(int W, int CPin, int CPout) {
+    const size_t W16 = (static_cast<size_t>(W) + 15) & ~static_cast<size_t>(15);
+    return 2 * (3 * CPin * (W16 + 4) + CPout * W16);
+}
+constexpr size_t kWgradRowsMaxLds = 96 * 1024;
+
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
                 int W, int CPin, int CPout, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
@@ -636,6 +824,39 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
     const int nblk = warm_wgrad_blocks(M, &chunk);
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
     const int n = 9 * CPin * CPout;
+    const size_t lds = warm_wgrad_rows_lds(W, CPin, CPout);
+    // 16 -> 16 channels (the full-resolution layers): the per-wave kernel
+    // below keeps more waves per CU (measured 103 us against 256 us for the
+    // row-staged kernel at 640 x 640 x 8); every other layer is faster row-staged
+    const bool k16_1 = CPin == 16 && CPout == 16 && W % 4 == 0;
+    if (!k16_1 && W % 4 == 0 && lds <= kWgradRowsMaxLds) {
+        int rpb = 0;
+        const int nb = warm_wgrad_rows_blocks(B, H, CPin, CPout, &rpb);
+#define RAS_WR(NT, KC)                                                                           \
+    do {                                                                                         \
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_wgrad_rows<NT, KC>),          \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,                    \
+                                  static_cast<int>(lds));                                        \
+        hipLaunchKernelGGL((k_wgrad_rows<NT, KC>), dim3(nb), dim3(256), lds, s, x, dz, part, B,   \
+                           H, W, rpb);                                                           \
+    } while (0)
+#define RAS_WR_KC(NT)                                                                            \
+    do {                                                                                         \
+        if (CPin == 16) RAS_WR(NT, 1);                                                           \
+        else if (CPin == 32) RAS_WR(NT, 2);                                                      \
+        else RAS_WR(NT, 4);                                                                      \
+    } while (0)
+        if (CPout == 16)
+            RAS_WR_KC(1);
+        else if (CPout == 32)
+            RAS_WR_KC(2);
+        else
+            RAS_WR_KC(4);
+#undef RAS_WR_KC
+#undef RAS_WR
+        sum_partials(part, nb, n, tmp, g, s);
+        return;
+    }
     if (CPin == 16 && CPout <= 32 && W % 4 == 0) {     // per-wave partials: 4 per block
         if (CPout == 16)
             hipLaunchKernelGGL(k_conv3x3_wgrad_k16<1>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
@@ -643,7 +864,7 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
         else
             hipLaunchKernelGGL(k_conv3x3_wgrad_k16<2>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
                                W, chunk);
-        sum_partials(part, 4 * nblk, n, tmp, g, s);
+        sum_partials(part, nblk, n, tmp, g, s);
         return;
     }
 #define RAS_WG(NT, KC)                                                                           \
@@ -699,7 +920,7 @@ void warm_mse(const float *y, const float *t, long long npix, double *partial, i
     const float scale = static_cast<float>(2.0 / (2.0 * npix));
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, y, t, npix, partial,
                        static_cast<bf16 *>(dY), scale);
-    hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(64), 0, s, partial, nblk, 1.0 / (2.0 * npix),
+    hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / (2.0 * npix),
                        loss);
 }
 void warm_adam(float *w, float *m, float *v, const float *g, int cin, int cout, int cip, int cop,

@@ -1178,3 +1178,33 @@ def test_persistent_band_solve_equals_hardware_dispatch():
         for zz in out[q]:
             assert np.array_equal(zz, out[0][0])
     H.close()
+
+
+@pytest.mark.parametrize("name", ["k40_two_slot", "ragged"])
+def test_fused_arnoldi_variants_agree(name):
+    """RAS_KNOB_ARNOLDI: the three fused Arnoldi variants (8 or 16 unknowns
+    per thread keeping v_i in registers, 12 reading it again) differ only in
+    the rounding of their reductions: same step counts, FP64 solutions within
+    1e-10; the knob reports the variant in use."""
+    pb = PROBLEMS[name]
+    R = oracle_for(name)
+    b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+    out = []
+    for var in (0, 1, 2):
+        H = setup_gpu(pb, rp.RAS_FP64)
+        rp.ras_pml_set_knob(H, rp.RAS_KNOB_ARNOLDI, var)
+        x = torch.zeros_like(b)
+        rc, it, rr, hist = rp.gmres_solve(H, b, x, rtol=1e-8, restart=30, maxit=300)
+        assert rc == rp.RAS_OK
+        assert rp.ras_pml_get_knob(H, rp.RAS_KNOB_ARNOLDI) == var
+        out.append((it, host(x)))
+        # switching after the first solve plans the step again
+        rp.ras_pml_set_knob(H, rp.RAS_KNOB_ARNOLDI, (var + 1) % 3)
+        assert rp.ras_pml_get_knob(H, rp.RAS_KNOB_ARNOLDI) == (var + 1) % 3
+        x2 = torch.zeros_like(b)
+        rc2, it2, _, _ = rp.gmres_solve(H, b, x2, rtol=1e-8, restart=30, maxit=300)
+        assert rc2 == rp.RAS_OK and abs(it2 - it) <= 1
+        H.close()
+    for it, x in out[1:]:
+        assert it == out[0][0]
+        assert relerr(x, out[0][1]) <= 1e-10
