@@ -142,6 +142,110 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
     }
 }
 
+// The same convolution for images whose width is a multiple of 64 and
+// height a multiple of 4, with the input staged in LDS: a block computes a
+// tile of 4 rows x 64 pixels (wave w: row w, four tiles of 16 pixels) and
+// first loads the 6 x 66 input pixels that tile reads (zeros outside the
+// image) with 16-byte loads, in the layout of the tensor (channels of a
+// pixel contiguous); every tap's B operand is then one 8-byte LDS read per
+// lane instead of a gather through the caches.  Output as k_conv3x3.
+template <int NT, int KC, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X,
+                                                      const bf16 *__restrict__ Wp,
+                                                      void *__restrict__ Y,
+                                                      const bf16 *__restrict__ gate, int B, int H,
+                                                      int W, int relu, int acc, int creal) {
+    constexpr int CPin = 16 * KC, CPout = 16 * NT;
+    constexpr int TW = 64, TH = 4, SW = TW + 2, SH = TH + 2;
+    __shared__ __align__(16) bf16 S[SH * SW * CPin];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int tx = W / TW, ty = H / TH;
+    int blk = blockIdx.x;
+    const int bx = blk % tx;
+    blk /= tx;
+    const int by = blk % ty;
+    const int b = blk / ty;
+    const int x0 = bx * TW, y0 = by * TH;
+    {   // stage the input tile: pixel (sy, sx) of the tile is input pixel
+        // (y0 + sy - 1, x0 + sx - 1)
+        constexpr int C8 = CPin / 8, items = SH * SW * C8;
+        for (int it = tid; it < items; it += 256) {
+            const int c = (it % C8) * 8, pix = it / C8;
+            const int sx = pix % SW, sy = pix / SW;
+            const int gx = x0 + sx - 1, gy = y0 + sy - 1;
+            uint4 v = uint4{0u, 0u, 0u, 0u};
+            if (gx >= 0 && gx < W && gy >= 0 && gy < H)
+                v = *reinterpret_cast<const uint4 *>(
+                    X + ((static_cast<long long>(b) * H + gy) * W + gx) * CPin + c);
+            *reinterpret_cast<uint4 *>(S + pix * CPin + c) = v;
+        }
+    }
+    __syncthreads();
+    v4f c[4][NT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const bf16 *wb = Wp + tap * KC * NT * 256 + i * 16 + 4 * kq;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            v4s wt[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int sp = (wave + dy + 1) * SW + 16 * u + i + dx + 1;
+                const v4s a = *reinterpret_cast<const v4s *>(S + sp * CPin + 16 * kc + 4 * kq);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    c[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[t], a, c[u][t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const long long po = (static_cast<long long>(b) * H + y0 + wave) * W + x0 + 16 * u + i;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = relu ? fmaxf(c[u][t][r], 0.f) : c[u][t][r];
+            const int ch = 16 * t + 4 * kq;
+            if (OUT_F32) {
+                float *yf = static_cast<float *>(Y) + po * creal;
+                if (t == 0 && kq == 0) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < creal) yf[r] = v[r];
+                }
+            } else {
+                bf16 *yb = static_cast<bf16 *>(Y) + po * CPout + ch;
+                if (acc) {
+                    const uint2 q = *reinterpret_cast<const uint2 *>(yb);
+                    v[0] += __uint_as_float(q.x << 16);
+                    v[1] += __uint_as_float(q.x & 0xFFFF0000u);
+                    v[2] += __uint_as_float(q.y << 16);
+                    v[3] += __uint_as_float(q.y & 0xFFFF0000u);
+                }
+                if (gate != nullptr) {
+                    const uint2 q = *reinterpret_cast<const uint2 *>(gate + po * CPout + ch);
+                    if ((q.x & 0xFFFFu) == 0) v[0] = 0.f;
+                    if ((q.x >> 16) == 0) v[1] = 0.f;
+                    if ((q.y & 0xFFFFu) == 0) v[2] = 0.f;
+                    if ((q.y >> 16) == 0) v[3] = 0.f;
+                }
+                *reinterpret_cast<uint2 *>(yb) =
+                    uint2{static_cast<unsigned>(f2bf(v[0])) | (static_cast<unsigned>(f2bf(v[1])) << 16),
+                          static_cast<unsigned>(f2bf(v[2])) | (static_cast<unsigned>(f2bf(v[3])) << 16)};
+            }
+        }
+    }
+}
+
 // Partial weight gradient of one pixel chunk:
 //   part[blk][tap][ci][co] = sum_{p in chunk} X[p + off(tap)][ci] dZ[p][co]
 // (dZ: the output gradient, already multiplied by the ReLU mask).
@@ -241,9 +345,12 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ 
 // four pixels then lie in one image row, so for each kernel row the six
 // input values x-1 .. x+4 serve the three horizontal taps (6 loads instead
 // of 12), and each wave takes all nine taps for its own pixels (no output
-// gradient is loaded twice).  The four waves' sums are added in LDS in wave
-// order and the block writes one partial: part[blk][tap][ci][co].
-template <int NT>
+// gradient is loaded twice).  A wave takes U groups of 16 pixels (64 pixels
+// apart, one group per wave of the block in between) per step and issues
+// the loads of all U before their multiplies, so that U groups' loads are in
+// flight at once.  The four waves' sums are added in LDS in wave order and
+// the block writes one partial: part[blk][tap][ci][co].
+template <int NT, int U>
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restrict__ X,
                                                            const bf16 *__restrict__ dZ,
                                                            float *__restrict__ part, int B, int H,
@@ -262,47 +369,54 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restric
     int p = c0 + 16 * wave + 4 * kq;           // first of the lane's four pixels
     const int q0 = min(p, M - 4);
     int x = q0 % W, y = (q0 / W) % H, b = q0 / (W * H);
-    for (; p - 4 * kq < c1; p += 64) {
-        const bool pv = p < c1;                // then p + 3 < c1 too
-        v4s bz[NT];
+    for (; p - 4 * kq < c1; p += 64 * U) {
+        short v[U][3][6];
+        v4s bz[U][NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int u = 0; u < U; ++u) {
+            const int pu = p + 64 * u;
+            const bool pv = pu < c1;           // then pu + 3 < c1 too
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-            {
-                const short z = static_cast<short>(dZ[static_cast<long long>(pv ? p + e : 0) * CPout + 16 * t + i]);
-                bz[t][e] = pv ? z : short(0);
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const short z = static_cast<short>(dZ[static_cast<long long>(pv ? pu + e : 0) * CPout + 16 * t + i]);
+                    bz[u][t][e] = pv ? z : short(0);
+                }
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const int yy = y + dy - 1;
+                const bool rok = pv && yy >= 0 && yy < H;
+                const int row = (b * H + (rok ? yy : 0)) * W;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int xx = x - 1 + k;
+                    const bool ok = rok && xx >= 0 && xx < W;
+                    const short w = static_cast<short>(X[static_cast<long long>(ok ? row + xx : 0) * CPin + i]);
+                    v[u][dy][k] = ok ? w : short(0);
+                }
             }
-#pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = y + dy;
-            const bool rok = pv && yy >= 0 && yy < H;
-            const int row = (b * H + (rok ? yy : 0)) * W;
-            short v[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const int xx = x - 1 + k;
-                const bool ok = rok && xx >= 0 && xx < W;
-                const short u = static_cast<short>(X[static_cast<long long>(ok ? row + xx : 0) * CPin + i]);
-                v[k] = ok ? u : short(0);
-            }
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const v4s a = v4s{v[dx], v[dx + 1], v[dx + 2], v[dx + 3]};
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    c[3 * (dy + 1) + dx][t] =
-                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[3 * (dy + 1) + dx][t], 0, 0, 0);
-            }
-        }
-        x += 64;                               // next step: 64 pixels on
-        while (x >= W) {
-            x -= W;
-            if (++y == H) {
-                y = 0;
-                ++b;
+            x += 64;                           // the next group: 64 pixels on
+            while (x >= W) {
+                x -= W;
+                if (++y == H) {
+                    y = 0;
+                    ++b;
+                }
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const v4s a = v4s{v[u][dy][dx], v[u][dy][dx + 1], v[u][dy][dx + 2], v[u][dy][dx + 3]};
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        c[3 * dy + dx][t] =
+                            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[u][t], c[3 * dy + dx][t], 0, 0, 0);
+                }
     }
     // waves 1..3 leave their sums in LDS, wave 0 adds them in wave order
     constexpr int NV = 9 * NT * 4;                     // values per lane
@@ -325,45 +439,227 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restric
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int q = (tap * NT + t) * 4 + r;
-                const float v = ((c[tap][t][r] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
-                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = v;
+                const float w = ((c[tap][t][r] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
+                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = w;
             }
+}
+
+// Weight gradient for 16 input channels and widths divisible by 64, one
+// wave per strip: part[blk][tap][ci][co] = sum over the block's pixels of
+// X[y + dy][x + dx][ci] dZ[y][x][co].  A wave takes a strip of 64 columns
+// and rows y0 .. y1 - 1 of one image; its own LDS holds the input rows
+// y - 1 .. y + 1 of the strip with its two halo columns as a ring of three
+// rows, transposed to [ci][x - x0 + 1] (rows and columns outside the image
+// are zero), and the output-gradient row of the strip as [co][x - x0].  Each
+// step writes the rows that the registers hold (input row y + 1, output
+// gradient row y), issues the 16-byte loads of the next step's rows into the
+// registers, and then runs the 36 NT multiplies of row y: for every group of
+// 16 pixels and kernel row, one 8-byte and one 4-byte LDS read give the six
+// values x - 1 .. x + 4 that serve the three horizontal taps.  No wave waits
+// for another until the four waves' sums are added in LDS, in wave order, so
+// that the block writes one partial.
+template <int NT>
+__global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ X,
+                                                       const bf16 *__restrict__ dZ,
+                                                       float *__restrict__ part, int B, int H, int W,
+                                                       int rows_per_wave, int nchunk) {
+    constexpr int CPin = 16, CPout = 16 * NT;
+    constexpr int XP = 68;                         // columns x0 - 1 .. x0 + 64 at 0 .. 65
+    constexpr int XS = 3 * CPin * XP, ZS = CPout * 64;
+    constexpr int RED = 3 * 36 * 64;               // floats of the wave-sum exchange
+    constexpr int LDS_EL = 4 * (XS + ZS) > 2 * RED ? 4 * (XS + ZS) : 2 * RED;
+    __shared__ __align__(16) bf16 lds[LDS_EL];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    bf16 *Xs = lds + wave * (XS + ZS);
+    bf16 *Zs = Xs + XS;
+    const int nstrip = W >> 6;
+    const int item = blockIdx.x * 4 + wave;
+    v4f c[9][NT];
+#pragma unroll
+    for (int s = 0; s < 9; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (item < B * nchunk * nstrip) {
+        const int x0 = (item % nstrip) << 6;
+        const int chunk = (item / nstrip) % nchunk, b = item / (nstrip * nchunk);
+        const int y0 = chunk * rows_per_wave, y1 = min(H, y0 + rows_per_wave);
+        const bf16 *img = X + static_cast<long long>(b) * H * W * CPin;
+        const bf16 *zimg = dZ + static_cast<long long>(b) * H * W * CPout;
+        // input row yy: item it < 132 is column x0 - 1 + (it >> 1), channels 8 (it & 1) ..
+        uint4 xr[3];
+        auto load_x = [&](int yy) {
+            const bool in = yy >= 0 && yy < H;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int it = lane + 64 * r;
+                const int gx = x0 - 1 + (it >> 1);
+                xr[r] = uint4{0u, 0u, 0u, 0u};
+                if (it < 132 && in && gx >= 0 && gx < W)
+                    xr[r] = *reinterpret_cast<const uint4 *>(img + (static_cast<long long>(yy) * W + gx) * CPin +
+                                                             8 * (it & 1));
+            }
+        };
+        auto store_x = [&](int yy) {
+            bf16 *dst = Xs + ((yy + 3) % 3) * CPin * XP;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int it = lane + 64 * r;
+                if (it < 132) {
+                    const int col = it >> 1, c8 = 8 * (it & 1);
+                    const unsigned u[4] = {xr[r].x, xr[r].y, xr[r].z, xr[r].w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        dst[(c8 + 2 * k) * XP + col] = static_cast<bf16>(u[k] & 0xFFFFu);
+                        dst[(c8 + 2 * k + 1) * XP + col] = static_cast<bf16>(u[k] >> 16);
+                    }
+                }
+            }
+        };
+        // output-gradient row y: item it < 16 NT x 2 is pixels x0 + 4 (it & 15) .. + 3,
+        // channels 8 (it >> 4) ..
+        uint4 zr[4];
+        auto load_z = [&](int y) {
+            const int it = lane;
+            if (it < 32 * NT) {
+                const bf16 *src = zimg + (static_cast<long long>(y) * W + x0 + 4 * (it & 15)) * CPout + 8 * (it >> 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) zr[e] = *reinterpret_cast<const uint4 *>(src + e * CPout);
+            }
+        };
+        auto store_z = [&]() {
+            const int it = lane;
+            if (it < 32 * NT) {
+                const int q = it & 15, c8 = 8 * (it >> 4);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    unsigned h[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const unsigned w = (k >> 1) == 0 ? zr[e].x : (k >> 1) == 1 ? zr[e].y
+                                         : (k >> 1) == 2 ? zr[e].z : zr[e].w;
+                        h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+                    }
+                    *reinterpret_cast<uint2 *>(Zs + (c8 + k) * 64 + 4 * q) =
+                        uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+                }
+            }
+        };
+        load_x(y0 - 1);
+        store_x(y0 - 1);
+        load_x(y0);
+        store_x(y0);
+        load_x(y0 + 1);
+        load_z(y0);
+        for (int y = y0; y < y1; ++y) {
+            // the previous step's reads of the slot and of Zs are done: a
+            // wave's LDS accesses complete in order
+            __builtin_amdgcn_wave_barrier();
+            store_x(y + 1);
+            store_z();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (y + 1 < y1) {
+                load_x(y + 2);
+                load_z(y + 1);
+            }
+#pragma unroll
+            for (int xg = 0; xg < 64; xg += 16) {
+                v4s bz[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * 64 + xg + 4 * kq);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const bf16 *rowl = Xs + ((y + dy + 2) % 3) * CPin * XP + i * XP + xg + 4 * kq;
+                    const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(rowl);
+                    const unsigned hi = *reinterpret_cast<const unsigned *>(rowl + 4);
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) {
+                        const unsigned long long w =
+                            dx == 0 ? lo : (lo >> (16 * dx)) | (static_cast<unsigned long long>(hi) << (64 - 16 * dx));
+                        v4s a;
+                        a[0] = static_cast<short>(w & 0xFFFFu);
+                        a[1] = static_cast<short>((w >> 16) & 0xFFFFu);
+                        a[2] = static_cast<short>((w >> 32) & 0xFFFFu);
+                        a[3] = static_cast<short>((w >> 48) & 0xFFFFu);
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            c[3 * dy + dx][t] =
+                                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[3 * dy + dx][t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // waves 1..3 leave their sums in LDS (one output tile column t at a
+    // time), wave 0 adds them in wave order and writes the block's partial
+    float *red = reinterpret_cast<float *>(lds);
+    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        __syncthreads();
+        if (wave > 0) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[((wave - 1) * 36 + tap * 4 + r) * 64 + lane] = c[tap][t][r];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = tap * 4 + r;
+                    const float w = ((c[tap][t][r] + red[q * 64 + lane]) + red[(36 + q) * 64 + lane]) +
+                                    red[(72 + q) * 64 + lane];
+                    pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = w;
+                }
+        }
+    }
 }
 
 // Weight gradient with the rows staged in LDS (any channel counts that are
 // multiples of 16, widths that are multiples of 4):
-//   part[blk][tap][ci][co] = sum over the block's rows of
-//                            sum_x X[y + dy][x + dx][ci] dZ[y][x][co].
-// A block takes consecutive image rows.  Per row, the three input rows
-// y - 1 .. y + 1 sit in LDS transposed to [ci][x + 1] (a sliding window:
-// moving to the next row of the same image loads one new input row; rows
-// outside the image and the columns x = -1, x >= W are zero), and the
-// output-gradient row in [co][x].  Both are loaded with 16-byte reads (four
-// pixels by eight channels per item) and written transposed.  Each wave owns
-// the (tap, channel block) row tiles wave, wave + 4, ...; for every group of
-// 16 pixels a tile takes its A operand (channel ci = 16 kc + lane & 15,
-// pixels x0 + 4 (lane >> 4) + dx .. + 3) from one 8-byte and one 4-byte LDS
-// read (the six values x - 1 .. x + 4 cover the three horizontal taps) and
-// its B operand (output gradient) from one 8-byte read.
+//   part[blk][tap][ci][co] = sum over the block's pixels of
+//                            X[y + dy][x + dx][ci] dZ[y][x][co].
+// A block takes a strip of SWD columns (SWD divides W and is a multiple of
+// 4; the launcher passes the whole row) and consecutive image rows down it.  Per row, the
+// three input rows y - 1 .. y + 1 of the strip and its two halo columns sit
+// in LDS transposed to [ci][x - x0 + 1] (a sliding window: moving to the next
+// row of the same image loads one new input row; rows outside the image and
+// columns outside it or past the strip's padding are zero), and the
+// output-gradient row of the strip in [co][x - x0].  Both are loaded with
+// 16-byte reads (four pixels by eight channels per item) and written
+// transposed.  Each wave owns the (tap, channel block) row tiles wave,
+// wave + 4, ...; for every group of 16 pixels a tile takes its A operand
+// (channel ci = 16 kc + lane & 15, pixels x + 4 (lane >> 4) + dx .. + 3) from
+// one 8-byte and one 4-byte LDS read (the six values x - 1 .. x + 4 cover
+// the three horizontal taps) and its B operand from one 8-byte read.
 template <int NT, int KC>
 __global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
                                                     const bf16 *__restrict__ dZ,
                                                     float *__restrict__ part, int B, int H, int W,
-                                                    int rows_per_blk) {
+                                                    int SWD, int rows_per_blk) {
     constexpr int CPin = 16 * KC, CPout = 16 * NT;
     constexpr int ntile = 9 * KC, MAXT = (ntile + 3) / 4;
     extern __shared__ __align__(16) unsigned char wg_lds[];
-    const int W16 = (W + 15) & ~15;
-    const int XP = W16 + 4;                    // input row: x at index x + 1
+    const int S16 = (SWD + 15) & ~15;           // strip padded to whole pixel groups
+    const int XP = S16 + 4;                     // input row: column x - x0 at index x - x0 + 1
     bf16 *Xs = reinterpret_cast<bf16 *>(wg_lds);          // [3][CPin][XP]
-    bf16 *Zs = Xs + 3 * CPin * XP;                         // [CPout][W16]
+    bf16 *Zs = Xs + 3 * CPin * XP;                         // [CPout][S16]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, kq = lane >> 4;
+    const int nstrip = W / SWD;
+    const int strip = blockIdx.x % nstrip;
+    const int x0 = strip * SWD;
     const int R = B * H;
-    const int r0 = blockIdx.x * rows_per_blk, r1 = min(r0 + rows_per_blk, R);
-    {   // zeros everywhere: the halo columns and the padding stay zero
+    const int r0 = (blockIdx.x / nstrip) * rows_per_blk, r1 = min(r0 + rows_per_blk, R);
+    {   // zeros everywhere: the padding stays zero
         unsigned *z = reinterpret_cast<unsigned *>(wg_lds);
-        const int nw = (3 * CPin * XP + CPout * W16) / 2;
+        const int nw = (3 * CPin * XP + CPout * S16) / 2;
         for (int k = tid; k < nw; k += 256) z[k] = 0u;
     }
     v4f c[MAXT][NT];
@@ -371,40 +667,56 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
     for (int s = 0; s < MAXT; ++s)
 #pragma unroll
         for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    // one input row (image b, row yy; zeros outside the image) into slot sl
+    // the strip's part of one input row (image b, row yy; zeros outside the
+    // image) and its halo columns x0 - 1, x0 + SWD into slot sl
     auto stage_x = [&](int b, int yy, int sl) {
         bf16 *dst = Xs + sl * CPin * XP;
         const bool in = yy >= 0 && yy < H;
-        const int nq = W >> 2, items = nq * (CPin >> 3);
-        for (int it = tid; it < items; it += 256) {
-            const int q = it % nq, c8 = (it / nq) * 8;
-            uint4 v[4];
+        const bf16 *rowp = X + static_cast<long long>(b * H + (in ? yy : 0)) * W * CPin;
+        const int nq = SWD >> 2, items = nq * (CPin >> 3);
+        for (int it = tid; it < items + 2 * (CPin >> 3); it += 256) {
+            if (it < items) {
+                const int q = it % nq, c8 = (it / nq) * 8;
+                uint4 v[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                v[e] = in ? *reinterpret_cast<const uint4 *>(
-                                X + (static_cast<long long>(b * H + yy) * W + 4 * q + e) * CPin + c8)
-                          : uint4{0u, 0u, 0u, 0u};
+                for (int e = 0; e < 4; ++e)
+                    v[e] = in ? *reinterpret_cast<const uint4 *>(rowp + (x0 + 4 * q + e) * CPin + c8)
+                              : uint4{0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned u[4] = {v[e].x, v[e].y, v[e].z, v[e].w};
+                for (int e = 0; e < 4; ++e) {
+                    const unsigned u[4] = {v[e].x, v[e].y, v[e].z, v[e].w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        dst[(c8 + 2 * k) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] & 0xFFFFu);
+                        dst[(c8 + 2 * k + 1) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] >> 16);
+                    }
+                }
+            } else {   // halo column: left (x0 - 1 at index 0) or right (x0 + SWD)
+                const int h = it - items;
+                const int side = h / (CPin >> 3), c8 = (h % (CPin >> 3)) * 8;
+                const int gx = side == 0 ? x0 - 1 : x0 + SWD;
+                const int idx = side == 0 ? 0 : SWD + 1;
+                uint4 v = uint4{0u, 0u, 0u, 0u};
+                if (in && gx >= 0 && gx < W) v = *reinterpret_cast<const uint4 *>(rowp + gx * CPin + c8);
+                const unsigned u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    dst[(c8 + 2 * k) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] & 0xFFFFu);
-                    dst[(c8 + 2 * k + 1) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] >> 16);
+                    dst[(c8 + 2 * k) * XP + idx] = static_cast<bf16>(u[k] & 0xFFFFu);
+                    dst[(c8 + 2 * k + 1) * XP + idx] = static_cast<bf16>(u[k] >> 16);
                 }
             }
         }
     };
-    // the output-gradient row (image b, row y) into Zs, four pixels per write
+    // the strip's output-gradient row (image b, row y), four pixels per write
     auto stage_z = [&](int b, int y) {
-        const int nq = W >> 2, items = nq * (CPout >> 3);
+        const bf16 *rowp = dZ + static_cast<long long>(b * H + y) * W * CPout;
+        const int nq = SWD >> 2, items = nq * (CPout >> 3);
         for (int it = tid; it < items; it += 256) {
             const int q = it % nq, c8 = (it / nq) * 8;
             uint4 v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                v[e] = *reinterpret_cast<const uint4 *>(
-                    dZ + (static_cast<long long>(b * H + y) * W + 4 * q + e) * CPout + c8);
+                v[e] = *reinterpret_cast<const uint4 *>(rowp + (x0 + 4 * q + e) * CPout + c8);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 unsigned h[4];
@@ -414,7 +726,7 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
                                      : (k >> 1) == 2 ? v[e].z : v[e].w;
                     h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
                 }
-                *reinterpret_cast<uint2 *>(Zs + (c8 + k) * W16 + 4 * q) =
+                *reinterpret_cast<uint2 *>(Zs + (c8 + k) * S16 + 4 * q) =
                     uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
             }
         }
@@ -432,21 +744,21 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
         pb = b;
         py = y;
         __syncthreads();
-        for (int x0 = 0; x0 < W16; x0 += 16) {
+        for (int xg = 0; xg < S16; xg += 16) {
             v4s bz[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * W16 + x0 + 4 * kq);
+                bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * S16 + xg + 4 * kq);
 #pragma unroll
             for (int s2 = 0; s2 < MAXT; ++s2) {
                 const int T = wave + 4 * s2;
                 if (T >= ntile) continue;
                 const int tap = T / KC, kc = T % KC;
                 const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                const bf16 *row = Xs + ((y + dy + 3) % 3) * CPin * XP + (16 * kc + i) * XP + x0 + 4 * kq;
-                // six values x - 1 .. x + 4 (indices x .. x + 5 of the padded row)
-                const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(row);
-                const unsigned hi = *reinterpret_cast<const unsigned *>(row + 4);
+                const bf16 *rowl = Xs + ((y + dy + 3) % 3) * CPin * XP + (16 * kc + i) * XP + xg + 4 * kq;
+                // six values x - 1 .. x + 4 (indices x - x0 .. x - x0 + 5 of the padded row)
+                const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(rowl);
+                const unsigned hi = *reinterpret_cast<const unsigned *>(rowl + 4);
                 const int sh = 16 * (dx + 1);
                 const unsigned long long w =
                     sh == 0 ? lo : (lo >> sh) | (static_cast<unsigned long long>(hi) << (64 - sh));
@@ -759,6 +1071,27 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
     const long long M = static_cast<long long>(B) * H * W;
+    if (W % 64 == 0 && H % 4 == 0 && CPin <= 32 && M >= 256LL * 1024) {
+        // the LDS-staged tile kernel (4 rows x 64 pixels per block)
+        const dim3 grid(static_cast<unsigned>(M / 256)), blk(256);
+        const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
+                   *g = static_cast<const bf16 *>(gate);
+#define RAS_TILE(NT, KC, F32)                                                                    \
+    hipLaunchKernelGGL((k_conv3x3_tile<NT, KC, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W,      \
+                       relu ? 1 : 0, acc ? 1 : 0, creal)
+#define RAS_TILE_KC(NT, F32)                  \
+    do {                                      \
+        if (CPin == 16) RAS_TILE(NT, 1, F32); \
+        else RAS_TILE(NT, 2, F32);            \
+    } while (0)
+        if (out_f32) RAS_TILE_KC(1, true);
+        else if (CPout == 16) RAS_TILE_KC(1, false);
+        else if (CPout == 32) RAS_TILE_KC(2, false);
+        else RAS_TILE_KC(4, false);
+#undef RAS_TILE_KC
+#undef RAS_TILE
+        return;
+    }
     const bool wide = M >= 256LL * 1024;
     const dim3 grid(blocks(M, wide ? 256 : 64)), blk(256);
     const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
@@ -800,20 +1133,48 @@ void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipS
     hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(n, 256)), dim3(256), 0, s, tmp, n, g);
 }
 
-// Blocks of the row-staged weight gradient: about 512 (fewer, so the
-// partials stay small, for layers with many channel tiles), at most one per
-// image row.  Its LDS bytes for a row width W.
-int warm_wgrad_rows_blocks(int B, int H, int CPin, int CPout, int *rows_per_blk) {
-    const int R = B * H;
+// Strips and row chunks of k_wgrad_strip16: about 4096 waves (one per SIMD
+// slot the kernel's LDS leaves), at least one row per wave.
+int warm_wgrad_strip16_blocks(int B, int H, int W, int *rows_per_wave, int *nchunk) {
+    const int nstrip = W / 64;
+    const int want = std::max(1, std::min(H, 4096 / std::max(1, B * nstrip)));
+    const int rpw = (H + want - 1) / want;
+    *rows_per_wave = rpw;
+    *nchunk = (H + rpw - 1) / rpw;
+    return (B * *nchunk * nstrip + 3) / 4;
+}
+// The most blocks it gives for any batch up to B.
+int warm_wgrad_strip16_blocks_max(int B, int W) {
+    return (std::max(4096, B * (W / 64)) + 3) / 4 + 1;
+}
+
+// Strip width of the row-staged weight gradient (the whole row: narrower
+// strips were measured slower, their barriers per multiply being more), its
+// blocks (strips x row chunks: 512 for up to two channel tiles, fewer for
+// more so that the partials stay small; at most one row chunk per image row)
+// and its LDS bytes.
+int warm_wgrad_strip(int W) { return W; }
+static int wgrad_rows_chunks(int W, int CPin, int CPout) {
+    const int nstrip = W / warm_wgrad_strip(W);
     const int tiles = (CPin / 16) * (CPout / 16);
     const int want = tiles >= 8 ? 128 : tiles >= 4 ? 256 : 512;
-    const int rpb = (R + want - 1) / want;
+    return std::max(1, want / nstrip);
+}
+int warm_wgrad_rows_blocks(int B, int H, int W, int CPin, int CPout, int *rows_per_blk) {
+    const int R = B * H, nstrip = W / warm_wgrad_strip(W);
+    const int chunks = wgrad_rows_chunks(W, CPin, CPout);
+    const int rpb = (R + chunks - 1) / chunks;
     *rows_per_blk = rpb;
-    return (R + rpb - 1) / rpb;
+    return nstrip * ((R + rpb - 1) / rpb);
+}
+// The most blocks warm_wgrad_rows_blocks gives for any batch up to B.
+int warm_wgrad_rows_blocks_max(int B, int H, int W, int CPin, int CPout) {
+    const int nstrip = W / warm_wgrad_strip(W);
+    return nstrip * std::min(B * H, wgrad_rows_chunks(W, CPin, CPout));
 }
 size_t warm_wgrad_rows_lds(int W, int CPin, int CPout) {
-    const size_t W16 = (static_cast<size_t>(W) + 15) & ~static_cast<size_t>(15);
-    return 2 * (3 * CPin * (W16 + 4) + CPout * W16);
+    const size_t S16 = (static_cast<size_t>(warm_wgrad_strip(W)) + 15) & ~static_cast<size_t>(15);
+    return 2 * (3 * CPin * (S16 + 4) + CPout * S16);
 }
 constexpr size_t kWgradRowsMaxLds = 96 * 1024;
 
@@ -825,20 +1186,31 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
     const int n = 9 * CPin * CPout;
     const size_t lds = warm_wgrad_rows_lds(W, CPin, CPout);
-    // 16 -> 16 channels (the full-resolution layers): the per-wave kernel
-    // below keeps more waves per CU (measured 103 us against 256 us for the
-    // row-staged kernel at 640 x 640 x 8); every other layer is faster row-staged
+    if (CPin == 16 && CPout <= 32 && W % 64 == 0) {   // one wave per strip
+        int rpw = 0, nch = 0;
+        const int nb = warm_wgrad_strip16_blocks(B, H, W, &rpw, &nch);
+        if (CPout == 16)
+            hipLaunchKernelGGL(k_wgrad_strip16<1>, dim3(nb), dim3(256), 0, s, x, dz, part, B, H, W, rpw, nch);
+        else
+            hipLaunchKernelGGL(k_wgrad_strip16<2>, dim3(nb), dim3(256), 0, s, x, dz, part, B, H, W, rpw, nch);
+        sum_partials(part, nb, n, tmp, g, s);
+        return;
+    }
+    // 16 -> 16 channels at other widths: the per-wave kernel below keeps more
+    // waves per CU than the row-staged one (measured 103 us against 256 us at
+    // 640 x 640 x 8); every other layer is faster row-staged
     const bool k16_1 = CPin == 16 && CPout == 16 && W % 4 == 0;
     if (!k16_1 && W % 4 == 0 && lds <= kWgradRowsMaxLds) {
         int rpb = 0;
-        const int nb = warm_wgrad_rows_blocks(B, H, CPin, CPout, &rpb);
+        const int nb = warm_wgrad_rows_blocks(B, H, W, CPin, CPout, &rpb);
+        const int swd = warm_wgrad_strip(W);
 #define RAS_WR(NT, KC)                                                                           \
     do {                                                                                         \
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_wgrad_rows<NT, KC>),          \
                                   hipFuncAttributeMaxDynamicSharedMemorySize,                    \
                                   static_cast<int>(lds));                                        \
         hipLaunchKernelGGL((k_wgrad_rows<NT, KC>), dim3(nb), dim3(256), lds, s, x, dz, part, B,   \
-                           H, W, rpb);                                                           \
+                           H, W, swd, rpb);                                                      \
     } while (0)
 #define RAS_WR_KC(NT)                                                                            \
     do {                                                                                         \
@@ -859,10 +1231,10 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
     }
     if (CPin == 16 && CPout <= 32 && W % 4 == 0) {     // per-wave partials: 4 per block
         if (CPout == 16)
-            hipLaunchKernelGGL(k_conv3x3_wgrad_k16<1>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
+            hipLaunchKernelGGL((k_conv3x3_wgrad_k16<1, 4>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
                                W, chunk);
         else
-            hipLaunchKernelGGL(k_conv3x3_wgrad_k16<2>, dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
+            hipLaunchKernelGGL((k_conv3x3_wgrad_k16<2, 4>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
                                W, chunk);
         sum_partials(part, nblk, n, tmp, g, s);
         return;

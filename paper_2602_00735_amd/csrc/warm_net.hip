@@ -33,7 +33,8 @@ namespace raspml {
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
 int warm_wgrad_blocks(long long M, int *chunk);
-int warm_wgrad_rows_blocks(int B, int H, int CPin, int CPout, int *rows_per_blk);
+int warm_wgrad_rows_blocks_max(int B, int H, int W, int CPin, int CPout);
+int warm_wgrad_strip16_blocks_max(int B, int W);
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
                 int W, int CPin, int CPout, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
@@ -229,11 +230,11 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
         const long long M = static_cast<long long>(batch_max) * S * S;
         const long long nblk = std::min(1024LL, (M + 255) / 256);
         part_max = std::max(part_max, static_cast<size_t>(nblk) * np);
-        // the row-staged kernel: at most 512 blocks and one per image row for
-        // any batch up to batch_max
-        int rpb = 0;
-        const int nbr = warm_wgrad_rows_blocks(1, std::max(1, batch_max) * S, N->cip(L), N->cop(L), &rpb);
-        part_max = std::max(part_max, static_cast<size_t>(std::max(nbr, std::min(512, batch_max * S))) * np);
+        // the row-staged kernel's blocks for any batch up to batch_max
+        const int nbr = warm_wgrad_rows_blocks_max(batch_max, S, S, N->cip(L), N->cop(L));
+        part_max = std::max(part_max, static_cast<size_t>(nbr) * np);
+        // the strip kernel (16 input channels)
+        part_max = std::max(part_max, static_cast<size_t>(warm_wgrad_strip16_blocks_max(batch_max, S)) * np);
     }
     auto act = [&](void **ptr, int l, int C) {
         const size_t S = static_cast<size_t>(grid >> l);

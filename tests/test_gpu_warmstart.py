@@ -87,6 +87,26 @@ def test_gradient_matches_oracle():
         assert relerr(gd[name], gref[name]) <= 6e-2, (name, relerr(gd[name], gref[name]))
 
 
+def test_full_resolution_kernels_match_oracle():
+    """A grid and batch large enough (256 x 256 x 4 pixels) for the
+    full-resolution layers to take the LDS-tiled convolution (4 rows x 64
+    pixels per block) and the weight gradients their per-wave and
+    row-staged kernels: forward, loss and every layer's weight gradient
+    against the float64 oracle."""
+    net, flat, x, t = setup(256, 4, 5)
+    y = net.forward(torch.from_numpy(x).cuda())
+    params = as_dict(flat, CH)
+    yref, tape = ows.forward(params, x.astype(np.float64))
+    assert relerr(y.cpu().numpy(), yref) <= 3e-2
+    loss, g = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    lref = ows.loss(yref, t.astype(np.float64))
+    gref = ows.backward(params, tape, t.astype(np.float64))
+    assert abs(loss - lref) <= 3e-2 * lref
+    gd = as_dict(g, CH)
+    for name in rp.WS_LAYERS:
+        assert relerr(gd[name], gref[name]) <= 6e-2, (name, relerr(gd[name], gref[name]))
+
+
 def test_adam_first_step_and_determinism():
     """Adam's first step moves every weight by -lr g / (|g| + eps) (its
     bias-corrected moments are g and g^2), with g the network's own
