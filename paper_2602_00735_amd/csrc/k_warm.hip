@@ -1,14 +1,13 @@
 // Learned warm start: the convolutional encoder-decoder's kernels.
 //
-// Tensors are NHWC bfloat16 with the channel count padded to a multiple of
-// 16 (padding channels hold zeros); accumulation is fp32.  Every 3 x 3
+// Tensors are NHWC bfloat16 with the channel count padded to 16, 32 or 64
+// (padding channels hold zeros); accumulation is fp32.  Every 3 x 3
 // convolution (zero padding, no bias) is an implicit GEMM on the matrix
 // cores, v_mfma_f32_16x16x16_bf16:
-//   forward / input gradient: rows = 16 output pixels per wave, columns =
-//     output channels (NT tiles of 16), K = 9 taps x input channels; the
-//     A operand is gathered straight from the input tensor (4 channels of
-//     one pixel per lane, one 8-byte load), the B operand from weights
-//     packed per (tap, channel block, column tile) as 16 x 16 blocks;
+//   forward / input gradient: rows = output channels (NT tiles of 16),
+//     columns = 16 output pixels, K = 9 taps x input channels; the weights
+//     are packed per (tap, channel block, column tile) as 16 x 16 blocks,
+//     the input is staged in LDS per tile of 4 x 64 pixels;
 //     the input gradient is the same kernel on the output gradient with
 //     the taps flipped and the channel roles swapped (every gradient is
 //     written already multiplied by the ReLU mask of its tensor, by the
@@ -36,131 +35,39 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
     return static_cast<bf16>(u >> 16);
 }
 // out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
-// NT: output channel tiles; PT: tiles of 16 output pixels per wave (the
-// weights of a tap are loaded once for all of them).  The matrix-core
-// product is D[co][p] = W^T X^T: A is the weight block (lane: output channel
-// lane & 15, input channels 4 (lane >> 4) .. + 3), B the gathered input
-// (lane: pixel lane & 15, the same four input channels, one 8-byte load),
-// so each lane ends with four consecutive output channels of one pixel and
-// writes them with one 8-byte store.  OUT_F32: write the first `creal`
-// (<= 4) channels as fp32 (the network's head).  gate (nullable, shaped as
-// the output): values are kept only where the gate is positive (the ReLU
-// mask of the tensor whose gradient this is; a post-ReLU value is positive
-// exactly when its bits are non-zero).
-template <int NT, int PT, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ X,
-                                                 const bf16 *__restrict__ Wp, void *__restrict__ Y,
-                                                 const bf16 *__restrict__ gate, int B, int H, int W,
-                                                 int CPin, int relu, int acc, int creal) {
-    constexpr int CPout = 16 * NT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int M = B * H * W;                // M * 64 < 2^31 (checked at creation)
-    const int pw0 = (blockIdx.x * 4 + wave) * 16 * PT;
-    if (pw0 >= M) return;                   // no barrier in this kernel
-    const int i = lane & 15, kq = lane >> 4;
-    // the lane's pixel in each tile, its border flags (each tap is then a
-    // uniform offset from it)
-    const bf16 *xc[PT];
-    unsigned char fl[PT];                   // bit0 x>0, bit1 x<W-1, bit2 y>0, bit3 y<H-1, bit4 in
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int p = pw0 + 16 * u + i;
-        const bool pin = p < M;
-        const int pc = pin ? p : M - 1;
-        const int x = pc % W, y = (pc / W) % H;
-        fl[u] = static_cast<unsigned char>((x > 0) | ((x < W - 1) << 1) | ((y > 0) << 2) |
-                                           ((y < H - 1) << 3) | (pin << 4));
-        xc[u] = X + pc * CPin + 4 * kq;
-    }
-    v4f c[PT][NT];
-#pragma unroll
-    for (int u = 0; u < PT; ++u)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) c[u][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int KC = CPin >> 4;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const unsigned need = 16u | (dx < 0 ? 1u : dx > 0 ? 2u : 0u) | (dy < 0 ? 4u : dy > 0 ? 8u : 0u);
-        const int off = (dy * W + dx) * CPin;
-        const bf16 *wb = Wp + tap * KC * NT * 256 + i * 16 + 4 * kq;
-        for (int kc = 0; kc < KC; ++kc) {
-            v4s wt[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
-#pragma unroll
-            for (int u = 0; u < PT; ++u) {
-                const bool ok = (fl[u] & need) == need;
-                v4s a = *reinterpret_cast<const v4s *>(xc[u] + (ok ? off : 0) + 16 * kc);
-                if (!ok) a = v4s{0, 0, 0, 0};
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    c[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[t], a, c[u][t], 0, 0, 0);
-            }
-        }
-    }
-    // lane holds D[4 kq + r][i] of every tile: channel 16 t + 4 kq + r of pixel
-    // pw0 + 16 u + i
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-        const int po = pw0 + 16 * u + i;
-        if (po >= M) continue;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            float v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = relu ? fmaxf(c[u][t][r], 0.f) : c[u][t][r];
-            const int ch = 16 * t + 4 * kq;
-            if (OUT_F32) {
-                float *yf = static_cast<float *>(Y) + static_cast<long long>(po) * creal;
-                if (t == 0 && kq == 0) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (r < creal) yf[r] = v[r];
-                }
-            } else {
-                bf16 *yb = static_cast<bf16 *>(Y) + static_cast<long long>(po) * CPout + ch;
-                if (acc) {
-                    const uint2 q = *reinterpret_cast<const uint2 *>(yb);
-                    v[0] += __uint_as_float(q.x << 16);
-                    v[1] += __uint_as_float(q.x & 0xFFFF0000u);
-                    v[2] += __uint_as_float(q.y << 16);
-                    v[3] += __uint_as_float(q.y & 0xFFFF0000u);
-                }
-                if (gate != nullptr) {
-                    const uint2 q = *reinterpret_cast<const uint2 *>(gate + static_cast<long long>(po) * CPout + ch);
-                    if ((q.x & 0xFFFFu) == 0) v[0] = 0.f;
-                    if ((q.x >> 16) == 0) v[1] = 0.f;
-                    if ((q.y & 0xFFFFu) == 0) v[2] = 0.f;
-                    if ((q.y >> 16) == 0) v[3] = 0.f;
-                }
-                *reinterpret_cast<uint2 *>(yb) =
-                    uint2{static_cast<unsigned>(f2bf(v[0])) | (static_cast<unsigned>(f2bf(v[1])) << 16),
-                          static_cast<unsigned>(f2bf(v[2])) | (static_cast<unsigned>(f2bf(v[3])) << 16)};
-            }
-        }
-    }
-}
-
-// The same convolution for images whose width is a multiple of 64 and
-// height a multiple of 4, with the input staged in LDS: a block computes a
-// tile of 4 rows x 64 pixels (wave w: row w, four tiles of 16 pixels) and
-// first loads the 6 x 66 input pixels that tile reads (zeros outside the
-// image) with 16-byte loads, in the layout of the tensor (channels of a
-// pixel contiguous); every tap's B operand is then one 8-byte LDS read per
-// lane instead of a gather through the caches.  Output as k_conv3x3.
+// A block computes a tile of 4 rows x 64 pixels (wave w: row w, four tiles
+// of 16 pixels; rows and 16-pixel tiles past the image's edge are skipped,
+// pixels past it are not written) and first loads the 6 x 66 input pixels
+// that tile reads (zeros outside the image) into LDS with 16-byte loads,
+// channels of a pixel contiguous.  The matrix-core product is
+// D[co][p] = W^T X^T: A is the weight block (lane: output channel
+// lane & 15, input channels 4 (lane >> 4) .. + 3), B the input (lane: pixel
+// lane & 15, the same four input channels, one 8-byte LDS read), so a tap's
+// weights serve the wave's 64 pixels and each lane ends with four
+// consecutive output channels of one pixel, written with one 8-byte store.
+// With 32 or 64 input channels the LDS pixel pitch is padded by eight
+// channels: a wave's read of 16 pixels x 16 channels then spreads over all
+// LDS banks (unpadded, 64 channels put all of it on 8 of the 32 banks).
+// NT: output channel tiles of the block (tiles NT blockIdx.y .. of the
+// ntot), KC: input channel blocks.  OUT_F32: write the
+// first `creal` (<= 4) channels as fp32 (the network's head).  gate
+// (nullable, shaped as the output): values are kept only where the gate is
+// positive (the ReLU mask of the tensor whose gradient this is; a post-ReLU
+// value is positive exactly when its bits are non-zero).
 template <int NT, int KC, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X,
                                                       const bf16 *__restrict__ Wp,
                                                       void *__restrict__ Y,
                                                       const bf16 *__restrict__ gate, int B, int H,
-                                                      int W, int relu, int acc, int creal) {
-    constexpr int CPin = 16 * KC, CPout = 16 * NT;
+                                                      int W, int relu, int acc, int creal, int ntot) {
+    constexpr int CPin = 16 * KC;
+    constexpr int PP = KC == 1 ? CPin : CPin + 8;          // LDS pixel pitch
+    const int CPout = 16 * ntot, t0 = blockIdx.y * NT;     // this block's column tiles
     constexpr int TW = 64, TH = 4, SW = TW + 2, SH = TH + 2;
-    __shared__ __align__(16) bf16 S[SH * SW * CPin];
+    __shared__ __align__(16) bf16 S[SH * SW * PP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, kq = lane >> 4;
-    const int tx = W / TW, ty = H / TH;
+    const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
     int blk = blockIdx.x;
     const int bx = blk % tx;
     blk /= tx;
@@ -178,10 +85,12 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
             if (gx >= 0 && gx < W && gy >= 0 && gy < H)
                 v = *reinterpret_cast<const uint4 *>(
                     X + ((static_cast<long long>(b) * H + gy) * W + gx) * CPin + c);
-            *reinterpret_cast<uint4 *>(S + pix * CPin + c) = v;
+            *reinterpret_cast<uint4 *>(S + pix * PP + c) = v;
         }
     }
     __syncthreads();
+    const int y = y0 + wave;
+    if (y >= H) return;
     v4f c[4][NT];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -190,16 +99,16 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const bf16 *wb = Wp + tap * KC * NT * 256 + i * 16 + 4 * kq;
+        const bf16 *wb = Wp + (tap * KC * ntot + t0) * 256 + i * 16 + 4 * kq;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             v4s wt[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * NT + t) * 256);
+            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * ntot + t) * 256);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) {        // pixels past the edge are zeros: no branch
                 const int sp = (wave + dy + 1) * SW + 16 * u + i + dx + 1;
-                const v4s a = *reinterpret_cast<const v4s *>(S + sp * CPin + 16 * kc + 4 * kq);
+                const v4s a = *reinterpret_cast<const v4s *>(S + sp * PP + 16 * kc + 4 * kq);
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
                     c[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[t], a, c[u][t], 0, 0, 0);
@@ -208,13 +117,14 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const long long po = (static_cast<long long>(b) * H + y0 + wave) * W + x0 + 16 * u + i;
+        if (x0 + 16 * u + i >= W) continue;
+        const long long po = (static_cast<long long>(b) * H + y) * W + x0 + 16 * u + i;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = relu ? fmaxf(c[u][t][r], 0.f) : c[u][t][r];
-            const int ch = 16 * t + 4 * kq;
+            const int ch = 16 * (t0 + t) + 4 * kq;
             if (OUT_F32) {
                 float *yf = static_cast<float *>(Y) + po * creal;
                 if (t == 0 && kq == 0) {
@@ -1065,56 +975,35 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-// B * H * W < 2^31 (the network object checks it at creation).
-// Pixel tiles per wave: four (a workgroup takes 256 pixels) where there are
-// enough pixels to fill the chip that way, else one.
+// B * H * W < 2^31 (the network object checks it at creation); channels
+// padded to 16, 32 or 64.
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
-    const long long M = static_cast<long long>(B) * H * W;
-    if (W % 64 == 0 && H % 4 == 0 && CPin <= 32 && M >= 256LL * 1024) {
-        // the LDS-staged tile kernel (4 rows x 64 pixels per block)
-        const dim3 grid(static_cast<unsigned>(M / 256)), blk(256);
-        const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
-                   *g = static_cast<const bf16 *>(gate);
+    const long long tiles = static_cast<long long>(B) * ((H + 3) / 4) * ((W + 63) / 64);
+    // fewer than 1024 pixel tiles: the output channel tiles are split over
+    // blocks (each stages the same input) so that more CUs take part
+    const int ntot = CPout / 16;
+    int split = 1;
+    while (split < ntot && tiles * split < 1024) split *= 2;
+    const int nt = ntot / split;
+    const dim3 grid(static_cast<unsigned>(tiles), split), blk(256);
+    const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
+               *g = static_cast<const bf16 *>(gate);
 #define RAS_TILE(NT, KC, F32)                                                                    \
     hipLaunchKernelGGL((k_conv3x3_tile<NT, KC, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W,      \
-                       relu ? 1 : 0, acc ? 1 : 0, creal)
+                       relu ? 1 : 0, acc ? 1 : 0, creal, ntot)
 #define RAS_TILE_KC(NT, F32)                  \
     do {                                      \
         if (CPin == 16) RAS_TILE(NT, 1, F32); \
-        else RAS_TILE(NT, 2, F32);            \
+        else if (CPin == 32) RAS_TILE(NT, 2, F32); \
+        else RAS_TILE(NT, 4, F32);            \
     } while (0)
-        if (out_f32) RAS_TILE_KC(1, true);
-        else if (CPout == 16) RAS_TILE_KC(1, false);
-        else if (CPout == 32) RAS_TILE_KC(2, false);
-        else RAS_TILE_KC(4, false);
+    if (out_f32) RAS_TILE_KC(1, true);         // one column tile: the head
+    else if (nt == 1) RAS_TILE_KC(1, false);
+    else if (nt == 2) RAS_TILE_KC(2, false);
+    else RAS_TILE_KC(4, false);
 #undef RAS_TILE_KC
 #undef RAS_TILE
-        return;
-    }
-    const bool wide = M >= 256LL * 1024;
-    const dim3 grid(blocks(M, wide ? 256 : 64)), blk(256);
-    const bf16 *x = static_cast<const bf16 *>(X), *w = static_cast<const bf16 *>(Wp),
-               *g = static_cast<const bf16 *>(gate);
-#define RAS_CONV(NT, PT, F32)                                                                    \
-    hipLaunchKernelGGL((k_conv3x3<NT, PT, F32>), grid, blk, 0, s, x, w, Y, g, B, H, W, CPin,    \
-                       relu ? 1 : 0, acc ? 1 : 0, creal)
-#define RAS_CONV_PT(NT, F32)                       \
-    do {                                           \
-        if (wide) RAS_CONV(NT, 4, F32);            \
-        else RAS_CONV(NT, 1, F32);                 \
-    } while (0)
-    if (out_f32) {
-        RAS_CONV_PT(1, true);
-    } else if (CPout == 16) {
-        RAS_CONV_PT(1, false);
-    } else if (CPout == 32) {
-        RAS_CONV_PT(2, false);
-    } else {
-        RAS_CONV_PT(4, false);
-    }
-#undef RAS_CONV_PT
-#undef RAS_CONV
 }
 
 int warm_wgrad_blocks(long long M, int *chunk) {

@@ -59,7 +59,9 @@ namespace {
 
 constexpr int kLayers = 10;            // e0 e1 e2 e3 e4 d3 d2 d1 d0 head
 constexpr int kMseBlocks = 1024;
-int cp16(int c) { return (c + 15) / 16 * 16; }
+// Channels padded to what the kernels are instantiated for: one, two or
+// four blocks of 16.
+int cpad(int c) { return c <= 16 ? 16 : c <= 32 ? 32 : 64; }
 
 }  // namespace
 
@@ -79,8 +81,8 @@ struct ras_pml_wsnet {
     std::vector<void *> allocs;
     std::string err;
 
-    int cip(int L) const { return cp16(cin[L]); }
-    int cop(int L) const { return cp16(cout[L]); }
+    int cip(int L) const { return cpad(cin[L]); }
+    int cop(int L) const { return cpad(cout[L]); }
     int side(int l) const { return grid >> l; }
     ~ras_pml_wsnet() {
         for (void *a : allocs) (void)hipFree(a);
@@ -101,7 +103,7 @@ namespace raspml {
 // forward pass on B samples; x: (B, grid, grid, 2) fp32, out: same shape
 int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream_t st) {
     const int G = N->grid;
-    const int C[5] = {cp16(N->ch[0]), cp16(N->ch[1]), cp16(N->ch[2]), cp16(N->ch[3]), cp16(N->ch[4])};
+    const int C[5] = {cpad(N->ch[0]), cpad(N->ch[1]), cpad(N->ch[2]), cpad(N->ch[3]), cpad(N->ch[4])};
     warm_pack_input(x, N->xin, static_cast<long long>(B) * G * G, st);
     warm_conv(N->xin, N->wf[0], N->e[0], nullptr, B, G, G, 16, C[0], true, false, false, 0, st);
     for (int l = 1; l <= 4; ++l) {
@@ -129,7 +131,7 @@ int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream
 // in N->g (padded layout), the loss in N->loss (device)
 int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipStream_t st) {
     const int G = N->grid;
-    const int C[5] = {cp16(N->ch[0]), cp16(N->ch[1]), cp16(N->ch[2]), cp16(N->ch[3]), cp16(N->ch[4])};
+    const int C[5] = {cpad(N->ch[0]), cpad(N->ch[1]), cpad(N->ch[2]), cpad(N->ch[3]), cpad(N->ch[4])};
     RCHK(wsnet_forward(N, x, B, N->y, st));
     warm_mse(N->y, t, static_cast<long long>(B) * G * G, N->lpart, kMseBlocks, N->gy, N->loss, st);
     // Every gradient is written already multiplied by the ReLU mask of the
@@ -238,7 +240,7 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     }
     auto act = [&](void **ptr, int l, int C) {
         const size_t S = static_cast<size_t>(grid >> l);
-        return N->alloc(ptr, static_cast<size_t>(batch_max) * S * S * cp16(C) * 2);
+        return N->alloc(ptr, static_cast<size_t>(batch_max) * S * S * cpad(C) * 2);
     };
     bool ok = act(&N->xin, 0, 16) && act(&N->gy, 0, 16);
     for (int l = 0; l < 5 && ok; ++l) ok = act(&N->e[l], l, c[l]);
@@ -250,8 +252,8 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     size_t dz_max = 0;
     for (int l = 0; l < 5; ++l) {
         const size_t S = static_cast<size_t>(grid >> l);
-        dz_max = std::max(dz_max, S * S * cp16(c[l]));
-        if (l < 4) dz_max = std::max(dz_max, S * S * cp16(dch[l]));
+        dz_max = std::max(dz_max, S * S * cpad(c[l]));
+        if (l < 4) dz_max = std::max(dz_max, S * S * cpad(dch[l]));
     }
     ok = ok && N->alloc(&N->dz, static_cast<size_t>(batch_max) * dz_max * 2);
     const size_t npix = static_cast<size_t>(batch_max) * grid * grid;

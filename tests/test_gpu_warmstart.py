@@ -107,6 +107,27 @@ def test_full_resolution_kernels_match_oracle():
         assert relerr(gd[name], gref[name]) <= 6e-2, (name, relerr(gd[name], gref[name]))
 
 
+@pytest.mark.parametrize("grid,B,channels", [(48, 2, (40, 48, 56, 64, 64)),
+                                              (80, 2, (12, 36, 64, 40, 40))])
+def test_wide_channels_and_ragged_tiles_match_oracle(grid, B, channels):
+    """Channel widths that pad to 64 (and to 32 next to 64), on grids whose
+    levels (48 .. 3, 80 .. 5) leave partial 64-pixel tiles, partial 4-row
+    tiles and widths that are no multiple of 4: forward, loss and every
+    layer's weight gradient against the float64 oracle."""
+    net, flat, x, t = setup(grid, B, 7, channels)
+    params = as_dict(flat, channels)
+    yref, tape = ows.forward(params, x.astype(np.float64))
+    y = net.forward(torch.from_numpy(x).cuda())
+    assert relerr(y.cpu().numpy(), yref) <= 3e-2
+    loss, g = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    lref = ows.loss(yref, t.astype(np.float64))
+    gref = ows.backward(params, tape, t.astype(np.float64))
+    assert abs(loss - lref) <= 3e-2 * lref
+    gd = as_dict(g, channels)
+    for name in rp.WS_LAYERS:
+        assert relerr(gd[name], gref[name]) <= 6e-2, (name, relerr(gd[name], gref[name]))
+
+
 def test_adam_first_step_and_determinism():
     """Adam's first step moves every weight by -lr g / (|g| + eps) (its
     bias-corrected moments are g and g^2), with g the network's own
