@@ -13,9 +13,9 @@
 //     written already multiplied by the ReLU mask of its tensor, by the
 //     kernel that produces it);
 //   weight gradient: rows = (tap, input channel), columns = output
-//     channels, K = pixels, split over workgroups in fixed chunks; every
-//     workgroup writes its partial sums and a second kernel adds them in a
-//     fixed order (deterministic).
+//     channels, K = pixels, split over waves by 64-column strips and row
+//     chunks; every workgroup writes its partial sums and two more kernels
+//     add them in a fixed order (deterministic).
 // Pooling (2 x 2 mean), nearest upsampling with the additive skip, the
 // squared-error loss and Adam are plain elementwise kernels.
 #include "device.h"
@@ -156,226 +156,31 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
     }
 }
 
-// Partial weight gradient of one pixel chunk:
-//   part[blk][tap][ci][co] = sum_{p in chunk} X[p + off(tap)][ci] dZ[p][co]
-// (dZ: the output gradient, already multiplied by the ReLU mask).
-// Each wave owns the (tap, channel block) row tiles w, w + 4, ...: at most
-// MAXT = ceil(9 KC / 4) of them (KC = input channel blocks).  The lane's four
-// pixels advance by 16 per step; their coordinates are stepped, not divided.
-template <int NT, int KC>
-__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const bf16 *__restrict__ X,
-                                                       const bf16 *__restrict__ dZ,
-                                                       float *__restrict__ part, int B, int H,
-                                                       int W, int chunk) {
-    constexpr int CPin = 16 * KC, CPout = 16 * NT;
-    constexpr int ntile = 9 * KC, MAXT = (ntile + 3) / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, kq = lane >> 4;
-    const int M = B * H * W;
-    const int c0 = blockIdx.x * chunk;
-    const int c1 = min(c0 + chunk, M);
-    v4f c[MAXT][NT];
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    int px[4], py[4], pb[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int q = min(c0 + 4 * kq + e, M - 1);
-        px[e] = q % W;
-        py[e] = (q / W) % H;
-        pb[e] = q / (W * H);
-    }
-    for (int p = c0; p < c1; p += 16) {
-        bool pv[4];
-        int q[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            pv[e] = p + 4 * kq + e < c1;
-            q[e] = (pb[e] * H + py[e]) * W + px[e];
-        }
-        v4s bz[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const short v = static_cast<short>(dZ[static_cast<long long>(pv[e] ? q[e] : 0) * CPout + 16 * t + i]);
-                bz[t][e] = pv[e] ? v : short(0);
-            }
-#pragma unroll
-        for (int s = 0; s < MAXT; ++s) {
-            const int T = wave + 4 * s;
-            if (T >= ntile) continue;
-            const int tap = T / KC, kc = T % KC;
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-            v4s a;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int yy = py[e] + dy, xx = px[e] + dx;
-                const bool ok = pv[e] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-                const int qq = ok ? q[e] + dy * W + dx : 0;
-                const short v = static_cast<short>(X[static_cast<long long>(qq) * CPin + 16 * kc + i]);
-                a[e] = ok ? v : short(0);
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                c[s][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[s][t], 0, 0, 0);
-        }
-        // advance the four pixels by 16
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            px[e] += 16;
-            while (px[e] >= W) {
-                px[e] -= W;
-                if (++py[e] == H) {
-                    py[e] = 0;
-                    ++pb[e];
-                }
-            }
-        }
-    }
-    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-        const int T = wave + 4 * s;
-        if (T >= ntile) continue;
-        const int tap = T / KC, kc = T % KC;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ci = 16 * kc + 4 * kq + r, co = 16 * t + i;
-                pw[(tap * CPin + ci) * CPout + co] = c[s][t][r];
-            }
-    }
-}
-
-// The weight gradient for 16 input channels and W divisible by 4: a lane's
-// four pixels then lie in one image row, so for each kernel row the six
-// input values x-1 .. x+4 serve the three horizontal taps (6 loads instead
-// of 12), and each wave takes all nine taps for its own pixels (no output
-// gradient is loaded twice).  A wave takes U groups of 16 pixels (64 pixels
-// apart, one group per wave of the block in between) per step and issues
-// the loads of all U before their multiplies, so that U groups' loads are in
-// flight at once.  The four waves' sums are added in LDS in wave order and
-// the block writes one partial: part[blk][tap][ci][co].
-template <int NT, int U>
-__global__ __launch_bounds__(256) void k_conv3x3_wgrad_k16(const bf16 *__restrict__ X,
-                                                           const bf16 *__restrict__ dZ,
-                                                           float *__restrict__ part, int B, int H,
-                                                           int W, int chunk) {
-    constexpr int CPin = 16, CPout = 16 * NT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = lane & 15, kq = lane >> 4;
-    const int M = B * H * W;                   // a multiple of 4, as is every chunk bound
-    const int c0 = blockIdx.x * chunk;
-    const int c1 = min(c0 + chunk, M);
-    v4f c[9][NT];
-#pragma unroll
-    for (int s = 0; s < 9; ++s)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    int p = c0 + 16 * wave + 4 * kq;           // first of the lane's four pixels
-    const int q0 = min(p, M - 4);
-    int x = q0 % W, y = (q0 / W) % H, b = q0 / (W * H);
-    for (; p - 4 * kq < c1; p += 64 * U) {
-        short v[U][3][6];
-        v4s bz[U][NT];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int pu = p + 64 * u;
-            const bool pv = pu < c1;           // then pu + 3 < c1 too
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const short z = static_cast<short>(dZ[static_cast<long long>(pv ? pu + e : 0) * CPout + 16 * t + i]);
-                    bz[u][t][e] = pv ? z : short(0);
-                }
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const int yy = y + dy - 1;
-                const bool rok = pv && yy >= 0 && yy < H;
-                const int row = (b * H + (rok ? yy : 0)) * W;
-#pragma unroll
-                for (int k = 0; k < 6; ++k) {
-                    const int xx = x - 1 + k;
-                    const bool ok = rok && xx >= 0 && xx < W;
-                    const short w = static_cast<short>(X[static_cast<long long>(ok ? row + xx : 0) * CPin + i]);
-                    v[u][dy][k] = ok ? w : short(0);
-                }
-            }
-            x += 64;                           // the next group: 64 pixels on
-            while (x >= W) {
-                x -= W;
-                if (++y == H) {
-                    y = 0;
-                    ++b;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const v4s a = v4s{v[u][dy][dx], v[u][dy][dx + 1], v[u][dy][dx + 2], v[u][dy][dx + 3]};
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        c[3 * dy + dx][t] =
-                            __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[u][t], c[3 * dy + dx][t], 0, 0, 0);
-                }
-    }
-    // waves 1..3 leave their sums in LDS, wave 0 adds them in wave order
-    constexpr int NV = 9 * NT * 4;                     // values per lane
-    __shared__ float red[3][NV][64];
-    if (wave > 0) {
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) red[wave - 1][(tap * NT + t) * 4 + r][lane] = c[tap][t][r];
-    }
-    __syncthreads();
-    if (wave != 0) return;
-    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int q = (tap * NT + t) * 4 + r;
-                const float w = ((c[tap][t][r] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
-                pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = w;
-            }
-}
-
-// Weight gradient for 16 input channels and widths divisible by 64, one
-// wave per strip: part[blk][tap][ci][co] = sum over the block's pixels of
-// X[y + dy][x + dx][ci] dZ[y][x][co].  A wave takes a strip of 64 columns
-// and rows y0 .. y1 - 1 of one image; its own LDS holds the input rows
-// y - 1 .. y + 1 of the strip with its two halo columns as a ring of three
-// rows, transposed to [ci][x - x0 + 1] (rows and columns outside the image
-// are zero), and the output-gradient row of the strip as [co][x - x0].  Each
-// step writes the rows that the registers hold (input row y + 1, output
-// gradient row y), issues the 16-byte loads of the next step's rows into the
+// Weight gradient, one wave per strip: part[blk][tap][ci][co] = sum over
+// the block's pixels of X[y + dy][x + dx][ci] dZ[y][x][co], for the input
+// channel block kc = blockIdx.y (channels 16 kc .. 16 kc + 15 of the CPin)
+// and the output tiles t0 .. t0 + NT - 1, t0 = NT blockIdx.z (of CPout / 16).
+// A wave takes a strip of 64 columns and rows y0 .. y1 - 1 of one image;
+// its own LDS holds the input rows y - 1 .. y + 1 of the strip (its channel
+// block) with the two halo columns as a ring of three rows, transposed to
+// [ci][x - x0 + 1], and the output-gradient row of the strip as [co][x - x0];
+// rows and columns outside the image are zero, so a strip that overhangs
+// the image's right edge computes on zeros without a branch.  Each step
+// writes the rows that the registers hold (input row y + 1, output gradient
+// row y), issues the 16-byte loads of the next step's rows into the
 // registers, and then runs the 36 NT multiplies of row y: for every group of
 // 16 pixels and kernel row, one 8-byte and one 4-byte LDS read give the six
 // values x - 1 .. x + 4 that serve the three horizontal taps.  No wave waits
 // for another until the four waves' sums are added in LDS, in wave order, so
-// that the block writes one partial.
+// that the block writes one partial (its channel block's rows of it).
 template <int NT>
-__global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ X,
-                                                       const bf16 *__restrict__ dZ,
-                                                       float *__restrict__ part, int B, int H, int W,
-                                                       int rows_per_wave, int nchunk) {
-    constexpr int CPin = 16, CPout = 16 * NT;
+__global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
+                                                     const bf16 *__restrict__ dZ,
+                                                     float *__restrict__ part, int B, int H, int W,
+                                                     int CPin, int CPout, int rows_per_wave, int nchunk) {
+    constexpr int ZR = (32 * NT + 63) / 64;
     constexpr int XP = 68;                         // columns x0 - 1 .. x0 + 64 at 0 .. 65
-    constexpr int XS = 3 * CPin * XP, ZS = CPout * 64;
+    constexpr int XS = 3 * 16 * XP, ZS = 16 * NT * 64;
     constexpr int RED = 3 * 36 * 64;               // floats of the wave-sum exchange
     constexpr int LDS_EL = 4 * (XS + ZS) > 2 * RED ? 4 * (XS + ZS) : 2 * RED;
     __shared__ __align__(16) bf16 lds[LDS_EL];
@@ -383,7 +188,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
     const int i = lane & 15, kq = lane >> 4;
     bf16 *Xs = lds + wave * (XS + ZS);
     bf16 *Zs = Xs + XS;
-    const int nstrip = W >> 6;
+    const int nstrip = (W + 63) >> 6, kc = blockIdx.y, t0 = NT * blockIdx.z;
     const int item = blockIdx.x * 4 + wave;
     v4f c[9][NT];
 #pragma unroll
@@ -394,8 +199,8 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
         const int x0 = (item % nstrip) << 6;
         const int chunk = (item / nstrip) % nchunk, b = item / (nstrip * nchunk);
         const int y0 = chunk * rows_per_wave, y1 = min(H, y0 + rows_per_wave);
-        const bf16 *img = X + static_cast<long long>(b) * H * W * CPin;
-        const bf16 *zimg = dZ + static_cast<long long>(b) * H * W * CPout;
+        const bf16 *img = X + static_cast<long long>(b) * H * W * CPin + 16 * kc;
+        const bf16 *zimg = dZ + static_cast<long long>(b) * H * W * CPout + 16 * t0;
         // input row yy: item it < 132 is column x0 - 1 + (it >> 1), channels 8 (it & 1) ..
         uint4 xr[3];
         auto load_x = [&](int yy) {
@@ -411,7 +216,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
             }
         };
         auto store_x = [&](int yy) {
-            bf16 *dst = Xs + ((yy + 3) % 3) * CPin * XP;
+            bf16 *dst = Xs + ((yy + 3) % 3) * 16 * XP;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int it = lane + 64 * r;
@@ -426,32 +231,41 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
                 }
             }
         };
-        // output-gradient row y: item it < 16 NT x 2 is pixels x0 + 4 (it & 15) .. + 3,
-        // channels 8 (it >> 4) ..
-        uint4 zr[4];
+        // output-gradient row y: item it < 32 NT is pixels x0 + 4 (it & 15) .. + 3,
+        // channels 8 (it >> 4) .. (zeros past the image's edge)
+        uint4 zr[ZR][4];
         auto load_z = [&](int y) {
-            const int it = lane;
-            if (it < 32 * NT) {
-                const bf16 *src = zimg + (static_cast<long long>(y) * W + x0 + 4 * (it & 15)) * CPout + 8 * (it >> 4);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) zr[e] = *reinterpret_cast<const uint4 *>(src + e * CPout);
+            for (int r = 0; r < ZR; ++r) {
+                const int it = lane + 64 * r;
+                if (it < 32 * NT) {
+                    const int px = x0 + 4 * (it & 15);
+                    const bf16 *src = zimg + (static_cast<long long>(y) * W + px) * CPout + 8 * (it >> 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        zr[r][e] = px + e < W ? *reinterpret_cast<const uint4 *>(src + e * CPout)
+                                              : uint4{0u, 0u, 0u, 0u};
+                }
             }
         };
         auto store_z = [&]() {
-            const int it = lane;
-            if (it < 32 * NT) {
-                const int q = it & 15, c8 = 8 * (it >> 4);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    unsigned h[4];
+            for (int r = 0; r < ZR; ++r) {
+                const int it = lane + 64 * r;
+                if (it < 32 * NT) {
+                    const int q = it & 15, c8 = 8 * (it >> 4);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const unsigned w = (k >> 1) == 0 ? zr[e].x : (k >> 1) == 1 ? zr[e].y
-                                         : (k >> 1) == 2 ? zr[e].z : zr[e].w;
-                        h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+                    for (int k = 0; k < 8; ++k) {
+                        unsigned h[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const unsigned w = (k >> 1) == 0 ? zr[r][e].x : (k >> 1) == 1 ? zr[r][e].y
+                                             : (k >> 1) == 2 ? zr[r][e].z : zr[r][e].w;
+                            h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
+                        }
+                        *reinterpret_cast<uint2 *>(Zs + (c8 + k) * 64 + 4 * q) =
+                            uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
                     }
-                    *reinterpret_cast<uint2 *>(Zs + (c8 + k) * 64 + 4 * q) =
-                        uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
                 }
             }
         };
@@ -482,7 +296,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
                     bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * 64 + xg + 4 * kq);
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
-                    const bf16 *rowl = Xs + ((y + dy + 2) % 3) * CPin * XP + i * XP + xg + 4 * kq;
+                    const bf16 *rowl = Xs + ((y + dy + 2) % 3) * 16 * XP + i * XP + xg + 4 * kq;
                     const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(rowl);
                     const unsigned hi = *reinterpret_cast<const unsigned *>(rowl + 4);
 #pragma unroll
@@ -525,177 +339,9 @@ __global__ __launch_bounds__(256) void k_wgrad_strip16(const bf16 *__restrict__ 
                     const int q = tap * 4 + r;
                     const float w = ((c[tap][t][r] + red[q * 64 + lane]) + red[(36 + q) * 64 + lane]) +
                                     red[(72 + q) * 64 + lane];
-                    pw[(tap * CPin + 4 * kq + r) * CPout + 16 * t + i] = w;
+                    pw[(tap * CPin + 16 * kc + 4 * kq + r) * CPout + 16 * (t0 + t) + i] = w;
                 }
         }
-    }
-}
-
-// Weight gradient with the rows staged in LDS (any channel counts that are
-// multiples of 16, widths that are multiples of 4):
-//   part[blk][tap][ci][co] = sum over the block's pixels of
-//                            X[y + dy][x + dx][ci] dZ[y][x][co].
-// A block takes a strip of SWD columns (SWD divides W and is a multiple of
-// 4; the launcher passes the whole row) and consecutive image rows down it.  Per row, the
-// three input rows y - 1 .. y + 1 of the strip and its two halo columns sit
-// in LDS transposed to [ci][x - x0 + 1] (a sliding window: moving to the next
-// row of the same image loads one new input row; rows outside the image and
-// columns outside it or past the strip's padding are zero), and the
-// output-gradient row of the strip in [co][x - x0].  Both are loaded with
-// 16-byte reads (four pixels by eight channels per item) and written
-// transposed.  Each wave owns the (tap, channel block) row tiles wave,
-// wave + 4, ...; for every group of 16 pixels a tile takes its A operand
-// (channel ci = 16 kc + lane & 15, pixels x + 4 (lane >> 4) + dx .. + 3) from
-// one 8-byte and one 4-byte LDS read (the six values x - 1 .. x + 4 cover
-// the three horizontal taps) and its B operand from one 8-byte read.
-template <int NT, int KC>
-__global__ __launch_bounds__(256) void k_wgrad_rows(const bf16 *__restrict__ X,
-                                                    const bf16 *__restrict__ dZ,
-                                                    float *__restrict__ part, int B, int H, int W,
-                                                    int SWD, int rows_per_blk) {
-    constexpr int CPin = 16 * KC, CPout = 16 * NT;
-    constexpr int ntile = 9 * KC, MAXT = (ntile + 3) / 4;
-    extern __shared__ __align__(16) unsigned char wg_lds[];
-    const int S16 = (SWD + 15) & ~15;           // strip padded to whole pixel groups
-    const int XP = S16 + 4;                     // input row: column x - x0 at index x - x0 + 1
-    bf16 *Xs = reinterpret_cast<bf16 *>(wg_lds);          // [3][CPin][XP]
-    bf16 *Zs = Xs + 3 * CPin * XP;                         // [CPout][S16]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int i = lane & 15, kq = lane >> 4;
-    const int nstrip = W / SWD;
-    const int strip = blockIdx.x % nstrip;
-    const int x0 = strip * SWD;
-    const int R = B * H;
-    const int r0 = (blockIdx.x / nstrip) * rows_per_blk, r1 = min(r0 + rows_per_blk, R);
-    {   // zeros everywhere: the padding stays zero
-        unsigned *z = reinterpret_cast<unsigned *>(wg_lds);
-        const int nw = (3 * CPin * XP + CPout * S16) / 2;
-        for (int k = tid; k < nw; k += 256) z[k] = 0u;
-    }
-    v4f c[MAXT][NT];
-#pragma unroll
-    for (int s = 0; s < MAXT; ++s)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) c[s][t] = v4f{0.f, 0.f, 0.f, 0.f};
-    // the strip's part of one input row (image b, row yy; zeros outside the
-    // image) and its halo columns x0 - 1, x0 + SWD into slot sl
-    auto stage_x = [&](int b, int yy, int sl) {
-        bf16 *dst = Xs + sl * CPin * XP;
-        const bool in = yy >= 0 && yy < H;
-        const bf16 *rowp = X + static_cast<long long>(b * H + (in ? yy : 0)) * W * CPin;
-        const int nq = SWD >> 2, items = nq * (CPin >> 3);
-        for (int it = tid; it < items + 2 * (CPin >> 3); it += 256) {
-            if (it < items) {
-                const int q = it % nq, c8 = (it / nq) * 8;
-                uint4 v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    v[e] = in ? *reinterpret_cast<const uint4 *>(rowp + (x0 + 4 * q + e) * CPin + c8)
-                              : uint4{0u, 0u, 0u, 0u};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const unsigned u[4] = {v[e].x, v[e].y, v[e].z, v[e].w};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        dst[(c8 + 2 * k) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] & 0xFFFFu);
-                        dst[(c8 + 2 * k + 1) * XP + 4 * q + e + 1] = static_cast<bf16>(u[k] >> 16);
-                    }
-                }
-            } else {   // halo column: left (x0 - 1 at index 0) or right (x0 + SWD)
-                const int h = it - items;
-                const int side = h / (CPin >> 3), c8 = (h % (CPin >> 3)) * 8;
-                const int gx = side == 0 ? x0 - 1 : x0 + SWD;
-                const int idx = side == 0 ? 0 : SWD + 1;
-                uint4 v = uint4{0u, 0u, 0u, 0u};
-                if (in && gx >= 0 && gx < W) v = *reinterpret_cast<const uint4 *>(rowp + gx * CPin + c8);
-                const unsigned u[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    dst[(c8 + 2 * k) * XP + idx] = static_cast<bf16>(u[k] & 0xFFFFu);
-                    dst[(c8 + 2 * k + 1) * XP + idx] = static_cast<bf16>(u[k] >> 16);
-                }
-            }
-        }
-    };
-    // the strip's output-gradient row (image b, row y), four pixels per write
-    auto stage_z = [&](int b, int y) {
-        const bf16 *rowp = dZ + static_cast<long long>(b * H + y) * W * CPout;
-        const int nq = SWD >> 2, items = nq * (CPout >> 3);
-        for (int it = tid; it < items; it += 256) {
-            const int q = it % nq, c8 = (it / nq) * 8;
-            uint4 v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                v[e] = *reinterpret_cast<const uint4 *>(rowp + (x0 + 4 * q + e) * CPout + c8);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                unsigned h[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const unsigned w = (k >> 1) == 0 ? v[e].x : (k >> 1) == 1 ? v[e].y
-                                     : (k >> 1) == 2 ? v[e].z : v[e].w;
-                    h[e] = (k & 1) ? (w >> 16) : (w & 0xFFFFu);
-                }
-                *reinterpret_cast<uint2 *>(Zs + (c8 + k) * S16 + 4 * q) =
-                    uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
-            }
-        }
-    };
-    int pb = -1, py = -2;                      // image and row of the previous step
-    for (int r = r0; r < r1; ++r) {
-        const int b = r / H, y = r % H;
-        __syncthreads();                       // the previous row's reads are done
-        if (b == pb && y == py + 1) {
-            stage_x(b, y + 1, (y + 1 + 3) % 3);
-        } else {
-            for (int d = -1; d <= 1; ++d) stage_x(b, y + d, (y + d + 3) % 3);
-        }
-        stage_z(b, y);
-        pb = b;
-        py = y;
-        __syncthreads();
-        for (int xg = 0; xg < S16; xg += 16) {
-            v4s bz[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-                bz[t] = *reinterpret_cast<const v4s *>(Zs + (16 * t + i) * S16 + xg + 4 * kq);
-#pragma unroll
-            for (int s2 = 0; s2 < MAXT; ++s2) {
-                const int T = wave + 4 * s2;
-                if (T >= ntile) continue;
-                const int tap = T / KC, kc = T % KC;
-                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                const bf16 *rowl = Xs + ((y + dy + 3) % 3) * CPin * XP + (16 * kc + i) * XP + xg + 4 * kq;
-                // six values x - 1 .. x + 4 (indices x - x0 .. x - x0 + 5 of the padded row)
-                const unsigned long long lo = *reinterpret_cast<const unsigned long long *>(rowl);
-                const unsigned hi = *reinterpret_cast<const unsigned *>(rowl + 4);
-                const int sh = 16 * (dx + 1);
-                const unsigned long long w =
-                    sh == 0 ? lo : (lo >> sh) | (static_cast<unsigned long long>(hi) << (64 - sh));
-                v4s a;
-                a[0] = static_cast<short>(w & 0xFFFFu);
-                a[1] = static_cast<short>((w >> 16) & 0xFFFFu);
-                a[2] = static_cast<short>((w >> 32) & 0xFFFFu);
-                a[3] = static_cast<short>((w >> 48) & 0xFFFFu);
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-                    c[s2][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bz[t], c[s2][t], 0, 0, 0);
-            }
-        }
-    }
-    float *pw = part + static_cast<long long>(blockIdx.x) * 9 * CPin * CPout;
-#pragma unroll
-    for (int s2 = 0; s2 < MAXT; ++s2) {
-        const int T = wave + 4 * s2;
-        if (T >= ntile) continue;
-        const int tap = T / KC, kc = T % KC;
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int ci = 16 * kc + 4 * kq + r, co = 16 * t + i;
-                pw[(tap * CPin + ci) * CPout + co] = c[s2][t][r];
-            }
     }
 }
 
@@ -1006,14 +652,6 @@ void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, 
 #undef RAS_TILE
 }
 
-int warm_wgrad_blocks(long long M, int *chunk) {
-    long long c = (M + 1023) / 1024;
-    c = (c + 15) / 16 * 16;
-    if (c < 256) c = 256;
-    *chunk = static_cast<int>(c);
-    return static_cast<int>((M + c - 1) / c);
-}
-
 // g = sum of the nblk partial gradients (n values each), tmp: kSumSlices * n.
 void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipStream_t s) {
     const int per = (nblk + kSumSlices - 1) / kSumSlices;
@@ -1022,132 +660,42 @@ void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipS
     hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(n, 256)), dim3(256), 0, s, tmp, n, g);
 }
 
-// Strips and row chunks of k_wgrad_strip16: about 4096 waves (one per SIMD
-// slot the kernel's LDS leaves), at least one row per wave.
-int warm_wgrad_strip16_blocks(int B, int H, int W, int *rows_per_wave, int *nchunk) {
-    const int nstrip = W / 64;
-    const int want = std::max(1, std::min(H, 4096 / std::max(1, B * nstrip)));
+// Strips and row chunks of k_wgrad_strip: about 4096 waves over the input
+// channel blocks and output tile groups (2048 with two output tiles a wave,
+// whose registers leave two waves per SIMD), at least one row per wave.
+// Returns the blocks in x.
+int warm_wgrad_strip_blocks(int B, int H, int W, int KC, int NT, int NZ, int *rows_per_wave,
+                            int *nchunk) {
+    const int nstrip = (W + 63) / 64;
+    const int target = std::max(1, (NT == 2 ? 2048 : 4096) / (KC * NZ));
+    const int want = std::max(1, std::min(H, target / std::max(1, B * nstrip)));
     const int rpw = (H + want - 1) / want;
     *rows_per_wave = rpw;
     *nchunk = (H + rpw - 1) / rpw;
     return (B * *nchunk * nstrip + 3) / 4;
 }
-// The most blocks it gives for any batch up to B.
-int warm_wgrad_strip16_blocks_max(int B, int W) {
-    return (std::max(4096, B * (W / 64)) + 3) / 4 + 1;
+// The most blocks (in x) it gives for any batch up to B.
+int warm_wgrad_strip_blocks_max(int B, int W) {
+    return (std::max(4096, B * ((W + 63) / 64)) + 3) / 4 + 1;
 }
-
-// Strip width of the row-staged weight gradient (the whole row: narrower
-// strips were measured slower, their barriers per multiply being more), its
-// blocks (strips x row chunks: 512 for up to two channel tiles, fewer for
-// more so that the partials stay small; at most one row chunk per image row)
-// and its LDS bytes.
-int warm_wgrad_strip(int W) { return W; }
-static int wgrad_rows_chunks(int W, int CPin, int CPout) {
-    const int nstrip = W / warm_wgrad_strip(W);
-    const int tiles = (CPin / 16) * (CPout / 16);
-    const int want = tiles >= 8 ? 128 : tiles >= 4 ? 256 : 512;
-    return std::max(1, want / nstrip);
-}
-int warm_wgrad_rows_blocks(int B, int H, int W, int CPin, int CPout, int *rows_per_blk) {
-    const int R = B * H, nstrip = W / warm_wgrad_strip(W);
-    const int chunks = wgrad_rows_chunks(W, CPin, CPout);
-    const int rpb = (R + chunks - 1) / chunks;
-    *rows_per_blk = rpb;
-    return nstrip * ((R + rpb - 1) / rpb);
-}
-// The most blocks warm_wgrad_rows_blocks gives for any batch up to B.
-int warm_wgrad_rows_blocks_max(int B, int H, int W, int CPin, int CPout) {
-    const int nstrip = W / warm_wgrad_strip(W);
-    return nstrip * std::min(B * H, wgrad_rows_chunks(W, CPin, CPout));
-}
-size_t warm_wgrad_rows_lds(int W, int CPin, int CPout) {
-    const size_t S16 = (static_cast<size_t>(warm_wgrad_strip(W)) + 15) & ~static_cast<size_t>(15);
-    return 2 * (3 * CPin * (S16 + 4) + CPout * S16);
-}
-constexpr size_t kWgradRowsMaxLds = 96 * 1024;
 
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
                 int W, int CPin, int CPout, hipStream_t s) {
-    const long long M = static_cast<long long>(B) * H * W;
-    int chunk = 0;
-    const int nblk = warm_wgrad_blocks(M, &chunk);
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
     const int n = 9 * CPin * CPout;
-    const size_t lds = warm_wgrad_rows_lds(W, CPin, CPout);
-    if (CPin == 16 && CPout <= 32 && W % 64 == 0) {   // one wave per strip
-        int rpw = 0, nch = 0;
-        const int nb = warm_wgrad_strip16_blocks(B, H, W, &rpw, &nch);
-        if (CPout == 16)
-            hipLaunchKernelGGL(k_wgrad_strip16<1>, dim3(nb), dim3(256), 0, s, x, dz, part, B, H, W, rpw, nch);
-        else
-            hipLaunchKernelGGL(k_wgrad_strip16<2>, dim3(nb), dim3(256), 0, s, x, dz, part, B, H, W, rpw, nch);
-        sum_partials(part, nb, n, tmp, g, s);
-        return;
-    }
-    // 16 -> 16 channels at other widths: the per-wave kernel below keeps more
-    // waves per CU than the row-staged one (measured 103 us against 256 us at
-    // 640 x 640 x 8); every other layer is faster row-staged
-    const bool k16_1 = CPin == 16 && CPout == 16 && W % 4 == 0;
-    if (!k16_1 && W % 4 == 0 && lds <= kWgradRowsMaxLds) {
-        int rpb = 0;
-        const int nb = warm_wgrad_rows_blocks(B, H, W, CPin, CPout, &rpb);
-        const int swd = warm_wgrad_strip(W);
-#define RAS_WR(NT, KC)                                                                           \
-    do {                                                                                         \
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_wgrad_rows<NT, KC>),          \
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,                    \
-                                  static_cast<int>(lds));                                        \
-        hipLaunchKernelGGL((k_wgrad_rows<NT, KC>), dim3(nb), dim3(256), lds, s, x, dz, part, B,   \
-                           H, W, swd, rpb);                                                      \
-    } while (0)
-#define RAS_WR_KC(NT)                                                                            \
-    do {                                                                                         \
-        if (CPin == 16) RAS_WR(NT, 1);                                                           \
-        else if (CPin == 32) RAS_WR(NT, 2);                                                      \
-        else RAS_WR(NT, 4);                                                                      \
-    } while (0)
-        if (CPout == 16)
-            RAS_WR_KC(1);
-        else if (CPout == 32)
-            RAS_WR_KC(2);
-        else
-            RAS_WR_KC(4);
-#undef RAS_WR_KC
-#undef RAS_WR
-        sum_partials(part, nb, n, tmp, g, s);
-        return;
-    }
-    if (CPin == 16 && CPout <= 32 && W % 4 == 0) {     // per-wave partials: 4 per block
-        if (CPout == 16)
-            hipLaunchKernelGGL((k_conv3x3_wgrad_k16<1, 4>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
-                               W, chunk);
-        else
-            hipLaunchKernelGGL((k_conv3x3_wgrad_k16<2, 4>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H,
-                               W, chunk);
-        sum_partials(part, nblk, n, tmp, g, s);
-        return;
-    }
-#define RAS_WG(NT, KC)                                                                           \
-    hipLaunchKernelGGL((k_conv3x3_wgrad<NT, KC>), dim3(nblk), dim3(256), 0, s, x, dz, part, B, H, \
-                       W, chunk)
-#define RAS_WG_KC(NT)                                                                            \
-    do {                                                                                         \
-        if (CPin == 16) RAS_WG(NT, 1);                                                           \
-        else if (CPin == 32) RAS_WG(NT, 2);                                                      \
-        else RAS_WG(NT, 4);                                                                      \
-    } while (0)
-    if (CPout == 16)
-        RAS_WG_KC(1);
-    else if (CPout == 32)
-        RAS_WG_KC(2);
+    // one wave per strip, at most two output tiles a wave
+    const int KC = CPin / 16, NT = CPout == 16 ? 1 : 2, NZ = CPout / (16 * NT);
+    int rpw = 0, nch = 0;
+    const int nb = warm_wgrad_strip_blocks(B, H, W, KC, NT, NZ, &rpw, &nch);
+    const dim3 grid(nb, KC, NZ);
+    if (NT == 1)
+        hipLaunchKernelGGL(k_wgrad_strip<1>, grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin, CPout, rpw,
+                           nch);
     else
-        RAS_WG_KC(4);
-#undef RAS_WG_KC
-#undef RAS_WG
-    sum_partials(part, nblk, n, tmp, g, s);
+        hipLaunchKernelGGL(k_wgrad_strip<2>, grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin, CPout, rpw,
+                           nch);
+    sum_partials(part, nb, n, tmp, g, s);
 }
-
 
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s) {
     const long long n = static_cast<long long>(B) * (H / 2) * (W / 2) * (C / 8);

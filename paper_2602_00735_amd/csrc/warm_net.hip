@@ -32,9 +32,7 @@ namespace raspml {
 
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
-int warm_wgrad_blocks(long long M, int *chunk);
-int warm_wgrad_rows_blocks_max(int B, int H, int W, int CPin, int CPout);
-int warm_wgrad_strip16_blocks_max(int B, int W);
+int warm_wgrad_strip_blocks_max(int B, int W);
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
                 int W, int CPin, int CPout, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
@@ -226,17 +224,9 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
         if (!N->alloc(&N->w[L], nw * 4) || !N->alloc(&N->m[L], nw * 4) || !N->alloc(&N->v[L], nw * 4) ||
             !N->alloc(&N->g[L], np * 4) || !N->alloc(&N->wf[L], np * 2) || !N->alloc(&N->wb[L], np * 2))
             return RAS_ENOMEM;
-        // any batch B <= batch_max uses at most min(1024, ceil(M / 256))
-        // partial blocks (chunks of >= 256 pixels, >= M / 1024 each)
+        // the weight gradient's partial blocks for any batch up to batch_max
         const int S = grid >> lvl[L];
-        const long long M = static_cast<long long>(batch_max) * S * S;
-        const long long nblk = std::min(1024LL, (M + 255) / 256);
-        part_max = std::max(part_max, static_cast<size_t>(nblk) * np);
-        // the row-staged kernel's blocks for any batch up to batch_max
-        const int nbr = warm_wgrad_rows_blocks_max(batch_max, S, S, N->cip(L), N->cop(L));
-        part_max = std::max(part_max, static_cast<size_t>(nbr) * np);
-        // the strip kernel (16 input channels)
-        part_max = std::max(part_max, static_cast<size_t>(warm_wgrad_strip16_blocks_max(batch_max, S)) * np);
+        part_max = std::max(part_max, static_cast<size_t>(warm_wgrad_strip_blocks_max(batch_max, S)) * np);
     }
     auto act = [&](void **ptr, int l, int C) {
         const size_t S = static_cast<size_t>(grid >> l);
