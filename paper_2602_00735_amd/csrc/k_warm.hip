@@ -34,6 +34,15 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
     u += 0x7FFFu + ((u >> 16) & 1u);
     return static_cast<bf16>(u >> 16);
 }
+// Block i runs on XCD i mod 8 (the dispatcher deals blocks out round
+// robin); the tile it takes: XCD x gets the x-th contiguous run of the n
+// tiles, in order, so that a tile row and the next one (which share two
+// input rows) are staged through the same L2.  A bijection of 0 .. n - 1.
+__device__ __forceinline__ int xcd_run(int i, int n) {
+    const int x = i & 7, l = i >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + l;
+}
+
 // out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
 // A block computes a tile of 4 rows x 64 pixels (wave w: row w, four tiles
 // of 16 pixels; rows and 16-pixel tiles past the image's edge are skipped,
@@ -55,7 +64,9 @@ __device__ __forceinline__ bf16 f2bf(float f) {          // round to nearest eve
 // positive (the ReLU mask of the tensor whose gradient this is; a post-ReLU
 // value is positive exactly when its bits are non-zero).
 template <int NT, int KC, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(NT == 4 ? 1 : KC == 1 ? (NT == 1 ? 8 : 6) : KC == 2 ? 5 : 2))) void
+k_conv3x3_tile(const bf16 *__restrict__ X,
                                                       const bf16 *__restrict__ Wp,
                                                       void *__restrict__ Y,
                                                       const bf16 *__restrict__ gate, int B, int H,
@@ -68,24 +79,49 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, kq = lane >> 4;
     const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
-    int blk = blockIdx.x;
+    int blk = xcd_run(blockIdx.x, gridDim.x);
     const int bx = blk % tx;
     blk /= tx;
     const int by = blk % ty;
     const int b = blk / ty;
     const int x0 = bx * TW, y0 = by * TH;
+    // with at most two (channel block, column tile) pairs the wave's weights
+    // (9 KC NT operands) are loaded before the input tile, so that their
+    // latency overlaps the staging instead of the multiplies
+    constexpr bool PRE = KC * NT <= 2;
+    v4s wpre[PRE ? 9 * KC * NT : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int q = 0; q < 9 * KC; ++q)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                wpre[q * NT + t] = *reinterpret_cast<const v4s *>(Wp + (q * ntot + t0 + t) * 256 + i * 16 + 4 * kq);
+    }
     {   // stage the input tile: pixel (sy, sx) of the tile is input pixel
-        // (y0 + sy - 1, x0 + sx - 1)
-        constexpr int C8 = CPin / 8, items = SH * SW * C8;
-        for (int it = tid; it < items; it += 256) {
+        // (y0 + sy - 1, x0 + sx - 1); every load of the thread is issued
+        // before the first LDS write, so that their latencies overlap
+        constexpr int C8 = CPin / 8, items = SH * SW * C8, NIT = (items + 255) / 256;
+        uint4 v[NIT];
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int it = tid + 256 * k;
             const int c = (it % C8) * 8, pix = it / C8;
             const int sx = pix % SW, sy = pix / SW;
             const int gx = x0 + sx - 1, gy = y0 + sy - 1;
-            uint4 v = uint4{0u, 0u, 0u, 0u};
-            if (gx >= 0 && gx < W && gy >= 0 && gy < H)
-                v = *reinterpret_cast<const uint4 *>(
-                    X + ((static_cast<long long>(b) * H + gy) * W + gx) * CPin + c);
-            *reinterpret_cast<uint4 *>(S + pix * PP + c) = v;
+            // branch-free: outside the image the load reads element 0 and
+            // the value is masked to zeros (the mask is opaque to the
+            // compiler, which would otherwise move the load into a branch)
+            const bool ok = it < items && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const long long off = ok ? ((static_cast<long long>(b) * H + gy) * W + gx) * CPin + c : 0;
+            unsigned m = ok ? 0xFFFFFFFFu : 0u;
+            asm volatile("" : "+v"(m));
+            const uint4 t = *reinterpret_cast<const uint4 *>(X + off);
+            v[k] = uint4{t.x & m, t.y & m, t.z & m, t.w & m};
+        }
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int it = tid + 256 * k;
+            if (it < items) *reinterpret_cast<uint4 *>(S + (it / C8) * PP + (it % C8) * 8) = v[k];
         }
     }
     __syncthreads();
@@ -104,7 +140,12 @@ __global__ __launch_bounds__(256) void k_conv3x3_tile(const bf16 *__restrict__ X
         for (int kc = 0; kc < KC; ++kc) {
             v4s wt[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * ntot + t) * 256);
+            for (int t = 0; t < NT; ++t) {
+                if constexpr (PRE)
+                    wt[t] = wpre[(tap * KC + kc) * NT + t];
+                else
+                    wt[t] = *reinterpret_cast<const v4s *>(wb + (kc * ntot + t) * 256);
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {        // pixels past the edge are zeros: no branch
                 const int sp = (wave + dy + 1) * SW + 16 * u + i + dx + 1;
@@ -202,8 +243,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
         const bf16 *img = X + static_cast<long long>(b) * H * W * CPin + 16 * kc;
         const bf16 *zimg = dZ + static_cast<long long>(b) * H * W * CPout + 16 * t0;
         // input row yy: item it < 132 is column x0 - 1 + (it >> 1), channels 8 (it & 1) ..
-        uint4 xr[3];
-        auto load_x = [&](int yy) {
+        auto load_x = [&](int yy, uint4 (&xr)[3]) {
             const bool in = yy >= 0 && yy < H;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
@@ -215,7 +255,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
                                                              8 * (it & 1));
             }
         };
-        auto store_x = [&](int yy) {
+        auto store_x = [&](int yy, const uint4 (&xr)[3]) {
             bf16 *dst = Xs + ((yy + 3) % 3) * 16 * XP;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
@@ -233,8 +273,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
         };
         // output-gradient row y: item it < 32 NT is pixels x0 + 4 (it & 15) .. + 3,
         // channels 8 (it >> 4) .. (zeros past the image's edge)
-        uint4 zr[ZR][4];
-        auto load_z = [&](int y) {
+        auto load_z = [&](int y, uint4 (&zr)[ZR][4]) {
 #pragma unroll
             for (int r = 0; r < ZR; ++r) {
                 const int it = lane + 64 * r;
@@ -248,7 +287,7 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
                 }
             }
         };
-        auto store_z = [&]() {
+        auto store_z = [&](const uint4 (&zr)[ZR][4]) {
 #pragma unroll
             for (int r = 0; r < ZR; ++r) {
                 const int it = lane + 64 * r;
@@ -269,24 +308,25 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
                 }
             }
         };
-        load_x(y0 - 1);
-        store_x(y0 - 1);
-        load_x(y0);
-        store_x(y0);
-        load_x(y0 + 1);
-        load_z(y0);
+        uint4 xr[3], zr[ZR][4];
+        load_x(y0 - 1, xr);
+        store_x(y0 - 1, xr);
+        load_x(y0, xr);
+        store_x(y0, xr);
+        load_x(y0 + 1, xr);
+        load_z(y0, zr);
         for (int y = y0; y < y1; ++y) {
             // the previous step's reads of the slot and of Zs are done: a
             // wave's LDS accesses complete in order
             __builtin_amdgcn_wave_barrier();
-            store_x(y + 1);
-            store_z();
+            store_x(y + 1, xr);
+            store_z(zr);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (y + 1 < y1) {
-                load_x(y + 2);
-                load_z(y + 1);
+                load_x(y + 2, xr);
+                load_z(y + 1, zr);
             }
 #pragma unroll
             for (int xg = 0; xg < 64; xg += 16) {
