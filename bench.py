@@ -559,17 +559,20 @@ def warmstart(args):
     # algorithmic flops of one training step: forward, input gradient (all but
     # the first convolution) and weight gradient of every 3 x 3 convolution
     # and its algorithmic HBM bytes: every convolution reads its input and
-    # writes its output (bf16, channels padded to 16), the input gradient
-    # reads the masked output gradient and writes the input gradient, the
-    # weight gradient reads input and masked gradient, and the kernel that
-    # writes a masked gradient reads the activation for its ReLU mask
+    # writes its output (bf16, channels padded to 16; the network's input and
+    # its output and output gradient are two fp32 channels, 8 bytes a pixel),
+    # the input gradient reads the masked output gradient and writes the
+    # input gradient, the weight gradient reads input and masked gradient,
+    # and the kernel that writes a masked gradient reads the activation for
+    # its ReLU mask
     lv = (0, 1, 2, 3, 4, 3, 2, 1, 0, 0)
     cp = lambda c: (c + 15) // 16 * 16
     flops = nbytes = 0.0
     for li, (ci, co) in enumerate(rp.ws_shapes(channels)):
         m = Bt * (n >> lv[li]) ** 2
         flops += (3 if li > 0 else 2) * 2.0 * m * 9 * ci * co
-        a, b = 2.0 * m * cp(ci), 2.0 * m * cp(co)
+        a = 8.0 * m if li == 0 else 2.0 * m * cp(ci)
+        b = 8.0 * m if li == 9 else 2.0 * m * cp(co)
         nbytes += (a + b) * (3 if li > 0 else 2) + (b if li < 9 else 0)
     t0 = time.perf_counter()
     step_times = []

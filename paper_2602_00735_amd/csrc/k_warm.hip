@@ -58,12 +58,14 @@ __device__ __forceinline__ int xcd_run(int i, int n) {
 // channels: a wave's read of 16 pixels x 16 channels then spreads over all
 // LDS banks (unpadded, 64 channels put all of it on 8 of the 32 banks).
 // NT: output channel tiles of the block (tiles NT blockIdx.y .. of the
-// ntot), KC: input channel blocks.  OUT_F32: write the
+// ntot), KC: input channel blocks.  IN2: the input is two fp32 channels per
+// pixel (the network's input, or the loss gradient at its head), rounded to
+// bf16 as it is staged, channels 2 .. 15 zero (KC = 1).  OUT_F32: write the
 // first `creal` (<= 4) channels as fp32 (the network's head).  gate
 // (nullable, shaped as the output): values are kept only where the gate is
 // positive (the ReLU mask of the tensor whose gradient this is; a post-ReLU
 // value is positive exactly when its bits are non-zero).
-template <int NT, int KC, bool OUT_F32>
+template <int NT, int KC, bool OUT_F32, bool IN2 = false>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NT == 4 ? 1 : KC == 1 ? (NT == 1 ? 8 : 6) : KC == 2 ? 5 : 2))) void
 k_conv3x3_tile(const bf16 *__restrict__ X,
@@ -97,7 +99,33 @@ k_conv3x3_tile(const bf16 *__restrict__ X,
             for (int t = 0; t < NT; ++t)
                 wpre[q * NT + t] = *reinterpret_cast<const v4s *>(Wp + (q * ntot + t0 + t) * 256 + i * 16 + 4 * kq);
     }
-    {   // stage the input tile: pixel (sy, sx) of the tile is input pixel
+    if constexpr (IN2) {   // two fp32 channels per pixel, one 8-byte load each
+        static_assert(KC == 1, "two-channel input: one channel block");
+        constexpr int items = SH * SW, NIT = (items + 255) / 256;
+        const float *Xf = reinterpret_cast<const float *>(X);
+        float2 v[NIT];
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int pix = tid + 256 * k;
+            const int sx = pix % SW, sy = pix / SW;
+            const int gx = x0 + sx - 1, gy = y0 + sy - 1;
+            const bool ok = pix < items && gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const long long off = ok ? ((static_cast<long long>(b) * H + gy) * W + gx) * 2 : 0;
+            unsigned m = ok ? 0xFFFFFFFFu : 0u;
+            asm volatile("" : "+v"(m));
+            const float2 t = *reinterpret_cast<const float2 *>(Xf + off);
+            v[k] = float2{__uint_as_float(__float_as_uint(t.x) & m), __uint_as_float(__float_as_uint(t.y) & m)};
+        }
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int pix = tid + 256 * k;
+            if (pix < items) {
+                const unsigned u = static_cast<unsigned>(f2bf(v[k].x)) | (static_cast<unsigned>(f2bf(v[k].y)) << 16);
+                *reinterpret_cast<uint4 *>(S + pix * PP) = uint4{u, 0u, 0u, 0u};
+                *reinterpret_cast<uint4 *>(S + pix * PP + 8) = uint4{0u, 0u, 0u, 0u};
+            }
+        }
+    } else {   // stage the input tile: pixel (sy, sx) of the tile is input pixel
         // (y0 + sy - 1, x0 + sx - 1); every load of the thread is issued
         // before the first LDS write, so that their latencies overlap
         constexpr int C8 = CPin / 8, items = SH * SW * C8, NIT = (items + 255) / 256;
@@ -214,7 +242,10 @@ k_conv3x3_tile(const bf16 *__restrict__ X,
 // values x - 1 .. x + 4 that serve the three horizontal taps.  No wave waits
 // for another until the four waves' sums are added in LDS, in wave order, so
 // that the block writes one partial (its channel block's rows of it).
-template <int NT>
+// X2 / Z2: the input / the output gradient is two fp32 channels per pixel
+// (the network's input; the loss gradient at its head), rounded to bf16 as
+// it is staged, the other 14 channel rows of the LDS buffers zero.
+template <int NT, bool X2 = false, bool Z2 = false>
 __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
                                                      const bf16 *__restrict__ dZ,
                                                      float *__restrict__ part, int B, int H, int W,
@@ -242,9 +273,29 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
         const int y0 = chunk * rows_per_wave, y1 = min(H, y0 + rows_per_wave);
         const bf16 *img = X + static_cast<long long>(b) * H * W * CPin + 16 * kc;
         const bf16 *zimg = dZ + static_cast<long long>(b) * H * W * CPout + 16 * t0;
+        const float *imgf = reinterpret_cast<const float *>(X) + static_cast<long long>(b) * H * W * 2;
+        const float *zimgf = reinterpret_cast<const float *>(dZ) + static_cast<long long>(b) * H * W * 2;
+        if constexpr (X2 || Z2) {   // the channel rows that two-channel tensors leave zero
+            for (int e = lane; e < (XS + ZS) / 8; e += 64)
+                reinterpret_cast<uint4 *>(Xs)[e] = uint4{0u, 0u, 0u, 0u};
+        }
         // input row yy: item it < 132 is column x0 - 1 + (it >> 1), channels 8 (it & 1) ..
         auto load_x = [&](int yy, uint4 (&xr)[3]) {
             const bool in = yy >= 0 && yy < H;
+            if constexpr (X2) {   // item it < 66: column x0 - 1 + it, two fp32 channels
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int it = lane + 64 * r;
+                    const int gx = x0 - 1 + it;
+                    xr[r] = uint4{0u, 0u, 0u, 0u};
+                    if (it < 66 && in && gx >= 0 && gx < W) {
+                        const float2 v = *reinterpret_cast<const float2 *>(imgf + (static_cast<long long>(yy) * W + gx) * 2);
+                        xr[r].x = __float_as_uint(v.x);
+                        xr[r].y = __float_as_uint(v.y);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int it = lane + 64 * r;
@@ -257,6 +308,17 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
         };
         auto store_x = [&](int yy, const uint4 (&xr)[3]) {
             bf16 *dst = Xs + ((yy + 3) % 3) * 16 * XP;
+            if constexpr (X2) {
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int it = lane + 64 * r;
+                    if (it < 66) {
+                        dst[it] = f2bf(__uint_as_float(xr[r].x));
+                        dst[XP + it] = f2bf(__uint_as_float(xr[r].y));
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int it = lane + 64 * r;
@@ -274,6 +336,16 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
         // output-gradient row y: item it < 32 NT is pixels x0 + 4 (it & 15) .. + 3,
         // channels 8 (it >> 4) .. (zeros past the image's edge)
         auto load_z = [&](int y, uint4 (&zr)[ZR][4]) {
+            if constexpr (Z2) {   // lane: pixel x0 + lane, two fp32 channels
+                const int px = x0 + lane;
+                zr[0][0] = uint4{0u, 0u, 0u, 0u};
+                if (px < W) {
+                    const float2 v = *reinterpret_cast<const float2 *>(zimgf + (static_cast<long long>(y) * W + px) * 2);
+                    zr[0][0].x = __float_as_uint(v.x);
+                    zr[0][0].y = __float_as_uint(v.y);
+                }
+                return;
+            }
 #pragma unroll
             for (int r = 0; r < ZR; ++r) {
                 const int it = lane + 64 * r;
@@ -288,6 +360,11 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
             }
         };
         auto store_z = [&](const uint4 (&zr)[ZR][4]) {
+            if constexpr (Z2) {
+                Zs[lane] = f2bf(__uint_as_float(zr[0][0].x));
+                Zs[64 + lane] = f2bf(__uint_as_float(zr[0][0].y));
+                return;
+            }
 #pragma unroll
             for (int r = 0; r < ZR; ++r) {
                 const int it = lane + 64 * r;
@@ -534,24 +611,13 @@ __global__ void k_up2_bwd(const bf16 *__restrict__ dS, const bf16 *__restrict__ 
     st8(dYc + pix * C + c, r);
 }
 
-// Two-channel fp32 grid (B, G, G, 2) -> bf16 input with 16 channels.
-__global__ void k_pack_input(const float *__restrict__ x, bf16 *__restrict__ X, long long npix) {
-    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    const float2 v = *reinterpret_cast<const float2 *>(x + 2 * p);
-    const unsigned u = static_cast<unsigned>(f2bf(v.x)) | (static_cast<unsigned>(f2bf(v.y)) << 16);
-    uint4 *q = reinterpret_cast<uint4 *>(X + 16 * p);
-    q[0] = uint4{u, 0u, 0u, 0u};
-    q[1] = uint4{0u, 0u, 0u, 0u};
-}
-
 // Squared error: per-block partial sums (double) and the gradient of the
-// mean, 2 (y - t) / n, into the 16-channel bf16 tensor dY (channels >= 2
-// stay zero).
+// mean, 2 (y - t) / n, into dY: two fp32 channels per pixel (the kernels
+// that read it round it to bf16 as they stage it).
 __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y,
                                              const float *__restrict__ t, long long npix,
                                              double *__restrict__ partial,
-                                             bf16 *__restrict__ dY, float scale) {
+                                             float *__restrict__ dY, float scale) {
     __shared__ double red[256];
     double s = 0.0;
     for (long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; p < npix;
@@ -560,7 +626,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ y,
         for (int c = 0; c < 2; ++c) {
             const float d = y[2 * p + c] - t[2 * p + c];
             s += static_cast<double>(d) * d;
-            dY[16 * p + c] = f2bf(scale * d);
+            dY[2 * p + c] = scale * d;
         }
     }
     red[threadIdx.x] = s;
@@ -664,7 +730,7 @@ unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) /
 // B * H * W < 2^31 (the network object checks it at creation); channels
 // padded to 16, 32 or 64.
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
-               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s) {
+               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, bool in2, hipStream_t s) {
     const long long tiles = static_cast<long long>(B) * ((H + 3) / 4) * ((W + 63) / 64);
     // fewer than 1024 pixel tiles: the output channel tiles are split over
     // blocks (each stages the same input) so that more CUs take part
@@ -684,7 +750,14 @@ void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, 
         else if (CPin == 32) RAS_TILE(NT, 2, F32); \
         else RAS_TILE(NT, 4, F32);            \
     } while (0)
-    if (out_f32) RAS_TILE_KC(1, true);         // one column tile: the head
+    if (in2) {                                 // two fp32 input channels (16 once staged)
+        if (nt == 1) hipLaunchKernelGGL((k_conv3x3_tile<1, 1, false, true>), grid, blk, 0, s, x, w, Y, g, B, H,
+                                        W, relu ? 1 : 0, acc ? 1 : 0, creal, ntot);
+        else if (nt == 2) hipLaunchKernelGGL((k_conv3x3_tile<2, 1, false, true>), grid, blk, 0, s, x, w, Y, g,
+                                             B, H, W, relu ? 1 : 0, acc ? 1 : 0, creal, ntot);
+        else hipLaunchKernelGGL((k_conv3x3_tile<4, 1, false, true>), grid, blk, 0, s, x, w, Y, g, B, H, W,
+                                relu ? 1 : 0, acc ? 1 : 0, creal, ntot);
+    } else if (out_f32) RAS_TILE_KC(1, true);  // one column tile: the head
     else if (nt == 1) RAS_TILE_KC(1, false);
     else if (nt == 2) RAS_TILE_KC(2, false);
     else RAS_TILE_KC(4, false);
@@ -720,7 +793,7 @@ int warm_wgrad_strip_blocks_max(int B, int W) {
 }
 
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
-                int W, int CPin, int CPout, hipStream_t s) {
+                int W, int CPin, int CPout, bool x2, bool z2, hipStream_t s) {
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
     const int n = 9 * CPin * CPout;
     // one wave per strip, at most two output tiles a wave
@@ -728,7 +801,21 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
     int rpw = 0, nch = 0;
     const int nb = warm_wgrad_strip_blocks(B, H, W, KC, NT, NZ, &rpw, &nch);
     const dim3 grid(nb, KC, NZ);
-    if (NT == 1)
+    // two fp32 channels: the input (16 channels once staged) or, with 16
+    // output channels, the output gradient
+    if (x2 && z2)
+        hipLaunchKernelGGL((k_wgrad_strip<1, true, true>), grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin,
+                           CPout, rpw, nch);
+    else if (x2 && NT == 1)
+        hipLaunchKernelGGL((k_wgrad_strip<1, true, false>), grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin,
+                           CPout, rpw, nch);
+    else if (x2)
+        hipLaunchKernelGGL((k_wgrad_strip<2, true, false>), grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin,
+                           CPout, rpw, nch);
+    else if (z2)
+        hipLaunchKernelGGL((k_wgrad_strip<1, false, true>), grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin,
+                           CPout, rpw, nch);
+    else if (NT == 1)
         hipLaunchKernelGGL(k_wgrad_strip<1>, grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin, CPout, rpw,
                            nch);
     else
@@ -760,15 +847,11 @@ void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int 
     hipLaunchKernelGGL(k_up2_bwd, dim3(blocks(n, 256)), dim3(256), 0, s, static_cast<const bf16 *>(dS),
                        static_cast<const bf16 *>(gate), static_cast<bf16 *>(dYc), B, H, W, C);
 }
-void warm_pack_input(const float *x, void *X, long long npix, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_input, dim3(blocks(npix, 256)), dim3(256), 0, s, x,
-                       static_cast<bf16 *>(X), npix);
-}
 void warm_mse(const float *y, const float *t, long long npix, double *partial, int nblk, void *dY,
               double *loss, hipStream_t s) {
     const float scale = static_cast<float>(2.0 / (2.0 * npix));
     hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, y, t, npix, partial,
-                       static_cast<bf16 *>(dY), scale);
+                       static_cast<float *>(dY), scale);
     hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / (2.0 * npix),
                        loss);
 }

@@ -31,17 +31,16 @@
 namespace raspml {
 
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
-               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, hipStream_t s);
+               int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, bool in2, hipStream_t s);
 int warm_wgrad_strip_blocks_max(int B, int W);
 void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
-                int W, int CPin, int CPout, hipStream_t s);
+                int W, int CPin, int CPout, bool x2, bool z2, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
 void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
                    int W, int C, hipStream_t s);
 void warm_up_add(const void *Yc, const void *E, void *S, int B, int H, int W, int C, hipStream_t s);
 void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int W, int C,
                  hipStream_t s);
-void warm_pack_input(const float *x, void *X, long long npix, hipStream_t s);
 void warm_mse(const float *y, const float *t, long long npix, double *partial, int nblk, void *dY,
               double *loss, hipStream_t s);
 void warm_adam(float *w, float *m, float *v, const float *g, int cin, int cout, int cip, int cop,
@@ -69,8 +68,9 @@ struct ras_pml_wsnet {
     int cin[kLayers] = {}, cout[kLayers] = {}, lvl[kLayers] = {};
     float *w[kLayers] = {}, *m[kLayers] = {}, *v[kLayers] = {}, *g[kLayers] = {};
     void *wf[kLayers] = {}, *wb[kLayers] = {};
-    void *xin = nullptr, *e[5] = {}, *p[5] = {}, *s[4] = {}, *d[4] = {};
-    void *gy = nullptr, *gp[5] = {}, *gs[4] = {};
+    void *e[5] = {}, *p[5] = {}, *s[4] = {}, *d[4] = {};
+    void *gp[5] = {}, *gs[4] = {};
+    float *gy = nullptr;                // the loss gradient: two fp32 channels per pixel
     void *dz = nullptr;                 // the current layer's output gradient, ReLU-masked
     float *y = nullptr, *stage = nullptr;
     float *part = nullptr, *psum = nullptr;   // weight-gradient partials, slice sums
@@ -102,13 +102,13 @@ namespace raspml {
 int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream_t st) {
     const int G = N->grid;
     const int C[5] = {cpad(N->ch[0]), cpad(N->ch[1]), cpad(N->ch[2]), cpad(N->ch[3]), cpad(N->ch[4])};
-    warm_pack_input(x, N->xin, static_cast<long long>(B) * G * G, st);
-    warm_conv(N->xin, N->wf[0], N->e[0], nullptr, B, G, G, 16, C[0], true, false, false, 0, st);
+    // the first layer reads the two fp32 input channels itself
+    warm_conv(x, N->wf[0], N->e[0], nullptr, B, G, G, 16, C[0], true, false, false, 0, true, st);
     for (int l = 1; l <= 4; ++l) {
         const int S = N->side(l);
         warm_pool(N->e[l - 1], N->p[l], B, 2 * S, 2 * S, C[l - 1], st);
         warm_conv(N->p[l], N->wf[l], N->e[l], nullptr, B, S, S, C[l - 1], C[l], true, false, false, 0,
-                  st);
+                  false, st);
     }
     // decoder: layer index 5 + (3 - l) for level l = 3..0
     const int din[4] = {C[0], C[1], C[2], C[3]};    // channels of s_l
@@ -118,10 +118,10 @@ int wsnet_forward(ras_pml_wsnet *N, const float *x, int B, float *out, hipStream
         const int S = N->side(l), L = 5 + (3 - l);
         warm_up_add(prev, N->e[l], N->s[l], B, S, S, din[l], st);
         warm_conv(N->s[l], N->wf[L], N->d[l], nullptr, B, S, S, din[l], dout[l], true, false, false, 0,
-                  st);
+                  false, st);
         prev = N->d[l];
     }
-    warm_conv(N->d[0], N->wf[9], out, nullptr, B, G, G, C[0], 16, false, false, true, 2, st);
+    warm_conv(N->d[0], N->wf[9], out, nullptr, B, G, G, C[0], 16, false, false, true, 2, false, st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -136,28 +136,28 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     // tensor it belongs to, into dz, which the next layer's weight gradient
     // and input gradient then read.
     // head (no ReLU): gradient of d0
-    warm_wgrad(N->d[0], N->gy, N->part, N->psum, N->g[9], B, G, G, C[0], 16, st);
-    warm_conv(N->gy, N->wb[9], N->dz, N->d[0], B, G, G, 16, C[0], false, false, false, 0, st);
+    warm_wgrad(N->d[0], N->gy, N->part, N->psum, N->g[9], B, G, G, C[0], 16, false, true, st);
+    warm_conv(N->gy, N->wb[9], N->dz, N->d[0], B, G, G, 16, C[0], false, false, false, 0, true, st);
     // decoder, level 0 up to 3
     const int din[4] = {C[0], C[1], C[2], C[3]};
     const int dout[4] = {C[0], C[0], C[1], C[2]};
     for (int l = 0; l <= 3; ++l) {
         const int S = N->side(l), L = 5 + (3 - l);
-        warm_wgrad(N->s[l], N->dz, N->part, N->psum, N->g[L], B, S, S, din[l], dout[l], st);
+        warm_wgrad(N->s[l], N->dz, N->part, N->psum, N->g[L], B, S, S, din[l], dout[l], false, false, st);
         warm_conv(N->dz, N->wb[L], N->gs[l], nullptr, B, S, S, dout[l], din[l], false, false, false, 0,
-                  st);
+                  false, st);
         const void *below = l < 3 ? N->d[l + 1] : N->e[4];   // the tensor one level down
         warm_up_bwd(N->gs[l], below, N->dz, B, S, S, din[l], st);
     }
     // encoder, level 4 down to 1; the skip gradient of s_{l-1} joins e_{l-1}
     for (int l = 4; l >= 1; --l) {
         const int S = N->side(l);
-        warm_wgrad(N->p[l], N->dz, N->part, N->psum, N->g[l], B, S, S, C[l - 1], C[l], st);
+        warm_wgrad(N->p[l], N->dz, N->part, N->psum, N->g[l], B, S, S, C[l - 1], C[l], false, false, st);
         warm_conv(N->dz, N->wb[l], N->gp[l], nullptr, B, S, S, C[l], C[l - 1], false, false, false, 0,
-                  st);
+                  false, st);
         warm_pool_bwd(N->gp[l], N->gs[l - 1], N->e[l - 1], N->dz, B, 2 * S, 2 * S, C[l - 1], st);
     }
-    warm_wgrad(N->xin, N->dz, N->part, N->psum, N->g[0], B, G, G, 16, C[0], st);
+    warm_wgrad(x, N->dz, N->part, N->psum, N->g[0], B, G, G, 16, C[0], true, false, st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -232,7 +232,7 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
         const size_t S = static_cast<size_t>(grid >> l);
         return N->alloc(ptr, static_cast<size_t>(batch_max) * S * S * cpad(C) * 2);
     };
-    bool ok = act(&N->xin, 0, 16) && act(&N->gy, 0, 16);
+    bool ok = true;
     for (int l = 0; l < 5 && ok; ++l) ok = act(&N->e[l], l, c[l]);
     for (int l = 1; l < 5 && ok; ++l) ok = act(&N->p[l], l, c[l - 1]) && act(&N->gp[l], l, c[l - 1]);
     const int dch[4] = {c[0], c[0], c[1], c[2]};
@@ -248,6 +248,7 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     ok = ok && N->alloc(&N->dz, static_cast<size_t>(batch_max) * dz_max * 2);
     const size_t npix = static_cast<size_t>(batch_max) * grid * grid;
     ok = ok && N->alloc(&N->y, npix * 2 * 4) && N->alloc(&N->stage, npix * 2 * 4) &&
+         N->alloc(&N->gy, npix * 2 * 4) &&
          N->alloc(&N->part, part_max * 4) && N->alloc(&N->psum, 32 * np_max * 4) &&
          N->alloc(&N->lpart, kMseBlocks * 8) &&
          N->alloc(&N->loss, 8);
