@@ -1,7 +1,9 @@
 // Learned warm start: the convolutional encoder-decoder's kernels.
 //
 // Tensors are NHWC bfloat16 with the channel count padded to 16, 32 or 64
-// (padding channels hold zeros); accumulation is fp32.  Every 3 x 3
+// (padding channels hold zeros), except the network's two-channel ends (its
+// input, its output and the loss gradient), which are fp32 pairs;
+// accumulation is fp32.  Every 3 x 3
 // convolution (zero padding, no bias) is an implicit GEMM on the matrix
 // cores, v_mfma_f32_16x16x16_bf16:
 //   forward / input gradient: rows = output channels (NT tiles of 16),
@@ -45,10 +47,10 @@ __device__ __forceinline__ int xcd_run(int i, int n) {
 
 // out[p][co] (+)= sum_{tap, ci} X[p + off(tap)][ci] W[tap][ci][co].
 // A block computes a tile of 4 rows x 64 pixels (wave w: row w, four tiles
-// of 16 pixels; rows and 16-pixel tiles past the image's edge are skipped,
-// pixels past it are not written) and first loads the 6 x 66 input pixels
-// that tile reads (zeros outside the image) into LDS with 16-byte loads,
-// channels of a pixel contiguous.  The matrix-core product is
+// of 16 pixels; rows past the image's edge are skipped, pixels past it are
+// computed on the staged zeros and not written) and first loads the 6 x 66
+// input pixels that tile reads (zeros outside the image) into LDS with
+// 16-byte loads, channels of a pixel contiguous.  The matrix-core product is
 // D[co][p] = W^T X^T: A is the weight block (lane: output channel
 // lane & 15, input channels 4 (lane >> 4) .. + 3), B the input (lane: pixel
 // lane & 15, the same four input channels, one 8-byte LDS read), so a tap's
@@ -68,11 +70,8 @@ __device__ __forceinline__ int xcd_run(int i, int n) {
 template <int NT, int KC, bool OUT_F32, bool IN2 = false>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(NT == 4 ? 1 : KC == 1 ? (NT == 1 ? 8 : 6) : KC == 2 ? 5 : 2))) void
-k_conv3x3_tile(const bf16 *__restrict__ X,
-                                                      const bf16 *__restrict__ Wp,
-                                                      void *__restrict__ Y,
-                                                      const bf16 *__restrict__ gate, int B, int H,
-                                                      int W, int relu, int acc, int creal, int ntot) {
+k_conv3x3_tile(const bf16 *__restrict__ X, const bf16 *__restrict__ Wp, void *__restrict__ Y,
+               const bf16 *__restrict__ gate, int B, int H, int W, int relu, int acc, int creal, int ntot) {
     constexpr int CPin = 16 * KC;
     constexpr int PP = KC == 1 ? CPin : CPin + 8;          // LDS pixel pitch
     const int CPout = 16 * ntot, t0 = blockIdx.y * NT;     // this block's column tiles
