@@ -105,6 +105,10 @@ def test_full_resolution_kernels_match_oracle():
     gd = as_dict(g, CH)
     for name in rp.WS_LAYERS:
         assert relerr(gd[name], gref[name]) <= 6e-2, (name, relerr(gd[name], gref[name]))
+    # the partial sums are added in a fixed order: the same inputs give the
+    # same loss and gradient bit for bit
+    loss2, g2 = net.gradient(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    assert loss2 == loss and np.array_equal(g2, g)
 
 
 @pytest.mark.parametrize("grid,B,channels", [(48, 2, (40, 48, 56, 64, 64)),
