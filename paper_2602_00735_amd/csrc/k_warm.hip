@@ -461,28 +461,45 @@ __global__ __launch_bounds__(256) void k_wgrad_strip(const bf16 *__restrict__ X,
     }
 }
 
-// g[idx] = sum over blocks of part[blk][idx], in two stages with a fixed
-// order (deterministic): slice s of the blocks, [s per, (s + 1) per), is
-// summed in block order into tmp[s][idx]; then the slices in slice order.
-// Consecutive threads take consecutive idx, so every load is coalesced.
+// g[idx] = sum over blocks of part[blk][idx] for every layer of a table, in
+// two stages with a fixed order (deterministic): slice s of a layer's
+// blocks, [s per, (s + 1) per), is summed in block order into tmp[s][idx];
+// then the slices in slice order.  One thread per (layer, idx) of the flat
+// list, layer L holding off[L] .. off[L + 1] - 1; consecutive threads take
+// consecutive idx, so every load is coalesced.
 constexpr int kSumSlices = 32;
-__global__ __launch_bounds__(256) void k_sum_slices(const float *__restrict__ part, int nblk,
-                                                    int n, int per, float *__restrict__ tmp) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n) return;
-    const int k0 = blockIdx.y * per, k1 = min(k0 + per, nblk);
+constexpr int kSumLayers = 10;
+struct SumLayers {
+    const float *part[kSumLayers];
+    float *tmp[kSumLayers], *g[kSumLayers];
+    int n[kSumLayers], nblk[kSumLayers], per[kSumLayers];
+    int off[kSumLayers + 1];
+    int nl;
+};
+__device__ __forceinline__ int sum_layer(const SumLayers &P, int f) {
+    int L = 0;
+    while (f >= P.off[L + 1]) ++L;
+    return L;
+}
+__global__ __launch_bounds__(256) void k_sum_slices(const SumLayers P) {
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= P.off[P.nl]) return;
+    const int L = sum_layer(P, f), idx = f - P.off[L], n = P.n[L];
+    const int k0 = blockIdx.y * P.per[L], k1 = min(k0 + P.per[L], P.nblk[L]);
+    const float *part = P.part[L];
     float s = 0.f;
     for (int k = k0; k < k1; ++k) s += part[static_cast<long long>(k) * n + idx];
-    tmp[static_cast<long long>(blockIdx.y) * n + idx] = s;
+    P.tmp[L][static_cast<long long>(blockIdx.y) * n + idx] = s;
 }
-__global__ __launch_bounds__(256) void k_sum_tmp(const float *__restrict__ tmp, int n,
-                                                 float *__restrict__ g) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n) return;
+__global__ __launch_bounds__(256) void k_sum_tmp(const SumLayers P) {
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= P.off[P.nl]) return;
+    const int L = sum_layer(P, f), idx = f - P.off[L], n = P.n[L];
+    const float *tmp = P.tmp[L];
     float s = 0.f;
 #pragma unroll
     for (int k = 0; k < kSumSlices; ++k) s += tmp[static_cast<long long>(k) * n + idx];
-    g[idx] = s;
+    P.g[L][idx] = s;
 }
 
 // Eight bfloat16 values (16 bytes) <-> floats, for the elementwise kernels:
@@ -653,21 +670,46 @@ __global__ __launch_bounds__(256) void k_sum_double(const double *__restrict__ p
     if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// Adam on the fp32 master weights W[tap][ci][co] (real channel counts) with
-// the gradient in the padded layout g[tap][cip][cop].
-__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ g, int cin, int cout, int cip, int cop, float lr,
-                       float b1, float b2, float c1, float c2, float eps) {
-    const int n = 9 * cin * cout;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+// Adam on every layer's master weights at once, each updated weight also
+// written into the two packed bf16 layouts below (its forward and its
+// input-gradient entry; the padding entries stay zero from creation).  One
+// thread per real weight of the flat list, layer L holding off[L] ..
+// off[L + 1] - 1: W[tap][ci][co] (real channel counts), the gradient in the
+// padded layout g[tap][cip][cop]; the packing is k_pack_weights'.
+constexpr int kMaxLayers = 10;
+struct AdamLayers {
+    float *w[kMaxLayers], *m[kMaxLayers], *v[kMaxLayers];
+    const float *g[kMaxLayers];
+    bf16 *fwd[kMaxLayers], *bwd[kMaxLayers];
+    int cin[kMaxLayers], cout[kMaxLayers], cip[kMaxLayers], cop[kMaxLayers];
+    int off[kMaxLayers + 1];
+    int nl;
+};
+__global__ void k_adam_pack(const AdamLayers P, float lr, float b1, float b2, float c1, float c2,
+                            float eps) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= P.off[P.nl]) return;
+    int L = 0;
+    while (f >= P.off[L + 1]) ++L;
+    const int idx = f - P.off[L];
+    const int cin = P.cin[L], cout = P.cout[L], cip = P.cip[L], cop = P.cop[L];
     const int co = idx % cout, ci = (idx / cout) % cin, tap = idx / (cout * cin);
-    const float gr = g[(tap * cip + ci) * cop + co];
-    const float mm = b1 * m[idx] + (1.f - b1) * gr;
-    const float vv = b2 * v[idx] + (1.f - b2) * gr * gr;
-    m[idx] = mm;
-    v[idx] = vv;
-    w[idx] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    const float gr = P.g[L][(tap * cip + ci) * cop + co];
+    const float mm = b1 * P.m[L][idx] + (1.f - b1) * gr;
+    const float vv = b2 * P.v[L][idx] + (1.f - b2) * gr * gr;
+    P.m[L][idx] = mm;
+    P.v[L][idx] = vv;
+    const float w = P.w[L][idx] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    P.w[L][idx] = w;
+    const bf16 h = f2bf(w);
+    {   // forward block (tap, kc, t), entry [co mod 16][ci mod 16]
+        const int KC = cip >> 4, NT = cop >> 4;
+        P.fwd[L][((tap * KC + (ci >> 4)) * NT + (co >> 4)) * 256 + (co & 15) * 16 + (ci & 15)] = h;
+    }
+    {   // input-gradient block (8 - tap, co / 16, ci / 16), entry [ci mod 16][co mod 16]
+        const int KC = cop >> 4, NT = cip >> 4;
+        P.bwd[L][(((8 - tap) * KC + (co >> 4)) * NT + (ci >> 4)) * 256 + (ci & 15) * 16 + (co & 15)] = h;
+    }
 }
 
 // Packs the master weights into the two B-operand layouts:
@@ -764,12 +806,24 @@ void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, 
 #undef RAS_TILE
 }
 
-// g = sum of the nblk partial gradients (n values each), tmp: kSumSlices * n.
-void sum_partials(const float *part, int nblk, int n, float *tmp, float *g, hipStream_t s) {
-    const int per = (nblk + kSumSlices - 1) / kSumSlices;
-    hipLaunchKernelGGL(k_sum_slices, dim3(blocks(n, 256), kSumSlices), dim3(256), 0, s, part, nblk, n,
-                       per, tmp);
-    hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(n, 256)), dim3(256), 0, s, tmp, n, g);
+// g[L] = sum of layer L's nblk[L] partial gradients (n[L] values each) for
+// the nl layers (nl <= 10), tmp[L]: kSumSlices * n[L]; two launches in all.
+void warm_sum_layers(int nl, const float *const *part, const int *nblk, const int *n, float *const *tmp,
+                     float *const *g, hipStream_t s) {
+    SumLayers P{};
+    P.nl = nl;
+    P.off[0] = 0;
+    for (int L = 0; L < nl; ++L) {
+        P.part[L] = part[L];
+        P.tmp[L] = tmp[L];
+        P.g[L] = g[L];
+        P.n[L] = n[L];
+        P.nblk[L] = nblk[L];
+        P.per[L] = (nblk[L] + kSumSlices - 1) / kSumSlices;
+        P.off[L + 1] = P.off[L] + n[L];
+    }
+    hipLaunchKernelGGL(k_sum_slices, dim3(blocks(P.off[nl], 256), kSumSlices), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_sum_tmp, dim3(blocks(P.off[nl], 256)), dim3(256), 0, s, P);
 }
 
 // Strips and row chunks of k_wgrad_strip: about 4096 waves over the input
@@ -786,15 +840,20 @@ int warm_wgrad_strip_blocks(int B, int H, int W, int KC, int NT, int NZ, int *ro
     *nchunk = (H + rpw - 1) / rpw;
     return (B * *nchunk * nstrip + 3) / 4;
 }
-// The most blocks (in x) it gives for any batch up to B.
-int warm_wgrad_strip_blocks_max(int B, int W) {
-    return (std::max(4096, B * ((W + 63) / 64)) + 3) / 4 + 1;
+// The most blocks (in x) it gives for any batch up to B, for a layer of
+// CPin -> CPout channels (B nchunk nstrip items never exceed the larger of
+// the wave target and B nstrip).
+int warm_wgrad_strip_blocks_max(int B, int W, int CPin, int CPout) {
+    const int KC = CPin / 16, NT = CPout == 16 ? 1 : 2, NZ = CPout / (16 * NT);
+    const int target = std::max(1, (NT == 2 ? 2048 : 4096) / (KC * NZ));
+    return (std::max(target, B * ((W + 63) / 64)) + 3) / 4 + 1;
 }
 
-void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
-                int W, int CPin, int CPout, bool x2, bool z2, hipStream_t s) {
+// The partial weight gradients of one layer into part; returns their count
+// (the blocks), which warm_sum_layers adds.
+int warm_wgrad(const void *X, const void *dZ, float *part, int B, int H, int W, int CPin, int CPout,
+               bool x2, bool z2, hipStream_t s) {
     const bf16 *x = static_cast<const bf16 *>(X), *dz = static_cast<const bf16 *>(dZ);
-    const int n = 9 * CPin * CPout;
     // one wave per strip, at most two output tiles a wave
     const int KC = CPin / 16, NT = CPout == 16 ? 1 : 2, NZ = CPout / (16 * NT);
     int rpw = 0, nch = 0;
@@ -820,7 +879,7 @@ void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g
     else
         hipLaunchKernelGGL(k_wgrad_strip<2>, grid, dim3(256), 0, s, x, dz, part, B, H, W, CPin, CPout, rpw,
                            nch);
-    sum_partials(part, nb, n, tmp, g, s);
+    return nb;
 }
 
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s) {
@@ -854,10 +913,29 @@ void warm_mse(const float *y, const float *t, long long npix, double *partial, i
     hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, s, partial, nblk, 1.0 / (2.0 * npix),
                        loss);
 }
-void warm_adam(float *w, float *m, float *v, const float *g, int cin, int cout, int cip, int cop,
-               float lr, float b1, float b2, float c1, float c2, float eps, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3(blocks(9 * cin * cout, 256)), dim3(256), 0, s, w, m, v, g, cin,
-                       cout, cip, cop, lr, b1, b2, c1, c2, eps);
+// Adam and the packing of the nl layers in one launch (nl <= 10).
+void warm_adam_pack(int nl, float *const *w, float *const *m, float *const *v, float *const *g,
+                    void *const *fwd, void *const *bwd, const int *cin, const int *cout, const int *cip,
+                    const int *cop, float lr, float b1, float b2, float c1, float c2, float eps,
+                    hipStream_t s) {
+    AdamLayers P{};
+    P.nl = nl;
+    P.off[0] = 0;
+    for (int L = 0; L < nl; ++L) {
+        P.w[L] = w[L];
+        P.m[L] = m[L];
+        P.v[L] = v[L];
+        P.g[L] = g[L];
+        P.fwd[L] = static_cast<bf16 *>(fwd[L]);
+        P.bwd[L] = static_cast<bf16 *>(bwd[L]);
+        P.cin[L] = cin[L];
+        P.cout[L] = cout[L];
+        P.cip[L] = cip[L];
+        P.cop[L] = cop[L];
+        P.off[L + 1] = P.off[L] + 9 * cin[L] * cout[L];
+    }
+    hipLaunchKernelGGL(k_adam_pack, dim3(blocks(P.off[nl], 256)), dim3(256), 0, s, P, lr, b1, b2, c1, c2,
+                       eps);
 }
 void warm_pack_weights(const float *w, int cin, int cout, int cip, int cop, void *fwd, void *bwd,
                        hipStream_t s) {

@@ -32,9 +32,11 @@ namespace raspml {
 
 void warm_conv(const void *X, const void *Wp, void *Y, const void *gate, int B, int H, int W,
                int CPin, int CPout, bool relu, bool acc, bool out_f32, int creal, bool in2, hipStream_t s);
-int warm_wgrad_strip_blocks_max(int B, int W);
-void warm_wgrad(const void *X, const void *dZ, float *part, float *tmp, float *g, int B, int H,
-                int W, int CPin, int CPout, bool x2, bool z2, hipStream_t s);
+int warm_wgrad_strip_blocks_max(int B, int W, int CPin, int CPout);
+int warm_wgrad(const void *X, const void *dZ, float *part, int B, int H, int W, int CPin, int CPout,
+               bool x2, bool z2, hipStream_t s);
+void warm_sum_layers(int nl, const float *const *part, const int *nblk, const int *n, float *const *tmp,
+                     float *const *g, hipStream_t s);
 void warm_pool(const void *X, void *Y, int B, int H, int W, int C, hipStream_t s);
 void warm_pool_bwd(const void *dY, const void *add, const void *gate, void *dX, int B, int H,
                    int W, int C, hipStream_t s);
@@ -43,8 +45,10 @@ void warm_up_bwd(const void *dS, const void *gate, void *dYc, int B, int H, int 
                  hipStream_t s);
 void warm_mse(const float *y, const float *t, long long npix, double *partial, int nblk, void *dY,
               double *loss, hipStream_t s);
-void warm_adam(float *w, float *m, float *v, const float *g, int cin, int cout, int cip, int cop,
-               float lr, float b1, float b2, float c1, float c2, float eps, hipStream_t s);
+void warm_adam_pack(int nl, float *const *w, float *const *m, float *const *v, float *const *g,
+                    void *const *fwd, void *const *bwd, const int *cin, const int *cout, const int *cip,
+                    const int *cop, float lr, float b1, float b2, float c1, float c2, float eps,
+                    hipStream_t s);
 void warm_pack_weights(const float *w, int cin, int cout, int cip, int cop, void *fwd, void *bwd,
                        hipStream_t s);
 
@@ -73,7 +77,9 @@ struct ras_pml_wsnet {
     float *gy = nullptr;                // the loss gradient: two fp32 channels per pixel
     void *dz = nullptr;                 // the current layer's output gradient, ReLU-masked
     float *y = nullptr, *stage = nullptr;
-    float *part = nullptr, *psum = nullptr;   // weight-gradient partials, slice sums
+    // each layer's weight-gradient partials and slice sums, added for all
+    // layers at once at the end of the backward pass
+    float *part[kLayers] = {}, *psum[kLayers] = {};
     double *lpart = nullptr, *loss = nullptr;
     long long step = 0;
     std::vector<void *> allocs;
@@ -136,14 +142,15 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     // tensor it belongs to, into dz, which the next layer's weight gradient
     // and input gradient then read.
     // head (no ReLU): gradient of d0
-    warm_wgrad(N->d[0], N->gy, N->part, N->psum, N->g[9], B, G, G, C[0], 16, false, true, st);
+    int nblk[kLayers], npar[kLayers];
+    nblk[9] = warm_wgrad(N->d[0], N->gy, N->part[9], B, G, G, C[0], 16, false, true, st);
     warm_conv(N->gy, N->wb[9], N->dz, N->d[0], B, G, G, 16, C[0], false, false, false, 0, true, st);
     // decoder, level 0 up to 3
     const int din[4] = {C[0], C[1], C[2], C[3]};
     const int dout[4] = {C[0], C[0], C[1], C[2]};
     for (int l = 0; l <= 3; ++l) {
         const int S = N->side(l), L = 5 + (3 - l);
-        warm_wgrad(N->s[l], N->dz, N->part, N->psum, N->g[L], B, S, S, din[l], dout[l], false, false, st);
+        nblk[L] = warm_wgrad(N->s[l], N->dz, N->part[L], B, S, S, din[l], dout[l], false, false, st);
         warm_conv(N->dz, N->wb[L], N->gs[l], nullptr, B, S, S, dout[l], din[l], false, false, false, 0,
                   false, st);
         const void *below = l < 3 ? N->d[l + 1] : N->e[4];   // the tensor one level down
@@ -152,12 +159,15 @@ int wsnet_gradient(ras_pml_wsnet *N, const float *x, const float *t, int B, hipS
     // encoder, level 4 down to 1; the skip gradient of s_{l-1} joins e_{l-1}
     for (int l = 4; l >= 1; --l) {
         const int S = N->side(l);
-        warm_wgrad(N->p[l], N->dz, N->part, N->psum, N->g[l], B, S, S, C[l - 1], C[l], false, false, st);
+        nblk[l] = warm_wgrad(N->p[l], N->dz, N->part[l], B, S, S, C[l - 1], C[l], false, false, st);
         warm_conv(N->dz, N->wb[l], N->gp[l], nullptr, B, S, S, C[l], C[l - 1], false, false, false, 0,
                   false, st);
         warm_pool_bwd(N->gp[l], N->gs[l - 1], N->e[l - 1], N->dz, B, 2 * S, 2 * S, C[l - 1], st);
     }
-    warm_wgrad(x, N->dz, N->part, N->psum, N->g[0], B, G, G, 16, C[0], true, false, st);
+    nblk[0] = warm_wgrad(x, N->dz, N->part[0], B, G, G, 16, C[0], true, false, st);
+    // every layer's partials added in a fixed order: two launches
+    for (int L = 0; L < kLayers; ++L) npar[L] = 9 * N->cip(L) * N->cop(L);
+    warm_sum_layers(kLayers, N->part, nblk, npar, N->psum, N->g, st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -166,11 +176,14 @@ int wsnet_adam(ras_pml_wsnet *N, float lr, hipStream_t st) {
     N->step += 1;
     const float c1 = static_cast<float>(1.0 - std::pow(0.9, static_cast<double>(N->step)));
     const float c2 = static_cast<float>(1.0 - std::pow(0.999, static_cast<double>(N->step)));
+    // every layer's Adam step and the packing of its updated weights: one launch
+    int cip[kLayers], cop[kLayers];
     for (int L = 0; L < kLayers; ++L) {
-        warm_adam(N->w[L], N->m[L], N->v[L], N->g[L], N->cin[L], N->cout[L], N->cip(L), N->cop(L), lr,
-                  b1, b2, c1, c2, eps, st);
-        warm_pack_weights(N->w[L], N->cin[L], N->cout[L], N->cip(L), N->cop(L), N->wf[L], N->wb[L], st);
+        cip[L] = N->cip(L);
+        cop[L] = N->cop(L);
     }
+    warm_adam_pack(kLayers, N->w, N->m, N->v, N->g, N->wf, N->wb, N->cin, N->cout, cip, cop, lr, b1, b2,
+                   c1, c2, eps, st);
     return hipGetLastError() == hipSuccess ? RAS_OK : RAS_EHIP;
 }
 
@@ -213,20 +226,20 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     const int cin[kLayers] = {2, c[0], c[1], c[2], c[3], c[4], c[2], c[1], c[0], c[0]};
     const int cout[kLayers] = {c[0], c[1], c[2], c[3], c[4], c[2], c[1], c[0], c[0], 2};
     const int lvl[kLayers] = {0, 1, 2, 3, 4, 3, 2, 1, 0, 0};
-    size_t part_max = 0, np_max = 0;
     for (int L = 0; L < kLayers; ++L) {
         N->cin[L] = cin[L];
         N->cout[L] = cout[L];
         N->lvl[L] = lvl[L];
         const size_t nw = 9 * static_cast<size_t>(cin[L]) * cout[L];
         const size_t np = 9 * static_cast<size_t>(N->cip(L)) * N->cop(L);
-        np_max = std::max(np_max, np);
         if (!N->alloc(&N->w[L], nw * 4) || !N->alloc(&N->m[L], nw * 4) || !N->alloc(&N->v[L], nw * 4) ||
             !N->alloc(&N->g[L], np * 4) || !N->alloc(&N->wf[L], np * 2) || !N->alloc(&N->wb[L], np * 2))
             return RAS_ENOMEM;
-        // the weight gradient's partial blocks for any batch up to batch_max
+        // the layer's weight-gradient partial blocks for any batch up to
+        // batch_max, and its slice sums
         const int S = grid >> lvl[L];
-        part_max = std::max(part_max, static_cast<size_t>(warm_wgrad_strip_blocks_max(batch_max, S)) * np);
+        const size_t nbmax = warm_wgrad_strip_blocks_max(batch_max, S, N->cip(L), N->cop(L));
+        if (!N->alloc(&N->part[L], nbmax * np * 4) || !N->alloc(&N->psum[L], 32 * np * 4)) return RAS_ENOMEM;
     }
     auto act = [&](void **ptr, int l, int C) {
         const size_t S = static_cast<size_t>(grid >> l);
@@ -249,7 +262,7 @@ int ras_pml_wsnet_create(int grid, const int channels[5], int batch_max, ras_pml
     const size_t npix = static_cast<size_t>(batch_max) * grid * grid;
     ok = ok && N->alloc(&N->y, npix * 2 * 4) && N->alloc(&N->stage, npix * 2 * 4) &&
          N->alloc(&N->gy, npix * 2 * 4) &&
-         N->alloc(&N->part, part_max * 4) && N->alloc(&N->psum, 32 * np_max * 4) &&
+
          N->alloc(&N->lpart, kMseBlocks * 8) &&
          N->alloc(&N->loss, 8);
     if (!ok) return RAS_ENOMEM;
