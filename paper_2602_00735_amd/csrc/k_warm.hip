@@ -487,8 +487,17 @@ __global__ __launch_bounds__(256) void k_sum_slices(const SumLayers P) {
     const int L = sum_layer(P, f), idx = f - P.off[L], n = P.n[L];
     const int k0 = blockIdx.y * P.per[L], k1 = min(k0 + P.per[L], P.nblk[L]);
     const float *part = P.part[L];
+    // eight loads in flight, then their sum in block order
     float s = 0.f;
-    for (int k = k0; k < k1; ++k) s += part[static_cast<long long>(k) * n + idx];
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = part[static_cast<long long>(k + e) * n + idx];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s += v[e];
+    }
+    for (; k < k1; ++k) s += part[static_cast<long long>(k) * n + idx];
     P.tmp[L][static_cast<long long>(blockIdx.y) * n + idx] = s;
 }
 __global__ __launch_bounds__(256) void k_sum_tmp(const SumLayers P) {
