@@ -424,6 +424,16 @@ int build(ras_pml_handle *H, hipStream_t st) {
             s.fac_off = static_cast<long long>(fac);
             s.vec_off = vec;
             s.loc_off = loc;
+            // local index of node (i, j): (j - jy0) nx + (i - ix0) along x, else
+            // (i - ix0) ny + (j - jy0)
+            s.pou_sx = s.xfast ? 1 : s.ny;
+            s.pou_sy = s.xfast ? s.nx : 1;
+            s.pou_off = static_cast<int>(vec) - (s.xfast ? s.jy0 * s.nx + s.ix0 : s.ix0 * s.ny + s.jy0);
+            s.pou_pad_ = 0;
+            if (vec + s.npad >= (1LL << 30)) {
+                H->last_error = "too many local unknowns (2^30)";
+                return RAS_EINVAL;
+            }
             if (s.W & 1) {            // the pair-layout solve relies on even W
                 H->last_error = "internal: odd factor column length";
                 return RAS_EINVAL;

@@ -2,6 +2,7 @@
 // C ABI.  Plain structs: the device reads them as they are laid out here.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -48,7 +49,12 @@ struct DevSub {
     long long fac_off;  // first L entry (elements); D^{-1} follows npad*W later
     long long vec_off;  // first entry of this subdomain's padded local vectors
     long long loc_off;  // first entry in the unpadded back-to-back layout
+    // the PoU sum's view, one 16-byte load: node (i, j) of the problem is
+    // entry pou_off + i pou_sx + j pou_sy of the padded local vectors
+    int pou_off, pou_sx, pou_sy, pou_pad_;
 };
+static_assert(sizeof(DevSub) % 16 == 0 && offsetof(DevSub, pou_off) % 16 == 0,
+              "DevSub: the PoU sum reads pou_off .. pou_pad_ as one 16-byte load");
 
 // One problem, as the kernels see it.
 struct DevProb {

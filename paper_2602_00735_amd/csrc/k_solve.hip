@@ -332,6 +332,40 @@ __global__ void k_pou_sum(const DevProb *__restrict__ probs, const DevSub *__res
     const int ex = P.pou_x + i, ey = P.pou_y + j;
     const int nxc = pcnt[ex], nyc = pcnt[ey];
     double zr = 0.0, zi = 0.0;
+    if (nxc <= 2 && nyc <= 2) {
+        // at most two subdomains along each axis (every node when the chunks
+        // are wider than the overlap): the four descriptors and values are
+        // loaded before the first FMA (a missing second subdomain repeats the
+        // first, whose value is then not added), the sum in the loop's order
+        const int p0 = pchunk[ex * kMaxPou], q0 = pchunk[ey * kMaxPou];
+        const int p1 = nxc > 1 ? pchunk[ex * kMaxPou + 1] : p0;
+        const int q1 = nyc > 1 ? pchunk[ey * kMaxPou + 1] : q0;
+        const double wx0 = pw[ex * kMaxPou], wx1 = pw[ex * kMaxPou + 1];
+        const double wy0 = pw[ey * kMaxPou], wy1 = pw[ey * kMaxPou + 1];
+        const DevSub *sb = subs + P.sub_first;
+        const int4 s00 = *reinterpret_cast<const int4 *>(&sb[q0 * P.Px + p0].pou_off);
+        const int4 s01 = *reinterpret_cast<const int4 *>(&sb[q0 * P.Px + p1].pou_off);
+        const int4 s10 = *reinterpret_cast<const int4 *>(&sb[q1 * P.Px + p0].pou_off);
+        const int4 s11 = *reinterpret_cast<const int4 *>(&sb[q1 * P.Px + p1].pou_off);
+        const cplx<T> x00 = xout[s00.x + i * s00.y + j * s00.z];
+        const cplx<T> x01 = xout[s01.x + i * s01.y + j * s01.z];
+        const cplx<T> x10 = xout[s10.x + i * s10.y + j * s10.z];
+        const cplx<T> x11 = xout[s11.x + i * s11.y + j * s11.z];
+        zr = fma(wx0 * wy0, static_cast<double>(x00.re), zr);
+        zi = fma(wx0 * wy0, static_cast<double>(x00.im), zi);
+        if (nxc > 1) {
+            zr = fma(wx1 * wy0, static_cast<double>(x01.re), zr);
+            zi = fma(wx1 * wy0, static_cast<double>(x01.im), zi);
+        }
+        if (nyc > 1) {
+            zr = fma(wx0 * wy1, static_cast<double>(x10.re), zr);
+            zi = fma(wx0 * wy1, static_cast<double>(x10.im), zi);
+            if (nxc > 1) {
+                zr = fma(wx1 * wy1, static_cast<double>(x11.re), zr);
+                zi = fma(wx1 * wy1, static_cast<double>(x11.im), zi);
+            }
+        }
+    } else
     for (int b = 0; b < nyc; ++b) {
         const int q = pchunk[ey * kMaxPou + b];
         const double wy = pw[ey * kMaxPou + b];
