@@ -388,12 +388,19 @@ __device__ __forceinline__ void barrier_arrive(unsigned long long *bar, unsigned
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned long long epoch,
-                                             int *err, bool &failed) {
+// The barrier in two halves, so that a block can issue loads that do not
+// depend on it between its arrival and its wait.
+__device__ __forceinline__ void grid_arrive(unsigned long long *bar, unsigned long long epoch) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_s_waitcnt(0);          // this block's published values are complete
         barrier_arrive(bar, epoch);
+    }
+}
+
+__device__ __forceinline__ void grid_wait(unsigned long long *bar, unsigned long long epoch,
+                                          int *err, bool &failed) {
+    if (threadIdx.x == 0) {
         unsigned long long *grel = bar + kBarStride * (blockIdx.x / kBarGroup + 1) + 16;
         if (!failed && !spin_until(grel, epoch)) {
             failed = true;
@@ -401,6 +408,12 @@ __device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned l
         }
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void grid_barrier(unsigned long long *bar, unsigned long long epoch,
+                                             int *err, bool &failed) {
+    grid_arrive(bar, epoch);
+    grid_wait(bar, epoch, err, failed);
 }
 
 // Block sum for the fused step: each wave reduces its lanes with DPP moves
@@ -434,8 +447,10 @@ __device__ cplx<double> problem_sum(const double2 *__restrict__ part, const Arno
 //   for i = 0..j: h_ij = <v_i, w>; w -= h_ij v_i   (modified Gram-Schmidt)
 //   h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}.
 // Each block keeps its slice of w (and the current v_i) in registers, so w is
-// never re-read; j + 2 grid barriers separate the reductions.  Problems not
-// in the cycle skip the arithmetic but take part in every barrier.
+// never re-read; j + 2 grid barriers separate the reductions.  With v_i kept
+// (KEEPV), the block loads v_{i+1} between its arrival at barrier i and its
+// wait there, so the load overlaps the wait for the other blocks.  Problems
+// not in the cycle skip the arithmetic but take part in every barrier.
 //
 // The step index j is the step count kp of the problems still in the cycle
 // (they all take their steps together), and the barrier epoch reached so far
@@ -503,22 +518,34 @@ __device__ __forceinline__ void arnoldi_step(
     }
     unsigned long long ep = 0;            // barriers passed in this launch
     bool failed = false;                  // (thread 0) a poll of this launch ran out
+    // KEEPV: v holds v_i at the top of projection i, vnext receives v_{i+1}
+    cplx<double> v[KEEPV ? E : 1], vnext[KEEPV ? E : 1];
+    auto load_v = [&](const double2 *vi, cplx<double> *dst) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int o = threadIdx.x + q * kRedThreads;
+            dst[q] = (on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0};
+        }
+    };
+    if constexpr (KEEPV) load_v(V, v);
     for (int i = 0; i <= j; ++i) {
         const double2 *vi = V + static_cast<long long>(i) * ntot;
-        cplx<double> v[KEEPV ? E : 1];
         cplx<double> acc{0, 0};
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int o = threadIdx.x + q * kRedThreads;
-            const cplx<double> vq = (on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0};
-            if (KEEPV) v[q] = vq;
+            const cplx<double> vq =
+                KEEPV ? v[q] : ((on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0});
             acc = cdotacc(acc, vq, w[q]);
         }
         double2 *part = part2 + static_cast<long long>(i & 1) * nblocks;
         const cplx<double> bs = block_sum_dpp(acc, sh4, par);
         if (threadIdx.x == 0) put_agent(part + blockIdx.x, bs);
         ++ep;
-        grid_barrier(bar, epoch0 + ep, err, failed);
+        grid_arrive(bar, epoch0 + ep);
+        if constexpr (KEEPV)
+            if (i < j) load_v(vi + ntot, vnext);
+        grid_wait(bar, epoch0 + ep, err, failed);
         const cplx<double> h = problem_sum(part, B, sh4, par);
 #pragma unroll
         for (int q = 0; q < E; ++q) {
@@ -528,6 +555,7 @@ __device__ __forceinline__ void arnoldi_step(
             const cplx<double> vq =
                 KEEPV ? v[q] : ((on && o < B.n) ? ld(vi, B.first + o) : cplx<double>{0, 0});
             w[q] = cfms(w[q], h, vq);
+            if (KEEPV) v[q] = vnext[q];
         }
         if (on && blockIdx.x == B.first_blk && threadIdx.x == 0) st(Hp, col + i, h);
     }
