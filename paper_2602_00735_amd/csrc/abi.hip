@@ -36,6 +36,11 @@ void launch_band_ldlt_mfma(bool, int, bool, const DevSub *, const int *, int, co
 void launch_band_solve(bool, bool, int, const DevProb *, const DevSub *, const int *, int,
                        const int *, const SolveSrc &, const void *, void *, void *,
                        const SolveDispatch &, hipStream_t);
+long long ldlt_wide_scratch(int K);
+void launch_band_ldlt_wide(bool, int, const DevSub *, const int *, int, const double2 *, void *,
+                           void *, int *, hipStream_t);
+void launch_band_solve_wide(bool, const DevProb *, const DevSub *, const int *, int, const int *,
+                            const SolveSrc &, const void *, void *, void *, hipStream_t);
 void launch_pou_sum(bool, const DevProb *, int, long long, const DevSub *, const int *,
                     const int *, const int *, const double *, const void *, const SumDst &, bool,
                     hipStream_t);
@@ -88,6 +93,13 @@ struct ras_pml_handle {
     // (LU_*), largest W} per group
     std::vector<int> lu_order;
     std::vector<std::array<int, 5>> lu_groups;
+    // wide subdomains (W > kMaxW): {K = W / 64, first in lu_order, count},
+    // factorised one group after another through the scratch d_wscratch
+    std::vector<std::array<int, 3>> wide_groups;
+    void *d_wscratch = nullptr;
+    // order: the nsub_reg subdomains with W <= kMaxW (largest first, widest
+    // maxW_reg), then the nsub_wide wide ones
+    int nsub_reg = 0, nsub_wide = 0, maxW_reg = 0;
     bool solve_deep = true;    // band-solve prefetch depth variant
     bool solve_queue = false;  // band-solve dispatch: persistent waves and a work queue
     int solve_waves = 0;       // waves of the persistent band solve (one per SIMD)
@@ -313,7 +325,7 @@ ras_pml_handle::~ras_pml_handle() {
                     d_F,     d_ybuf,  d_xout,  d_status, d_V,    d_Z,      d_r,        d_H,
                     d_g,     d_sn,    d_y,     d_cs,   d_hist,   d_ks,     d_active,   d_partials,
                     d_redout, d_counters, d_ablocks, d_part2, d_bar, d_err, d_rs, d_rhist,
-                    d_queue, d_epoch};
+                    d_queue, d_epoch, d_wscratch};
     bool any = false;
     for (void *p : ptrs) any = any || p != nullptr;
     if (any) idle_device(device);
@@ -371,6 +383,9 @@ int factorise(ras_pml_handle *H, hipStream_t st) {
             launch_band_ldlt_mfma(H->fp64, g[0], g[3] == LU_MFMA_CAPPED, H->d_subs,
                                   H->d_lu_order + g[1], g[2], H->d_lst, H->d_F, H->d_status, s);
     }
+    for (const auto &g : H->wide_groups)
+        launch_band_ldlt_wide(H->fp64, g[0], H->d_subs, H->d_lu_order + g[1], g[2], H->d_lst,
+                              H->d_F, H->d_wscratch, H->d_status, st);
     hipError_t e = hipGetLastError();
     if (aux && e == hipSuccess) {
         e = hipEventRecord(join, aux);
@@ -459,19 +474,39 @@ int build(ras_pml_handle *H, hipStream_t st) {
     H->nloc = loc;
     H->fac_elems = fac;
     H->csize = H->fp64 ? 16 : 8;
-    // largest subdomains first (longest processing time first)
+    // largest subdomains first (longest processing time first), those of
+    // the register-ring kernels (W <= kMaxW) ahead of the wide ones
+    auto wide = [&](int j) { return H->hsubs[j].W > kMaxW; };
     H->order.resize(H->nsub);
     std::iota(H->order.begin(), H->order.end(), 0);
     std::stable_sort(H->order.begin(), H->order.end(),
                      [&](int a, int b) { return H->hsubs[a].n > H->hsubs[b].n; });
+    std::stable_partition(H->order.begin(), H->order.end(), [&](int j) { return !wide(j); });
+    H->nsub_wide = static_cast<int>(std::count_if(H->order.begin(), H->order.end(), wide));
+    H->nsub_reg = H->nsub - H->nsub_wide;
+    H->maxW_reg = 0;
+    for (int i = 0; i < H->nsub_reg; ++i)
+        H->maxW_reg = std::max(H->maxW_reg, H->hsubs[H->order[i]].W);
+    H->lu_groups.clear();
+    H->wide_groups.clear();
     {
         H->lu_order = H->order;
-        auto tiles = [&](int j) { return ldlt_mfma_tiles(H->hsubs[j].W); };
-        std::stable_sort(H->lu_order.begin(), H->lu_order.end(),
+        // window classes of the register kernel, widest first; then the wide
+        // subdomains by W
+        auto tiles = [&](int j) { return wide(j) ? -H->hsubs[j].W : ldlt_mfma_tiles(H->hsubs[j].W); };
+        std::stable_sort(H->lu_order.begin(), H->lu_order.begin() + H->nsub_reg,
                          [&](int a, int b) { return tiles(a) > tiles(b); });
-        for (int i = 0; i < H->nsub;) {
+        std::stable_sort(H->lu_order.begin() + H->nsub_reg, H->lu_order.end(),
+                         [&](int a, int b) { return H->hsubs[a].W > H->hsubs[b].W; });
+        for (int i = H->nsub_reg; i < H->nsub;) {
+            int e = i;
+            while (e < H->nsub && H->hsubs[H->lu_order[e]].W == H->hsubs[H->lu_order[i]].W) ++e;
+            H->wide_groups.push_back({H->hsubs[H->lu_order[i]].W / 64, i, e - i});
+            i = e;
+        }
+        for (int i = 0; i < H->nsub_reg;) {
             int e = i, wmax = 0;
-            while (e < H->nsub && tiles(H->lu_order[e]) == tiles(H->lu_order[i]))
+            while (e < H->nsub_reg && tiles(H->lu_order[e]) == tiles(H->lu_order[i]))
                 wmax = std::max(wmax, H->hsubs[H->lu_order[e++]].W);
             const int nt = tiles(H->lu_order[i]);
             H->lu_groups.push_back(
@@ -510,6 +545,12 @@ int build(ras_pml_handle *H, hipStream_t st) {
     RCHK(dalloc(H, &H->d_xout, H->csize * H->nvec));
     RCHK(dalloc(H, &H->d_status, sizeof(int) * H->nsub));
     RCHK(dalloc(H, &H->d_queue, sizeof(unsigned int) * 2));
+    {
+        long long wsc = 0;
+        for (const auto &g : H->wide_groups)
+            wsc = std::max(wsc, static_cast<long long>(g[2]) * ldlt_wide_scratch(g[0]));
+        if (wsc > 0) RCHK(dalloc(H, &H->d_wscratch, H->csize * static_cast<size_t>(wsc)));
+    }
     HCHK(H, hipMemsetAsync(H->d_queue, 0, sizeof(unsigned int) * 2, st));
     {
         int cus = 0;
@@ -694,13 +735,23 @@ SolveDispatch solve_dispatch(const ras_pml_handle *H) {
     return SolveDispatch{H->solve_queue ? H->d_queue : nullptr, H->solve_waves};
 }
 
+// Band solves of every subdomain: the register-ring kernel for those with
+// W <= kMaxW, then the wide kernel for the others.
+void launch_solves(const ras_pml_handle *H, bool deep, const int *active, const SolveSrc &src,
+                   const SolveDispatch &dsp, hipStream_t st) {
+    if (H->nsub_reg > 0)
+        launch_band_solve(H->fp64, deep, H->maxW_reg, H->d_probs, H->d_subs, H->d_order,
+                          H->nsub_reg, active, src, H->d_F, H->d_ybuf, H->d_xout, dsp, st);
+    if (H->nsub_wide > 0)
+        launch_band_solve_wide(H->fp64, H->d_probs, H->d_subs, H->d_order + H->nsub_reg,
+                               H->nsub_wide, active, src, H->d_F, H->d_ybuf, H->d_xout, st);
+}
+
 int do_apply(ras_pml_handle *H, const double2 *v, double2 *z, const int *active, hipStream_t st,
              bool acc = false, bool timed = true) {
     {
         Timer t(H, C_SOLVE, st, timed);
-        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
-                          H->nsub, active, SolveSrc{v, nullptr, 0}, H->d_F, H->d_ybuf, H->d_xout,
-                          solve_dispatch(H), st);
+        launch_solves(H, H->solve_deep, active, SolveSrc{v, nullptr, 0}, solve_dispatch(H), st);
     }
     HCHK(H, hipGetLastError());
     {
@@ -741,9 +792,8 @@ int enqueue_step(ras_pml_handle *H, int j, int m, hipStream_t st, bool timed) {
     const int P = H->nprob;
     {
         Timer t(H, C_SOLVE, st, timed);
-        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
-                          H->nsub, H->d_active, SolveSrc{H->d_V, H->d_ks, n}, H->d_F, H->d_ybuf,
-                          H->d_xout, solve_dispatch(H), st);
+        launch_solves(H, H->solve_deep, H->d_active, SolveSrc{H->d_V, H->d_ks, n},
+                      solve_dispatch(H), st);
     }
     HCHK(H, hipGetLastError());
     {
@@ -1552,9 +1602,8 @@ int ras_pml_local_solve(ras_pml_t H, const void *v, void *xloc, void *stream) {
     hipStream_t st = as_stream(stream);
     {
         Timer t(H, C_SOLVE, st);
-        launch_band_solve(H->fp64, H->solve_deep, H->maxW, H->d_probs, H->d_subs, H->d_order,
-                          H->nsub, nullptr, SolveSrc{static_cast<const double2 *>(v), nullptr, 0},
-                          H->d_F, H->d_ybuf, H->d_xout, solve_dispatch(H), st);
+        launch_solves(H, H->solve_deep, nullptr,
+                      SolveSrc{static_cast<const double2 *>(v), nullptr, 0}, solve_dispatch(H), st);
     }
     HCHK(H, hipGetLastError());
     if (xloc == nullptr) return RAS_OK;        // the solves alone (timing)
@@ -1840,16 +1889,14 @@ int ras_pml_autotune(ras_pml_t H, const char *cache_path, void *stream) {
         // prefetch depth x dispatch (the persistent queue only matters with
         // more subdomains than SIMDs)
         float t[2][2] = {{1e30f, 1e30f}, {1e30f, 1e30f}};
-        const int nq = H->nsub > H->solve_waves ? 2 : 1;
+        const int nq = H->nsub_reg > H->solve_waves ? 2 : 1;
         if (hipMemsetAsync(v, 0, sizeof(double2) * H->ntot, st) == hipSuccess) {
             for (int q = 0; q < nq; ++q)
                 for (int deep = 0; deep < 2; ++deep)
                     t[q][deep] = timeit([&] {
-                        launch_band_solve(H->fp64, deep != 0, H->maxW, H->d_probs, H->d_subs,
-                                          H->d_order, H->nsub, nullptr, SolveSrc{v, nullptr, 0},
-                                          H->d_F, H->d_ybuf, H->d_xout,
-                                          SolveDispatch{q ? H->d_queue : nullptr, H->solve_waves},
-                                          st);
+                        launch_solves(H, deep != 0, nullptr, SolveSrc{v, nullptr, 0},
+                                      SolveDispatch{q ? H->d_queue : nullptr, H->solve_waves},
+                                      st);
                     }, 3);
             int bq = 0, bd = 1;
             for (int q = 0; q < nq; ++q)

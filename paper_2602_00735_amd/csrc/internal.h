@@ -11,8 +11,11 @@
 
 namespace raspml {
 
-// Largest factor column length W = n_fast + 2 the kernels are built for.
+// Factor column length W: n_fast + 2 rounded up to even up to kMaxW (the
+// register-ring kernels), else rounded up to a multiple of 64 up to
+// kMaxWideW (the wide kernels: 3 to 6 registers of 64 slots per lane).
 constexpr int kMaxW = 128;
+constexpr int kMaxWideW = 384;
 // Largest number of chunks whose partition-of-unity weight is non-zero at
 // one mesh node along one axis.
 constexpr int kMaxPou = 4;
@@ -35,7 +38,8 @@ struct DevSub {
     int npad;       // n rounded up to kPad
     int nf;         // unknowns along the fast axis
     int W;          // factor column length: half-bandwidth + 1 = nf + 2, rounded
-                    // up to even (the extra slot holds zeros)
+                    // up to even (the extra slot holds zeros); above kMaxW
+                    // rounded up to a multiple of 64 (the wide kernels)
     int xfast;      // 1: x is the fast axis
     int ix0, nx;    // first unknown node index and count along x
     int jy0, ny;    // same along y

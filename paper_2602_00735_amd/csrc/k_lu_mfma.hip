@@ -413,7 +413,262 @@ void launch_t(int NT, bool occ, const DevSub *subs, const int *order, int count,
     }
 }
 
+// ------------------------------------------------------------ wide bands
+// W = 64 K with K = 3..6 (bands 129..383: the subdomains of Section 4's own
+// experiments, 300-cell cores with their overlap and PML).  The same
+// blocked LDL^T in 16-column panels, but the window (M = W + 16 rows and
+// columns, NT = 4 K + 1 tiles per side, NT (NT + 1) / 2 tiles on and below
+// the diagonal: 650 KB in complex64 at K = 6) no longer fits the register
+// file: it lives in a global scratch of the workgroup's own (L2-resident),
+// as the same diagonal rings.  Tile u of the scratch holds element
+// (ti + RS r, tj) of lane l at u * 256 + 64 r + l, the matrix-core
+// accumulator layout.  Per panel:
+//   1. logical tile column 0 is read into LDS;
+//   2. one wave factorises the 16 x 16 diagonal block (pivot broadcast with
+//      v_readlane, as in the register kernel); every other row of the panel
+//      is then one thread's 16-step forward substitution against it (the
+//      pre-scaled block and the reciprocals from LDS);
+//   3. L (column copy in slot order, row copy) and D^{-1} are written out,
+//      in the layout of the other kernels with W the column length;
+//   4. each wave takes its share of the tiles with J >= 1 (C -= L_I (L_J D)^T
+//      on the matrix cores: loaded from the scratch, 16 products, stored
+//      back), and the tiles with J == 0 become their diagonal's entering
+//      tile, straight from the stencil.
+// Rows M - 1 .. of a window start at panel 0 as the stencil's couplings;
+// rows past the matrix end are identity rows.
+
+// A_j(r, q) as band_entry, loading only where the stencil couples r and q.
+template <typename T>
+__device__ __forceinline__ cplx<T> band_entry_sparse(const double2 *__restrict__ lst, int n,
+                                                     int nf, int r, int q) {
+    const int hi = max(r, q), lo = min(r, q), d = hi - lo;
+    const bool wrap = (hi % nf) == 0;
+    const bool in = hi < n;
+    const bool coupled = in && (d == 0 || d == nf || ((d == 1 || d == nf + 1) && !wrap));
+    if (!coupled) return cplx<T>{(!in && d == 0) ? T(1) : T(0), T(0)};
+    const int e = d == 0 ? 0 : d == 1 ? 1 : d == nf ? 2 : 3;
+    const double2 v = lst[4LL * lo + e];
+    return cplx<T>{static_cast<T>(v.x), static_cast<T>(v.y)};
+}
+
+// First tile of diagonal d in the rings (diagonal e has NT - e tiles).
+template <int NT>
+__device__ __forceinline__ int ring_base(int d) { return d * NT - d * (d - 1) / 2; }
+
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict__ subs,
+                                                        const int *__restrict__ order,
+                                                        const double2 *__restrict__ lst_all,
+                                                        cplx<T> *__restrict__ F,
+                                                        cplx<T> *__restrict__ scratch,
+                                                        int *__restrict__ status) {
+    typedef typename Prec<T>::v4 v4;
+    constexpr int W = 64 * K;
+    constexpr int NT = 4 * K + 1;
+    constexpr int M = 16 * NT;
+    constexpr int NL = NT * (NT + 1) / 2;
+    constexpr int RS = Prec<T>::rs;
+    __shared__ cplx<T> LP[M * kLdsStride];    // the panel; then L (zero on and above the diagonal)
+    __shared__ cplx<T> WD[16 * kLdsStride];   // diagonal block, pre-scaled values (L D)
+    __shared__ cplx<T> DV[16], IV[16];        // d_k and 1 / d_k of the panel's columns
+    __shared__ int TQ[NL];                    // ring tile u: diagonal d (high half), slot q
+
+    const int sid = order[blockIdx.x];
+    const DevSub S = subs[sid];
+    const int nf = S.nf, n = S.n, npad = S.npad;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2 *lst = lst_all + 4 * S.loc_off;
+    cplx<T> *L = F + S.fac_off;
+    cplx<T> *Rw = L + static_cast<long long>(npad) * W;   // rows of L, last first
+    cplx<T> *Dinv = Rw + static_cast<long long>(npad) * W;
+    cplx<T> *win = scratch + static_cast<long long>(blockIdx.x) * NL * 256;
+    const int ti = Prec<T>::row0(lane), tj = lane & 15;
+    const cplx<T> zero{T(0), T(0)};
+
+    // Row r < W of R has no columns before 0 at positions r+1 .. W-1.
+#pragma unroll 1
+    for (int i = tid; i < W * W; i += 256) {
+        const int r = i / W, q = i % W;
+        if (q > r && r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + q] = zero;
+    }
+    for (int d = 0, u = 0; d < NT; ++d)
+        for (int q = 0; q < NT - d; ++q, ++u)
+            if (u % 256 == tid) TQ[u] = (d << 16) | q;
+    __syncthreads();
+    // window at panel 0: ring tile (d, q) holds rows 16 (q + d).., columns 16 q..
+#pragma unroll 1
+    for (int u = wave; u < NL; u += 4) {
+        const int d = TQ[u] >> 16, q = TQ[u] & 0xffff;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            win[u * 256 + 64 * r + lane] =
+                band_entry_sparse<T>(lst, n, nf, 16 * (q + d) + ti + RS * r, 16 * q + tj);
+    }
+    __syncthreads();
+
+    int bad = -1;
+#pragma unroll 1
+    for (int c0 = 0; c0 < npad; c0 += 16) {
+        const int p = c0 >> 4;
+        // 1. logical tile column 0 (ring slot p mod (NT - I) of diagonal I)
+#pragma unroll 1
+        for (int I = wave; I < NT; I += 4) {
+            const cplx<T> *tile = win + (ring_base<NT>(I) + p % (NT - I)) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                LP[(16 * I + ti + RS * r) * kLdsStride + tj] = tile[64 * r + lane];
+        }
+        __syncthreads();
+        // 2a. the diagonal block, rows 0..15 in lanes 0..15 of wave 0
+        if (wave == 0) {
+            const int row = min(lane, 15);
+            cplx<T> x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = LP[row * kLdsStride + k];
+            const int cd = c0 + row;            // |A_j(cd, cd)| for the pivot test
+            const double2 a = lst[4LL * min(cd, n - 1)];
+            const cplx<T> ad0{static_cast<T>(a.x), static_cast<T>(a.y)};
+            const T dg = cd < n ? sqrt(cabs2(ad0)) : T(1);
+            T pa = T(0);
+            cplx<T> dinv = zero;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const cplx<T> w = x[k];
+                const cplx<T> d = readlane(w, k);
+                const T m2 = cabs2(d);
+                pa = writelane(pa, m2, k);
+                const T rm = Prec<T>::rcp(m2);
+                const cplx<T> inv{d.re * rm, -d.im * rm};
+                dinv = writelane(dinv, inv, k);
+                const cplx<T> l = cmul(w, inv);
+#pragma unroll
+                for (int j = k + 1; j < 16; ++j) x[j] = cfms(x[j], l, readlane(w, j));
+                if (lane < 16) {
+                    LP[lane * kLdsStride + k] = csel(lane > k, l, zero);
+                    WD[lane * kLdsStride + k] = w;
+                }
+                if (lane == k) {
+                    DV[k] = d;
+                    IV[k] = inv;
+                }
+            }
+            if (lane < 16) Dinv[c0 + lane] = dinv;
+            const T ad = sqrt(pa);
+            const bool fail = lane < 16 && !(ad > Prec<T>::tol * dg && ad < T(1e30));
+            const unsigned long long fm = __ballot(fail);
+            if (bad < 0 && fm != 0) bad = c0 + __builtin_ctzll(fm);
+        }
+        __syncthreads();
+        // 2b. rows 16 .. M-1
+#pragma unroll 1
+        for (int r = 16 + tid; r < M; r += 256) {
+            cplx<T> x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = LP[r * kLdsStride + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const cplx<T> l = cmul(x[k], IV[k]);
+#pragma unroll
+                for (int j = k + 1; j < 16; ++j) x[j] = cfms(x[j], l, WD[j * kLdsStride + k]);
+                LP[r * kLdsStride + k] = l;
+            }
+        }
+        __syncthreads();
+        // 3. columns c0 .. c0+15 of L (slot order: row r at position r mod W,
+        //    the column's own position 0) and their entries in the rows of L
+        {
+            const int sl0 = c0 % W;              // sl0 + 15 < W (W is a multiple of 64)
+#pragma unroll 1
+            for (int i = tid; i < 16 * W; i += 256) {
+                const int k = i / W, pos = i - (i / W) * W;
+                const int c = c0 + k, sl = sl0 + k;
+                const int r = c + (pos >= sl ? pos - sl : pos - sl + W);
+                L[static_cast<long long>(c) * W + pos] =
+                    r == c ? zero : LP[(r - c0) * kLdsStride + k];
+            }
+            const int k = tid & 15, c = c0 + k, slk = sl0 + k;
+            if (tid < 16) Rw[static_cast<long long>(npad - 1 - c) * W + slk] = zero;
+#pragma unroll 1
+            for (int r = c0 + 1 + (tid >> 4); r < c0 + W + 15; r += 16)
+                if (r > c && r < c + W && r < npad)
+                    Rw[static_cast<long long>(npad - 1 - r) * W + slk] =
+                        LP[(r - c0) * kLdsStride + k];
+        }
+        // 4. rank-16 update of the tiles with J >= 1; the tiles with J == 0
+        //    leave and their slots take the entering tiles
+#pragma unroll 1
+        for (int u = wave; u < NL; u += 4) {
+            const int d = TQ[u] >> 16, q = TQ[u] & 0xffff;
+            const int len = NT - d;
+            const int J = (q - p % len + len) % len;
+            cplx<T> *tile = win + u * 256;
+            if (J >= 1) {
+                const int I = J + d;
+                v4 cre, cim;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const cplx<T> v = tile[64 * r + lane];
+                    cre[r] = v.re;
+                    cim[r] = v.im;
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int col = 4 * kk + (lane >> 4);
+                    const cplx<T> l = LP[(16 * I + tj) * kLdsStride + col];
+                    const cplx<T> w = cmul(LP[(16 * J + tj) * kLdsStride + col], DV[col]);
+                    cre = Prec<T>::mfma(-l.re, w.re, cre);
+                    cre = Prec<T>::mfma(l.im, w.im, cre);
+                    cim = Prec<T>::mfma(-l.re, w.im, cim);
+                    cim = Prec<T>::mfma(-l.im, w.re, cim);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tile[64 * r + lane] = cplx<T>{cre[r], cim[r]};
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    tile[64 * r + lane] = band_entry_sparse<T>(
+                        lst, n, nf, 16 * (p + NT) + ti + RS * r, 16 * (p + NT - d) + tj);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) status[sid] = bad;
+}
+
+template <typename T>
+void launch_wide_t(int K, const DevSub *subs, const int *order, int count, const double2 *lst,
+                   void *F, void *scratch, int *status, hipStream_t st) {
+    cplx<T> *Fc = static_cast<cplx<T> *>(F);
+    cplx<T> *sc = static_cast<cplx<T> *>(scratch);
+    switch (K) {
+        case 3: hipLaunchKernelGGL((k_band_ldlt_wide<T, 3>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 4: hipLaunchKernelGGL((k_band_ldlt_wide<T, 4>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 5: hipLaunchKernelGGL((k_band_ldlt_wide<T, 5>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
+        default: hipLaunchKernelGGL((k_band_ldlt_wide<T, 6>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
+    }
+}
+
 }  // namespace
+
+// Scratch elements (complex values) per workgroup of the wide factorisation
+// for W = 64 K.
+long long ldlt_wide_scratch(int K) {
+    const long long NT = 4 * K + 1;
+    return NT * (NT + 1) / 2 * 256;
+}
+
+// count subdomains order[0 .. count) that all have W == 64 K (K = 3..6);
+// scratch: count * ldlt_wide_scratch(K) complex values of the factor
+// precision.
+void launch_band_ldlt_wide(bool fp64, int K, const DevSub *subs, const int *order, int count,
+                           const double2 *lst, void *F, void *scratch, int *status,
+                           hipStream_t st) {
+    if (fp64)
+        launch_wide_t<double>(K, subs, order, count, lst, F, scratch, status, st);
+    else
+        launch_wide_t<float>(K, subs, order, count, lst, F, scratch, status, st);
+}
 
 // Window tiles per side for a factor column length W (at most 128).
 int ldlt_mfma_tiles(int W) { return (W + 15 + 15) / 16; }

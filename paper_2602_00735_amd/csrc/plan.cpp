@@ -208,10 +208,11 @@ int plan_problem(double k, double h, const int grid[2], const int subdomains[2],
             s.xfast = s.nx <= s.ny ? 1 : 0;
             s.nf = s.xfast ? s.nx : s.ny;
             s.W = (s.nf + 3) & ~1;    // nf + 2, rounded up to even (one zero slot)
-            if (s.W > kMaxW) {
+            if (s.W > kMaxW) s.W = (s.nf + 2 + 63) / 64 * 64;    // the wide kernels' ring
+            if (s.W > kMaxWideW) {
                 std::snprintf(buf, sizeof buf,
                               "subdomain band %d exceeds the supported maximum %d; use more subdomains",
-                              s.nf + 1, kMaxW - 1);
+                              s.nf + 1, kMaxWideW - 1);
                 err = buf;
                 return RAS_ENOTSUP;
             }

@@ -80,6 +80,24 @@ def test_plan_rejects_bad_parameters(L, args, status):
     assert e.value.status == status
 
 
+def test_wide_band_columns_are_multiples_of_64(L):
+    """Bands above 127 take the wide kernels: W = n_fast + 2 rounded up to a
+    multiple of 64, up to 384 (Section 4's own subdomains, 300-cell cores
+    with their overlap and PML, have n_fast of about 330..370)."""
+    o = rp.default_opts(global_pml=6)
+    for n_int, nf, W in ((115, 126, 128), (116, 127, 192), (194, 205, 256), (254, 265, 320),
+                         (340, 351, 384), (370, 381, 384)):
+        d = rp.ras_pml_plan(40.0, 1 / n_int, (n_int, n_int), (1, 1), 0, 0, o)
+        assert (d[0][1], d[0][2]) == (nf, W), (n_int, d[0][1], d[0][2])
+    with pytest.raises(rp.RasPmlError) as e:
+        rp.ras_pml_plan(40.0, 1 / 372, (372, 372), (1, 1), 0, 0, o)      # n_fast 383: W 385
+    assert e.value.status == rp.RAS_ENOTSUP
+    # the paper's Table 4 covering at k = 600 (16 subdomains, pml 16, ovlp 5,
+    # global PML of three wavelengths): every band fits
+    d = rp.ras_pml_plan(600.0, 1 / 1200, (1200, 1200), (4, 4), 5, 16, rp.default_opts(global_pml=38))
+    assert max(x[2] for x in d) == 384 and min(x[2] for x in d) >= 192
+
+
 def test_setup_validation_runs_before_any_device_work(L):
     out = ctypes.c_void_p(123)
     rc = L.ras_pml_setup(20.0, 1 / 41, rp._i2((40, 40)), rp._i2((2, 2)), 6, 6, None, None,
