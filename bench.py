@@ -91,6 +91,14 @@ def main():
                          "subdomain boundary conditions (Tables 1/2 set-up) and the growth of "
                          "iterations and time with k (Tables 3/4 set-up); one JSON line per run")
     ap.add_argument("--sweep-max-k", type=float, default=1280.0)
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="only run Section 4's own covering: grid (2k)^2, N = (k/150)^2 "
+                         "subdomains with 300-cell cores, widths from the width rule, a global "
+                         "PML of three wavelengths, the smoothed point source, rtol 1e-10, "
+                         "at most 500 iterations: Tables 1/2 (C_kappa = 3/8, three subdomain "
+                         "conditions, Richardson and GMRES) and Tables 3/4 (C_kappa = 1/2, "
+                         "Richardson, setup and solve seconds); one JSON line per run")
+    ap.add_argument("--paper-max-k", type=float, default=2400.0)
     ap.add_argument("--warmstart", action="store_true",
                     help="only run the learned warm start at k = 320, h = 1/640, 16x16 subdomains: "
                          "solve --ws-train seeded problems, train the encoder-decoder on the "
@@ -129,6 +137,9 @@ def main():
                           "dispatches": 3}))
         return
 
+    if args.paper_tables:
+        paper_tables(args.paper_max_k)
+        return
     if args.sweep:
         sweep(args.sweep_max_k)
         return
@@ -495,6 +506,77 @@ def sweep(max_k):
         r.update(sweep="growth", variant="RAS-PML-Imp",
                  total_per_k=round((r["setup_s"] + r["solve_s"]) / k, 6))
         print(json.dumps(r), flush=True)
+
+
+def paper_tables(max_k):
+    """Section 4's covering on one GPU: k = 300 ... max_k, grid (2k)^2 (12
+    points per wavelength), P = k/150 subdomains per side (300-cell cores of
+    the interior grid; the covering divides the grid with its global PML),
+    overlap and PML from the width rule, a global PML of three wavelengths,
+    g = 10 k x^3, the smoothed point source, rtol 1e-10, at most 500
+    iterations, mixed precision.  Subdomain bands of 333..373: the wide
+    kernels.
+      - "tables12": C_delta = 1/6, C_kappa = 3/8; RAS-PML-Imp, RAS-PML-Drch
+        and RAS-Imp; Richardson and GMRES(100) (GMRES up to k = 1200, whose
+        Krylov basis still fits beside the factors).
+      - "table4": C_delta = 1/6, C_kappa = 1/2; RAS-PML-Imp Richardson;
+        setup and solve seconds."""
+    import torch
+    import paper_2602_00735_amd as rp
+    from paper_2602_00735_amd import inputs
+    torch.cuda.set_device(0)
+    ks = [k for k in (300.0, 600.0, 1200.0, 2400.0) if k <= max_k]
+
+    def run(k, bc, pml, c_kappa, solver):
+        n = int(round(2 * k))
+        h = 1.0 / n
+        P = int(round(k / 150))
+        G = int(math.floor(3 * 2 * math.pi / k / h + 1e-9))
+        o = rp.default_opts(global_pml=G, bc=bc, precision=rp.RAS_MIXED, width_c_kappa=c_kappa)
+        t0 = time.perf_counter()
+        H = rp.ras_pml_setup(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, pml, o)
+        f = torch.from_numpy(inputs.paper(k, n, G)).to("cuda")
+        b = torch.empty_like(f)
+        x = torch.zeros_like(f)
+        rp.ras_pml_rhs(H, f, b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if solver == "richardson":
+            rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-10, maxit=500, check=False)
+        else:
+            rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-10, restart=100, maxit=500,
+                                           check=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        desc = H.desc()
+        d = desc[0]
+        H.close()
+        del f, b, x
+        torch.cuda.empty_cache()
+        return {"k": k, "grid": n, "subdomains": P * P, "ovlp": d[20], "pml": d[21],
+                "global_pml": G, "band_max": max(e[1] for e in desc) + 1,
+                "W_max": max(e[2] for e in desc), "solver": solver, "iters": it,
+                "relres": rr if math.isfinite(rr) else None,
+                "converged": rc == rp.RAS_OK, "status": rc,
+                "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4)}
+
+    run(300.0, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")       # warm-up
+    for k in ks:
+        r = run(k, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")
+        r.update(table="table4", variant="RAS-PML-Imp",
+                 total_per_k=round((r["setup_s"] + r["solve_s"]) / k, 6))
+        print(json.dumps(r), flush=True)
+    variants = (("RAS-PML-Imp", rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE),
+                ("RAS-PML-Drch", rp.RAS_BC_DRCH, rp.RAS_WIDTH_RULE),
+                ("RAS-Imp", rp.RAS_BC_IMP, 0))
+    for k in ks:
+        for name, bc, pml in variants:
+            for solver in ("richardson", "gmres"):
+                if solver == "gmres" and k > 1200.0:
+                    continue
+                r = run(k, bc, pml, 3.0 / 8.0, solver)
+                r.update(table="tables12", variant=name)
+                print(json.dumps(r), flush=True)
 
 
 def warmstart(args):
