@@ -41,8 +41,8 @@ namespace {
 // leaves D[row0(l) + rs r][l & 15] in accumulator r -- rows 4 (l >> 4) .. + 3
 // in complex64 (v_mfma_f32_16x16x4f32), rows (l >> 4) + {0, 4, 8, 12} in
 // complex128 (v_mfma_f64_16x16x4f64; measured lane by lane); the pivot
-// reciprocal (v_rcp_f32 within 1 ulp for complex64 factors, a correctly
-// rounded division for complex128) and the relative pivot test.
+// reciprocal (v_rcp_f32 within 1 ulp for complex64 factors, v_rcp_f64 with
+// two Newton steps for complex128) and the relative pivot test.
 template <typename T>
 struct Prec;
 template <>
@@ -62,7 +62,15 @@ struct Prec<double> {
     static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    // v_rcp_f64 and two Newton steps r <- r + r (1 - x r): within an ulp or
+    // two of 1/x (the division's scaling and fix-up steps, which make it
+    // correctly rounded and handle denormal and huge x, lie on the panel's
+    // serial chain; |d|^2 of a pivot that passes the test is neither)
+    static __device__ __forceinline__ double rcp(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, 1.0), r);
+        return fma(r, fma(-x, r, 1.0), r);
+    }
     static __device__ __forceinline__ int row0(int lane) { return lane >> 4; }
     static constexpr int rs = 4;
     static constexpr double tol = 1e-14;
