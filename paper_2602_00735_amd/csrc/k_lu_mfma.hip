@@ -500,9 +500,12 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
         const int r = i / W, q = i % W;
         if (q > r && r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + q] = zero;
     }
-    for (int d = 0, u = 0; d < NT; ++d)
-        for (int q = 0; q < NT - d; ++q, ++u)
-            if (u % 256 == tid) TQ[u] = (d << 16) | q;
+#pragma unroll 1
+    for (int u = tid; u < NL; u += 256) {
+        int d = 0, q = u;
+        while (q >= NT - d) q -= NT - d++;
+        TQ[u] = (d << 16) | q;
+    }
     __syncthreads();
     // window at panel 0: ring tile (d, q) holds rows 16 (q + d).., columns 16 q..
 #pragma unroll 1
@@ -568,9 +571,12 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
             if (bad < 0 && fm != 0) bad = c0 + __builtin_ctzll(fm);
         }
         __syncthreads();
-        // 2b. rows 16 .. M-1
+        // 2b. rows 16 .. M-1 (the clobber keeps the block's LDS values from
+        // being hoisted into registers across the at most two rows a thread
+        // takes)
 #pragma unroll 1
         for (int r = 16 + tid; r < M; r += 256) {
+            asm volatile("" ::: "memory");
             cplx<T> x[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) x[k] = LP[r * kLdsStride + k];
