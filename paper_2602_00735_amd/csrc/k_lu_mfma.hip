@@ -463,8 +463,14 @@ __device__ __forceinline__ cplx<T> band_entry_sparse(const double2 *__restrict__
 template <int NT>
 __device__ __forceinline__ int ring_base(int d) { return d * NT - d * (d - 1) / 2; }
 
+// Threads per workgroup: as many waves as the registers allow (one
+// workgroup per CU): twelve in complex64 (three per SIMD), eight in
+// complex128.
+template <typename T>
+constexpr int wide_threads() { return sizeof(T) == 4 ? 768 : 512; }
+
 template <typename T, int K>
-__global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict__ subs,
+__global__ __launch_bounds__(wide_threads<T>()) void k_band_ldlt_wide(const DevSub *__restrict__ subs,
                                                         const int *__restrict__ order,
                                                         const double2 *__restrict__ lst_all,
                                                         cplx<T> *__restrict__ F,
@@ -475,11 +481,14 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
     constexpr int NT = 4 * K + 1;
     constexpr int M = 16 * NT;
     constexpr int NL = NT * (NT + 1) / 2;
+    constexpr int NU = NT * (NT - 1) / 2;   // tiles a panel updates (J >= 1)
     constexpr int RS = Prec<T>::rs;
+    constexpr int NTH = wide_threads<T>(), NWV = NTH / 64;
     __shared__ cplx<T> LP[M * kLdsStride];    // the panel; then L (zero on and above the diagonal)
     __shared__ cplx<T> WD[16 * kLdsStride];   // diagonal block, pre-scaled values (L D)
     __shared__ cplx<T> DV[16], IV[16];        // d_k and 1 / d_k of the panel's columns
     __shared__ int TQ[NL];                    // ring tile u: diagonal d (high half), slot q
+    __shared__ int TU[NU];                    // update tile t: diagonal d (high half), column J
 
     const int sid = order[blockIdx.x];
     const DevSub S = subs[sid];
@@ -496,20 +505,27 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
 
     // Row r < W of R has no columns before 0 at positions r+1 .. W-1.
 #pragma unroll 1
-    for (int i = tid; i < W * W; i += 256) {
+    for (int i = tid; i < W * W; i += NTH) {
         const int r = i / W, q = i % W;
         if (q > r && r < npad) Rw[static_cast<long long>(npad - 1 - r) * W + q] = zero;
     }
 #pragma unroll 1
-    for (int u = tid; u < NL; u += 256) {
+    for (int u = tid; u < NL; u += NTH) {
         int d = 0, q = u;
         while (q >= NT - d) q -= NT - d++;
         TQ[u] = (d << 16) | q;
     }
+    // diagonal d has NT - 1 - d tiles with J >= 1
+#pragma unroll 1
+    for (int t = tid; t < NU; t += NTH) {
+        int d = 0, j = t;
+        while (j >= NT - 1 - d) j -= NT - 1 - d++;
+        TU[t] = (d << 16) | (j + 1);
+    }
     __syncthreads();
     // window at panel 0: ring tile (d, q) holds rows 16 (q + d).., columns 16 q..
 #pragma unroll 1
-    for (int u = wave; u < NL; u += 4) {
+    for (int u = wave; u < NL; u += NWV) {
         const int d = TQ[u] >> 16, q = TQ[u] & 0xffff;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -524,7 +540,7 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
         const int p = c0 >> 4;
         // 1. logical tile column 0 (ring slot p mod (NT - I) of diagonal I)
 #pragma unroll 1
-        for (int I = wave; I < NT; I += 4) {
+        for (int I = wave; I < NT; I += NWV) {
             const cplx<T> *tile = win + (ring_base<NT>(I) + p % (NT - I)) * 256;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -575,7 +591,7 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
         // being hoisted into registers across the at most two rows a thread
         // takes)
 #pragma unroll 1
-        for (int r = 16 + tid; r < M; r += 256) {
+        for (int r = 16 + tid; r < M; r += NTH) {
             asm volatile("" ::: "memory");
             cplx<T> x[16];
 #pragma unroll
@@ -594,7 +610,7 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
         {
             const int sl0 = c0 % W;              // sl0 + 15 < W (W is a multiple of 64)
 #pragma unroll 1
-            for (int i = tid; i < 16 * W; i += 256) {
+            for (int i = tid; i < 16 * W; i += NTH) {
                 const int k = i / W, pos = i - (i / W) * W;
                 const int c = c0 + k, sl = sl0 + k;
                 const int r = c + (pos >= sl ? pos - sl : pos - sl + W);
@@ -604,45 +620,64 @@ __global__ __launch_bounds__(256) void k_band_ldlt_wide(const DevSub *__restrict
             const int k = tid & 15, c = c0 + k, slk = sl0 + k;
             if (tid < 16) Rw[static_cast<long long>(npad - 1 - c) * W + slk] = zero;
 #pragma unroll 1
-            for (int r = c0 + 1 + (tid >> 4); r < c0 + W + 15; r += 16)
+            for (int r = c0 + 1 + (tid >> 4); r < c0 + W + 15; r += NTH / 16)
                 if (r > c && r < c + W && r < npad)
                     Rw[static_cast<long long>(npad - 1 - r) * W + slk] =
                         LP[(r - c0) * kLdsStride + k];
         }
-        // 4. rank-16 update of the tiles with J >= 1; the tiles with J == 0
-        //    leave and their slots take the entering tiles
+        // 4. the tiles with J == 0 leave: their slots take their diagonal's
+        //    entering tile (row NT - 1 of the next window), from the stencil
 #pragma unroll 1
-        for (int u = wave; u < NL; u += 4) {
-            const int d = TQ[u] >> 16, q = TQ[u] & 0xffff;
-            const int len = NT - d;
-            const int J = (q - p % len + len) % len;
-            cplx<T> *tile = win + u * 256;
-            if (J >= 1) {
-                const int I = J + d;
-                v4 cre, cim;
+        for (int d = wave; d < NT; d += NWV) {
+            cplx<T> *tile = win + (ring_base<NT>(d) + p % (NT - d)) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                tile[64 * r + lane] = band_entry_sparse<T>(
+                    lst, n, nf, 16 * (p + NT) + ti + RS * r, 16 * (p + NT - d) + tj);
+        }
+        //    rank-16 update of the tiles with J >= 1 (logical (J + d, J),
+        //    ring slot (p + J) mod (NT - d)), two per wave at a time so that
+        //    the matrix-core chains of the two interleave; past the end the
+        //    second repeats the last tile and is not stored
+#pragma unroll 1
+        for (int t = wave; t < NU; t += 2 * NWV) {
+            const bool two = t + NWV < NU;
+            const int tt[2] = {t, min(t + NWV, NU - 1)};
+            int I[2], J[2];
+            cplx<T> *tile[2];
+            v4 cre[2], cim[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int d = TU[tt[h]] >> 16;
+                J[h] = TU[tt[h]] & 0xffff;
+                I[h] = J[h] + d;
+                tile[h] = win + (ring_base<NT>(d) + (p + J[h]) % (NT - d)) * 256;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const cplx<T> v = tile[64 * r + lane];
-                    cre[r] = v.re;
-                    cim[r] = v.im;
+                    const cplx<T> v = tile[h][64 * r + lane];
+                    cre[h][r] = v.re;
+                    cim[h][r] = v.im;
                 }
+            }
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const int col = 4 * kk + (lane >> 4);
-                    const cplx<T> l = LP[(16 * I + tj) * kLdsStride + col];
-                    const cplx<T> w = cmul(LP[(16 * J + tj) * kLdsStride + col], DV[col]);
-                    cre = Prec<T>::mfma(-l.re, w.re, cre);
-                    cre = Prec<T>::mfma(l.im, w.im, cre);
-                    cim = Prec<T>::mfma(-l.re, w.im, cim);
-                    cim = Prec<T>::mfma(-l.im, w.re, cim);
+            for (int kk = 0; kk < 4; ++kk) {
+                const int col = 4 * kk + (lane >> 4);
+                const cplx<T> dv = DV[col];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const cplx<T> l = LP[(16 * I[h] + tj) * kLdsStride + col];
+                    const cplx<T> w = cmul(LP[(16 * J[h] + tj) * kLdsStride + col], dv);
+                    cre[h] = Prec<T>::mfma(-l.re, w.re, cre[h]);
+                    cim[h] = Prec<T>::mfma(-l.re, w.im, cim[h]);
+                    cre[h] = Prec<T>::mfma(l.im, w.im, cre[h]);
+                    cim[h] = Prec<T>::mfma(-l.im, w.re, cim[h]);
                 }
+            }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tile[64 * r + lane] = cplx<T>{cre[r], cim[r]};
-            } else {
+            for (int r = 0; r < 4; ++r) tile[0][64 * r + lane] = cplx<T>{cre[0][r], cim[0][r]};
+            if (two) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    tile[64 * r + lane] = band_entry_sparse<T>(
-                        lst, n, nf, 16 * (p + NT) + ti + RS * r, 16 * (p + NT - d) + tj);
+                for (int r = 0; r < 4; ++r) tile[1][64 * r + lane] = cplx<T>{cre[1][r], cim[1][r]};
             }
         }
         __syncthreads();
@@ -656,10 +691,10 @@ void launch_wide_t(int K, const DevSub *subs, const int *order, int count, const
     cplx<T> *Fc = static_cast<cplx<T> *>(F);
     cplx<T> *sc = static_cast<cplx<T> *>(scratch);
     switch (K) {
-        case 3: hipLaunchKernelGGL((k_band_ldlt_wide<T, 3>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
-        case 4: hipLaunchKernelGGL((k_band_ldlt_wide<T, 4>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
-        case 5: hipLaunchKernelGGL((k_band_ldlt_wide<T, 5>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
-        default: hipLaunchKernelGGL((k_band_ldlt_wide<T, 6>), dim3(count), dim3(256), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 3: hipLaunchKernelGGL((k_band_ldlt_wide<T, 3>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 4: hipLaunchKernelGGL((k_band_ldlt_wide<T, 4>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 5: hipLaunchKernelGGL((k_band_ldlt_wide<T, 5>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
+        default: hipLaunchKernelGGL((k_band_ldlt_wide<T, 6>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
     }
 }
 
