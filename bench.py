@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (default: tune once before the warmup, outside the "
                          "timed region, and set every timed handle up from its cache)")
+    ap.add_argument("--no-section4", action="store_true",
+                    help="skip Section 4's own covering at k = 300 and 1200 (wide bands)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 32-problem batch (seeded multi-source problems, one handle)")
     ap.add_argument("--sweep", action="store_true",
@@ -425,6 +427,20 @@ def main():
         out["paper_source"] = blk
         progress("paper source done")
 
+    # ---------------------------------------------------------------- Section 4's covering
+    # the paper's own subdomains (300-cell cores, bands of ~350: the wide
+    # kernels) at k = 300 and 1200, Table 4's constants, Richardson to 1e-10
+    if not args.no_section4:
+        sec = []
+        section4_run(300.0, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")    # warm-up
+        for ks4 in (300.0, 1200.0):
+            r = section4_run(ks4, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")
+            sec.append({key: r[key] for key in ("k", "grid", "subdomains", "ovlp", "pml",
+                                                 "W_max", "iters", "relres", "converged",
+                                                 "setup_s", "solve_s")})
+        out["section4_covering"] = sec
+        progress("Section 4 covering done")
+
     # ---------------------------------------------------------------- CPU oracle
     if not args.no_cpu:
         xs = {args.source: {"mixed": mixed["x"]}}
@@ -508,13 +524,52 @@ def sweep(max_k):
         print(json.dumps(r), flush=True)
 
 
+def section4_run(k, bc, pml, c_kappa, solver):
+    """One run of Section 4's covering (see paper_tables): setup, right-hand
+    side and solve of a fresh handle; returns the run's figures."""
+    import torch
+    import paper_2602_00735_amd as rp
+    from paper_2602_00735_amd import inputs
+    n = int(round(2 * k))
+    h = 1.0 / n
+    P = int(round(k / 150))
+    G = int(math.floor(3 * 2 * math.pi / k / h + 1e-9))
+    o = rp.default_opts(global_pml=G, bc=bc, precision=rp.RAS_MIXED, width_c_kappa=c_kappa)
+    t0 = time.perf_counter()
+    H = rp.ras_pml_setup(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, pml, o)
+    f = torch.from_numpy(inputs.paper(k, n, G)).to("cuda")
+    b = torch.empty_like(f)
+    x = torch.zeros_like(f)
+    rp.ras_pml_rhs(H, f, b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if solver == "richardson":
+        rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-10, maxit=500, check=False)
+    else:
+        rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-10, restart=100, maxit=500,
+                                       check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    desc = H.desc()
+    d = desc[0]
+    H.close()
+    del f, b, x
+    torch.cuda.empty_cache()
+    return {"k": k, "grid": n, "subdomains": P * P, "ovlp": d[20], "pml": d[21],
+            "global_pml": G, "band_max": max(e[1] for e in desc) + 1,
+            "W_max": max(e[2] for e in desc), "solver": solver, "iters": it,
+            "relres": rr if math.isfinite(rr) else None,
+            "converged": rc == rp.RAS_OK, "status": rc,
+            "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4)}
+
+
 def paper_tables(max_k):
     """Section 4's covering on one GPU: k = 300 ... max_k, grid (2k)^2 (12
     points per wavelength), P = k/150 subdomains per side (300-cell cores of
     the interior grid; the covering divides the grid with its global PML),
     overlap and PML from the width rule, a global PML of three wavelengths,
     g = 10 k x^3, the smoothed point source, rtol 1e-10, at most 500
-    iterations, mixed precision.  Subdomain bands of 333..373: the wide
+    iterations, mixed precision.  Subdomain bands of 323..375: the wide
     kernels.
       - "tables12": C_delta = 1/6, C_kappa = 3/8; RAS-PML-Imp, RAS-PML-Drch
         and RAS-Imp; Richardson and GMRES(100) (GMRES up to k = 1200, whose
@@ -523,42 +578,9 @@ def paper_tables(max_k):
         setup and solve seconds."""
     import torch
     import paper_2602_00735_amd as rp
-    from paper_2602_00735_amd import inputs
     torch.cuda.set_device(0)
     ks = [k for k in (300.0, 600.0, 1200.0, 2400.0) if k <= max_k]
-
-    def run(k, bc, pml, c_kappa, solver):
-        n = int(round(2 * k))
-        h = 1.0 / n
-        P = int(round(k / 150))
-        G = int(math.floor(3 * 2 * math.pi / k / h + 1e-9))
-        o = rp.default_opts(global_pml=G, bc=bc, precision=rp.RAS_MIXED, width_c_kappa=c_kappa)
-        t0 = time.perf_counter()
-        H = rp.ras_pml_setup(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, pml, o)
-        f = torch.from_numpy(inputs.paper(k, n, G)).to("cuda")
-        b = torch.empty_like(f)
-        x = torch.zeros_like(f)
-        rp.ras_pml_rhs(H, f, b)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if solver == "richardson":
-            rc, it, rr, _ = rp.ras_pml_richardson(H, b, x, rtol=1e-10, maxit=500, check=False)
-        else:
-            rc, it, rr, _ = rp.gmres_solve(H, b, x, rtol=1e-10, restart=100, maxit=500,
-                                           check=False)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        desc = H.desc()
-        d = desc[0]
-        H.close()
-        del f, b, x
-        torch.cuda.empty_cache()
-        return {"k": k, "grid": n, "subdomains": P * P, "ovlp": d[20], "pml": d[21],
-                "global_pml": G, "band_max": max(e[1] for e in desc) + 1,
-                "W_max": max(e[2] for e in desc), "solver": solver, "iters": it,
-                "relres": rr if math.isfinite(rr) else None,
-                "converged": rc == rp.RAS_OK, "status": rc,
-                "setup_s": round(t1 - t0, 4), "solve_s": round(t2 - t1, 4)}
+    run = section4_run
 
     run(300.0, rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE, 0.5, "richardson")       # warm-up
     for k in ks:
