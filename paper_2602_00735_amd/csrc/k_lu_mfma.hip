@@ -438,12 +438,12 @@ void launch_t(int NT, bool occ, const DevSub *subs, const int *order, int count,
 //      pre-scaled block and the reciprocals from LDS);
 //   3. L (column copy in slot order, row copy) and D^{-1} are written out,
 //      in the layout of the other kernels with W the column length;
-//   4. each wave takes its share of the tiles with J >= 1 (C -= L_I (L_J D)^T
-//      on the matrix cores: loaded from the scratch, 16 products, stored
-//      back), and the tiles with J == 0 become their diagonal's entering
-//      tile, straight from the stencil.
-// Rows M - 1 .. of a window start at panel 0 as the stencil's couplings;
-// rows past the matrix end are identity rows.
+//   4. the tiles with J == 0 become their diagonal's entering tile,
+//      straight from the stencil, and each wave takes its share of the tiles
+//      with J >= 1 (C -= L_I (L_J D)^T on the matrix cores: loaded from the
+//      scratch, 16 products, stored back), two at a time.
+// The window at panel 0 holds the stencil's couplings; rows past the matrix
+// end are identity rows.
 
 // A_j(r, q) as band_entry, loading only where the stencil couples r and q.
 template <typename T>
@@ -470,12 +470,10 @@ template <typename T>
 constexpr int wide_threads() { return sizeof(T) == 4 ? 768 : 512; }
 
 template <typename T, int K>
-__global__ __launch_bounds__(wide_threads<T>()) void k_band_ldlt_wide(const DevSub *__restrict__ subs,
-                                                        const int *__restrict__ order,
-                                                        const double2 *__restrict__ lst_all,
-                                                        cplx<T> *__restrict__ F,
-                                                        cplx<T> *__restrict__ scratch,
-                                                        int *__restrict__ status) {
+__global__ __launch_bounds__(wide_threads<T>()) void k_band_ldlt_wide(
+    const DevSub *__restrict__ subs, const int *__restrict__ order,
+    const double2 *__restrict__ lst_all, cplx<T> *__restrict__ F, cplx<T> *__restrict__ scratch,
+    int *__restrict__ status) {
     typedef typename Prec<T>::v4 v4;
     constexpr int W = 64 * K;
     constexpr int NT = 4 * K + 1;
@@ -690,12 +688,16 @@ void launch_wide_t(int K, const DevSub *subs, const int *order, int count, const
                    void *F, void *scratch, int *status, hipStream_t st) {
     cplx<T> *Fc = static_cast<cplx<T> *>(F);
     cplx<T> *sc = static_cast<cplx<T> *>(scratch);
+    const dim3 grid(count), block(wide_threads<T>());
+#define RAS_WIDE(KK) \
+    hipLaunchKernelGGL((k_band_ldlt_wide<T, KK>), grid, block, 0, st, subs, order, lst, Fc, sc, status)
     switch (K) {
-        case 3: hipLaunchKernelGGL((k_band_ldlt_wide<T, 3>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
-        case 4: hipLaunchKernelGGL((k_band_ldlt_wide<T, 4>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
-        case 5: hipLaunchKernelGGL((k_band_ldlt_wide<T, 5>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
-        default: hipLaunchKernelGGL((k_band_ldlt_wide<T, 6>), dim3(count), dim3(wide_threads<T>()), 0, st, subs, order, lst, Fc, sc, status); break;
+        case 3: RAS_WIDE(3); break;
+        case 4: RAS_WIDE(4); break;
+        case 5: RAS_WIDE(5); break;
+        default: RAS_WIDE(6); break;
     }
+#undef RAS_WIDE
 }
 
 }  // namespace
