@@ -233,3 +233,30 @@ def test_table4_covering_at_k300(solver):
     assert rc == rp.RAS_OK and it <= 10, (rc, it)
     xs = host(x)
     assert np.linalg.norm(b - A @ xs) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-6)
+
+
+def test_wide_and_narrow_problems_in_one_batch():
+    """A batch handle holding a problem of wide subdomains (W = 192) and one
+    of narrow ones (register-ring kernels): the fixed-point iteration of each
+    equals its own oracle run (FP64), step for step."""
+    pbs = [Problem(k=30.0, n_int=230, G=8, Px=2, Py=2, delta=8, kappa=8, sigma=300.0),
+           Problem(k=20.0, n_int=40, G=6, Px=2, Py=2, delta=6, kappa=6, sigma=200.0)]
+    o = rp.default_opts(precision=rp.RAS_FP64)
+    H = rp.ras_pml_setup_batch([p.k for p in pbs], [1 / p.n_int for p in pbs],
+                               [(p.n_int, p.n_int) for p in pbs], [(p.Px, p.Py) for p in pbs],
+                               [p.delta for p in pbs], [p.kappa for p in pbs], o)
+    assert sorted({d[2] > 128 for d in H.desc()}) == [False, True]
+    Rs = [ras.RasPml(p) for p in pbs]
+    bs = [fem.rhs(R.M1, inputs.centre_gaussian(p.n_int, p.G, 0.1)) for p, R in zip(pbs, Rs)]
+    refs = [richardson.ras_richardson(lambda y, R=R: R.A @ y, R.apply, b, rtol=1e-6, maxit=80)
+            for R, b in zip(Rs, bs)]
+    x = torch.zeros(H.ndof, dtype=torch.complex128, device="cuda")
+    rc, it, rr, hist = rp.ras_pml_richardson(H, dev(np.concatenate(bs)), x, rtol=1e-6, maxit=80)
+    assert it == max(r.iters for r in refs)
+    xs = host(x)
+    for p, ref in enumerate(refs):
+        off, m = H.problem_offset(p)
+        itp, rrp, conv = rp.ras_pml_batch_result(H, p)
+        assert itp == ref.iters and conv == ref.converged
+        assert abs(rrp - ref.relres) <= 1e-8 * ref.relres
+        assert relerr(xs[off:off + m], ref.x) <= 1e-9
