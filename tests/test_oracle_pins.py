@@ -140,9 +140,14 @@ def test_p3_band_lu_detects_zero_pivot():
     assert st == 1
 
 
-def test_p11_local_solves_vs_lapack_banded():
-    pb = geometry.config_problem("k20")
-    R = ras.RasPml(pb, with_global=False)
+# k20, and a corner subdomain of band 138 (137 x 137 unknowns: the width of
+# the GPU's wide kernels)
+@pytest.mark.parametrize("pb,subset", [
+    (geometry.config_problem("k20"), None),
+    (geometry.Problem(k=30.0, n_int=230, G=6, Px=2, Py=2, delta=8, kappa=8, sigma=300.0), [0]),
+])
+def test_p11_local_solves_vs_lapack_banded(pb, subset):
+    R = ras.RasPml(pb, subset=subset, with_global=False)
     v = inputs.random_vector(pb.ndof, 11)
     loc = R.local_solve(v)
     rhs_all = R.restrict(v)
