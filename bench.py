@@ -524,9 +524,10 @@ def sweep(max_k):
         print(json.dumps(r), flush=True)
 
 
-def section4_run(k, bc, pml, c_kappa, solver):
+def section4_run(k, bc, pml, c_kappa, solver, overlap=None):
     """One run of Section 4's covering (see paper_tables): setup, right-hand
-    side and solve of a fresh handle; returns the run's figures."""
+    side and solve of a fresh handle; returns the run's figures.  overlap and
+    pml in cells, or RAS_WIDTH_RULE (the default overlap)."""
     import torch
     import paper_2602_00735_amd as rp
     from paper_2602_00735_amd import inputs
@@ -535,8 +536,9 @@ def section4_run(k, bc, pml, c_kappa, solver):
     P = int(round(k / 150))
     G = int(math.floor(3 * 2 * math.pi / k / h + 1e-9))
     o = rp.default_opts(global_pml=G, bc=bc, precision=rp.RAS_MIXED, width_c_kappa=c_kappa)
+    ov = rp.RAS_WIDTH_RULE if overlap is None else overlap
     t0 = time.perf_counter()
-    H = rp.ras_pml_setup(k, h, (n, n), (P, P), rp.RAS_WIDTH_RULE, pml, o)
+    H = rp.ras_pml_setup(k, h, (n, n), (P, P), ov, pml, o)
     f = torch.from_numpy(inputs.paper(k, n, G)).to("cuda")
     b = torch.empty_like(f)
     x = torch.zeros_like(f)
@@ -575,7 +577,12 @@ def paper_tables(max_k):
         and RAS-Imp; Richardson and GMRES(100) (GMRES up to k = 1200, whose
         Krylov basis still fits beside the factors).
       - "table4": C_delta = 1/6, C_kappa = 1/2; RAS-PML-Imp Richardson;
-        setup and solve seconds."""
+        setup and solve seconds.
+      - "table3": RAS-PML-Imp Richardson with the PML a fixed two
+        wavelengths and the overlap two thirds of a wavelength or from the
+        rule, and with the rule's PML (C_kappa = 1/2) and an overlap of a
+        third of a wavelength (the fourth column pair of Table 3 is
+        Table 4's set-up)."""
     import torch
     import paper_2602_00735_amd as rp
     torch.cuda.set_device(0)
@@ -588,6 +595,14 @@ def paper_tables(max_k):
         r.update(table="table4", variant="RAS-PML-Imp",
                  total_per_k=round((r["setup_s"] + r["solve_s"]) / k, 6))
         print(json.dumps(r), flush=True)
+    for k in ks:
+        cells = lambda wavelengths: int(math.floor(wavelengths * 2 * math.pi / k * 2 * k + 1e-9))
+        for name, pml, ov in (("pml 2 wavelengths, ovlp 2/3 wavelength", cells(2.0), cells(2.0 / 3.0)),
+                              ("pml 2 wavelengths, ovlp rule", cells(2.0), None),
+                              ("pml rule, ovlp 1/3 wavelength", rp.RAS_WIDTH_RULE, cells(1.0 / 3.0))):
+            r = run(k, rp.RAS_BC_IMP, pml, 0.5, "richardson", overlap=ov)
+            r.update(table="table3", variant=name)
+            print(json.dumps(r), flush=True)
     variants = (("RAS-PML-Imp", rp.RAS_BC_IMP, rp.RAS_WIDTH_RULE),
                 ("RAS-PML-Drch", rp.RAS_BC_DRCH, rp.RAS_WIDTH_RULE),
                 ("RAS-Imp", rp.RAS_BC_IMP, 0))

@@ -107,7 +107,7 @@ void ras_pml_default_opts(ras_pml_opts *o);
  *   desc       nullable; if given, nsub * RAS_DESC_INTS int32 (host memory):
  *              [0] n_local  [1] n_fast  [2] W = n_fast + 2 rounded up to
  *              even, or to a multiple of 64 when that exceeds 128 (factor
- *              column length; at most 384)  [3] x_fast  [4] first unknown
+ *              column length; at most 448)  [3] x_fast  [4] first unknown
  *              node i  [5] n_x
  *              [6] first unknown node j  [7] n_y  [8] chunk p  [9] chunk q
  *              [10..13] Omega_int x lo, x hi, y lo, y hi (node indices)

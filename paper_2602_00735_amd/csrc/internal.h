@@ -13,9 +13,9 @@ namespace raspml {
 
 // Factor column length W: n_fast + 2 rounded up to even up to kMaxW (the
 // register-ring kernels), else rounded up to a multiple of 64 up to
-// kMaxWideW (the wide kernels: 3 to 6 registers of 64 slots per lane).
+// kMaxWideW (the wide kernels: 3 to 7 registers of 64 slots per lane).
 constexpr int kMaxW = 128;
-constexpr int kMaxWideW = 384;
+constexpr int kMaxWideW = 448;
 // Largest number of chunks whose partition-of-unity weight is non-zero at
 // one mesh node along one axis.
 constexpr int kMaxPou = 4;

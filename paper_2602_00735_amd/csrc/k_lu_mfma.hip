@@ -422,7 +422,7 @@ void launch_t(int NT, bool occ, const DevSub *subs, const int *order, int count,
 }
 
 // ------------------------------------------------------------ wide bands
-// W = 64 K with K = 3..6 (bands 129..383: the subdomains of Section 4's own
+// W = 64 K with K = 3..7 (bands 129..447: the subdomains of Section 4's own
 // experiments, 300-cell cores with their overlap and PML).  The same
 // blocked LDL^T in 16-column panels, but the window (M = W + 16 rows and
 // columns, NT = 4 K + 1 tiles per side, NT (NT + 1) / 2 tiles on and below
@@ -695,7 +695,8 @@ void launch_wide_t(int K, const DevSub *subs, const int *order, int count, const
         case 3: RAS_WIDE(3); break;
         case 4: RAS_WIDE(4); break;
         case 5: RAS_WIDE(5); break;
-        default: RAS_WIDE(6); break;
+        case 6: RAS_WIDE(6); break;
+        default: RAS_WIDE(7); break;
     }
 #undef RAS_WIDE
 }
@@ -709,7 +710,7 @@ long long ldlt_wide_scratch(int K) {
     return NT * (NT + 1) / 2 * 256;
 }
 
-// count subdomains order[0 .. count) that all have W == 64 K (K = 3..6);
+// count subdomains order[0 .. count) that all have W == 64 K (K = 3..7);
 // scratch: count * ldlt_wide_scratch(K) complex values of the factor
 // precision.
 void launch_band_ldlt_wide(bool fp64, int K, const DevSub *subs, const int *order, int count,

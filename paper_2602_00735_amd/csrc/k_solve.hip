@@ -397,7 +397,7 @@ __global__ void k_export_local(const DevSub *__restrict__ subs, const cplx<T> *_
     xl[S.loc_off + r] = make_double2(static_cast<double>(x.re), static_cast<double>(x.im));
 }
 
-// Wide bands (W = 64 K, K = 3..6): register k of lane l holds ring slot
+// Wide bands (W = 64 K, K = 3..7): register k of lane l holds ring slot
 // 64 k + l, the slot of the rows congruent to it mod W.  W is a multiple of
 // 64, so the pivots of a block of 64 steps sit in one register, number
 // (block index) mod K, in lanes 0..63.  A finished slot keeps accumulating
@@ -526,7 +526,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         case 3: solve_wide<T, 3, PD>(probs, S, vs, F, ybuf, xout); break;
         case 4: solve_wide<T, 4, PD>(probs, S, vs, F, ybuf, xout); break;
         case 5: solve_wide<T, 5, PD>(probs, S, vs, F, ybuf, xout); break;
-        default: solve_wide<T, 6, PD>(probs, S, vs, F, ybuf, xout); break;
+        case 6: solve_wide<T, 6, PD>(probs, S, vs, F, ybuf, xout); break;
+        default: solve_wide<T, 7, PD>(probs, S, vs, F, ybuf, xout); break;
     }
 }
 
@@ -557,7 +558,7 @@ void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order
 // dispatch of one wave per subdomain, or a persistent grid of dsp.waves
 // waves taking subdomains from the counter dsp.queue (two words, zero
 // between launches) when fewer waves than subdomains are asked for.
-// The wide subdomains order[0 .. nsub) (W = 192, 256, 320 or 384), one
+// The wide subdomains order[0 .. nsub) (W = 192, 256, 320, 384 or 448), one
 // wave each; prefetch 16 vectors in complex64, 8 in complex128.
 void launch_band_solve_wide(bool fp64, const DevProb *probs, const DevSub *subs, const int *order,
                             int nsub, const int *active, const SolveSrc &src, const void *F,

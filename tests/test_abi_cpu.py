@@ -69,7 +69,7 @@ def test_strerror(L):
     (dict(subdomains=(0, 2)), rp.RAS_EINVAL),
     (dict(overlap=-2), rp.RAS_EINVAL),            # -1 is RAS_WIDTH_RULE
     (dict(pml_width=-3), rp.RAS_EINVAL),
-    (dict(subdomains=(1, 1), grid=(400, 400), h=1 / 400), rp.RAS_ENOTSUP),   # band too wide
+    (dict(subdomains=(1, 1), grid=(500, 500), h=1 / 500), rp.RAS_ENOTSUP),   # band too wide
 ])
 def test_plan_rejects_bad_parameters(L, args, status):
     kw = dict(k=20.0, h=1 / 40, grid=(40, 40), subdomains=(2, 2), overlap=6, pml_width=6)
@@ -82,20 +82,25 @@ def test_plan_rejects_bad_parameters(L, args, status):
 
 def test_wide_band_columns_are_multiples_of_64(L):
     """Bands above 127 take the wide kernels: W = n_fast + 2 rounded up to a
-    multiple of 64, up to 384 (Section 4's own subdomains, 300-cell cores
-    with their overlap and PML, have n_fast of about 330..370)."""
+    multiple of 64, up to 448 (Section 4's own subdomains, 300-cell cores
+    with their overlap and PML, have n_fast of about 330..390)."""
     o = rp.default_opts(global_pml=6)
     for n_int, nf, W in ((115, 126, 128), (116, 127, 192), (194, 205, 256), (254, 265, 320),
-                         (340, 351, 384), (370, 381, 384)):
+                         (340, 351, 384), (370, 381, 384), (371, 382, 384), (372, 383, 448),
+                         (434, 445, 448), (435, 446, 448)):
         d = rp.ras_pml_plan(40.0, 1 / n_int, (n_int, n_int), (1, 1), 0, 0, o)
         assert (d[0][1], d[0][2]) == (nf, W), (n_int, d[0][1], d[0][2])
     with pytest.raises(rp.RasPmlError) as e:
-        rp.ras_pml_plan(40.0, 1 / 372, (372, 372), (1, 1), 0, 0, o)      # n_fast 383: W 385
+        rp.ras_pml_plan(40.0, 1 / 436, (436, 436), (1, 1), 0, 0, o)      # n_fast 447: W 449
     assert e.value.status == rp.RAS_ENOTSUP
     # the paper's Table 4 covering at k = 600 (16 subdomains, pml 16, ovlp 5,
     # global PML of three wavelengths): every band fits
     d = rp.ras_pml_plan(600.0, 1 / 1200, (1200, 1200), (4, 4), 5, 16, rp.default_opts(global_pml=38))
     assert max(x[2] for x in d) == 384 and min(x[2] for x in d) >= 192
+    # Table 3's fixed PML of two wavelengths (25 cells) and overlap of two
+    # thirds of one (8 cells) at k = 600: middle subdomains of band 387
+    d = rp.ras_pml_plan(600.0, 1 / 1200, (1200, 1200), (4, 4), 8, 25, rp.default_opts(global_pml=37))
+    assert max(x[1] for x in d) + 1 == 387 and max(x[2] for x in d) == 448
 
 
 def test_setup_validation_runs_before_any_device_work(L):
