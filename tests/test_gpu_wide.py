@@ -261,3 +261,39 @@ def test_wide_and_narrow_problems_in_one_batch():
         assert itp == ref.iters and conv == ref.converged
         assert abs(rrp - ref.relres) <= 1e-8 * ref.relres
         assert relerr(xs[off:off + m], ref.x) <= 1e-9
+
+
+def test_wide_graph_replayed_steps_and_autotune():
+    """The FGMRES steps replayed from the recorded HIP graph (wide band-solve
+    launches included) equal the eager steps bit for bit; the autotuner runs
+    on a handle whose subdomains are all wide, and the apply afterwards is
+    unchanged (its factorisation has no variants to choose)."""
+    pb = WIDE["mixed_wide"]
+    R = oracle_for("mixed_wide")
+    b = dev(fem.rhs(R.M1, inputs.centre_gaussian(pb.n_int, pb.G, 0.1)))
+    res = []
+    for flags in (0, rp.RAS_FLAG_GRAPH_STEPS):
+        o = rp.default_opts(sigma=pb.sigma, global_pml=pb.G, precision=rp.RAS_MIXED, flags=flags)
+        H = rp.ras_pml_setup(pb.k, 1.0 / pb.n_int, (pb.n_int, pb.n_int), (pb.Px, pb.Py),
+                             pb.delta, pb.kappa, o)
+        x = torch.zeros_like(b)
+        rc, it, rr, hist = rp.gmres_solve(H, b, x, rtol=1e-6, restart=16, maxit=500)
+        assert rc == rp.RAS_OK
+        res.append((it, rr, np.asarray(hist).copy(), host(x)))
+        H.close()
+    (it0, rr0, h0, x0), (it1, rr1, h1, x1) = res
+    assert it0 == it1 and rr0 == rr1 and np.array_equal(h0, h1) and np.array_equal(x0, x1)
+    # the autotuner on an all-wide handle
+    import os
+    import tempfile
+    pw = WIDE["wide"]
+    H = setup_gpu(pw, rp.RAS_MIXED)
+    v = dev(inputs.random_vector(pw.ndof, 5))
+    z0 = torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, z0)
+    path = os.path.join(tempfile.mkdtemp(), "tune.json")
+    rp.ras_pml_autotune(H, path)
+    z1 = torch.zeros_like(v)
+    rp.ras_pml_apply(H, v, z1)
+    assert torch.equal(z0, z1)
+    assert rp.ras_pml_tuning(H)["ldlt"] == []
