@@ -397,137 +397,157 @@ __global__ void k_export_local(const DevSub *__restrict__ subs, const cplx<T> *_
     xl[S.loc_off + r] = make_double2(static_cast<double>(x.re), static_cast<double>(x.im));
 }
 
-// Wide bands (W = 64 K, K = 3..7): register k of lane l holds ring slot
-// 64 k + l, the slot of the rows congruent to it mod W.  W is a multiple of
-// 64, so the pivots of a block of 64 steps sit in one register, number
-// (block index) mod K, in lanes 0..63.  A finished slot keeps accumulating
-// for the row W further on; at the start of that row's block the register
-// takes (right-hand side - finished value), the finished values being the
-// block's outputs K blocks before, kept in registers (hk).  The factor
-// vectors are read K lanes-wide loads per step, PD steps ahead; the stream
-// layout is that of the other kernels.
+// Wide bands (W = 64 K, K = 3..7), two waves per subdomain.  Ring register
+// k of lane l holds slot 64 k + l, the slot of the rows congruent to it mod
+// W; W is a multiple of 64, so the pivots of a block of 64 steps all sit in
+// register (block index) mod K.  Wave 0 holds registers 0 .. KA-1, wave 1
+// the rest (KA = ceil(K / 2)).  Every pivot updates every register, but the
+// pivots of a block come from one wave, its owner, which runs the block's
+// serial steps on its own registers and publishes the 64 pivots in LDS; the
+// other wave applies them to its registers one block later (no serial
+// dependence there).  In the lock-step iteration of block b the owner of b
+// first applies block b - 1 if the other wave owned it, then runs block b;
+// the other wave applies block b - 1 if it did not own it.  Both waves pass
+// one workgroup barrier per block.  Ownership changes every KA or K - KA
+// blocks, so per K blocks about K / 2 + 1 of the half-width block times are
+// on the critical path instead of K full ones.  A finished slot keeps
+// accumulating for the row W further on; at the start of that row's block
+// its owner adds (right-hand side - finished value), the finished values
+// being its block outputs K blocks before (hk).  Each wave reads its part of
+// every factor vector it applies, PD steps ahead; the stream layout is that
+// of the other kernels.
 template <typename T, int K, int PD>
 __device__ __forceinline__ void solve_wide(const DevProb *__restrict__ probs, const DevSub &S,
                                            const double2 *__restrict__ v,
                                            const cplx<T> *__restrict__ F,
                                            cplx<T> *__restrict__ ybuf,
-                                           cplx<T> *__restrict__ xout) {
+                                           cplx<T> *__restrict__ xout, cplx<T> (*pbuf)[64]) {
     constexpr int W = 64 * K;
+    constexpr int KA = (K + 1) / 2;            // registers per wave (wave 1: K - KA)
     const int dof_off = static_cast<int>(probs[S.prob].dof_off);
     const int n1 = probs[S.prob].n1;
-    const int lane = threadIdx.x;
-    const int npad = S.npad;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int g0 = wv ? KA : 0;                // first ring register of this wave
+    const int npad = S.npad, nb = npad / 64;
     const long long NW = static_cast<long long>(npad) * W;
     const cplx<T> *L = F + S.fac_off;
     const cplx<T> *Dv = L + 2 * NW;
     cplx<T> *yb = ybuf + S.vec_off;
     cplx<T> *xo = xout + S.vec_off;
     const cplx<T> zero{0, 0};
-    // the pivot register kb as a value: a select over the K registers
-    auto pick = [&](const cplx<T> *a, int kb) {
+    // this wave's lane offsets in a factor vector (wave 1 of an odd K has
+    // one register fewer: its last one re-reads a valid entry and is never
+    // a pivot)
+    int off[KA];
+#pragma unroll
+    for (int j = 0; j < KA; ++j) off[j] = 64 * min(g0 + j, K - 1) + lane;
+    auto owner = [&](int kb) { return kb < KA ? 0 : 1; };
+    auto pick = [&](const cplx<T> *a, int j) {
         cplx<T> r = a[0];
 #pragma unroll
-        for (int k = 1; k < K; ++k) r = csel(kb == k, a[k], r);
+        for (int i = 1; i < KA; ++i) r = csel(j == i, a[i], r);
         return r;
     };
-    const cplx<T> *pf = L;
-    cplx<T> f[PD][K];
+    const cplx<T> *pf;
+    cplx<T> f[PD][KA];
+    auto start = [&](const cplx<T> *p) {
+        pf = p;
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
+        for (int u = 0; u < PD; ++u) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) f[u][k] = nt_load(pf + 64 * k + lane);
-        pf += W;
-    }
-    cplx<T> y[K], hk[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) y[k] = hk[k] = zero;
-
-    // ------------------------------------------------------------ forward
-    cplx<T> rnext = gather_rhs<T>(S, dof_off, n1, v, lane);
-    int kb = 0;
-    for (int c0 = 0; c0 < npad; c0 += 64) {
-        const cplx<T> rblk = rnext;
-        const double2 rraw = gather_raw(S, dof_off, n1, v, c0 + 64 + lane);
-#pragma unroll
-        for (int k = 0; k < K; ++k) y[k] = csel(kb == k, cadd(y[k], csub(rblk, hk[k])), y[k]);
-        cplx<T> yout = zero;
-#pragma unroll
-        for (int t = 0; t < 64; ++t) {
-            const int u = t % PD;
-            const cplx<T> piv = readlane(pick(y, kb), t);          // y_(c0+t)
-#pragma unroll
-            for (int k = 0; k < K; ++k) y[k] = cfms(y[k], f[u][k], piv);
-            yout = writelane(yout, piv, t);
-#pragma unroll
-            for (int k = 0; k < K; ++k) f[u][k] = nt_load(pf + 64 * k + lane);
+            for (int j = 0; j < KA; ++j) f[u][j] = nt_load(pf + off[j]);
             pf += W;
-            __builtin_amdgcn_sched_barrier(0);
         }
-        rnext = to_T<T>(rraw, c0 + 64 + lane < S.n);
-        yb[c0 + lane] = yout;
-#pragma unroll
-        for (int k = 0; k < K; ++k) hk[k] = csel(kb == k, yout, hk[k]);
-        kb = kb + 1 == K ? 0 : kb + 1;
-    }
-
-    // ------------------------------------------------------------ backward
-    // L^T x = D^{-1} y, rows in decreasing order: the slot of row r held
-    // row r + W before
-    cplx<T> x[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) x[k] = hk[k] = zero;
-    auto zrow = [&](int r) {           // z_r, 0 for r < 0
-        const int rr = max(r, 0);
-        return csel(r >= 0, cmul(yb[rr], Dv[rr]), zero);
     };
-    kb = (npad / 64 - 1) % K;
-    cplx<T> znext = zrow(npad - 64 + lane);
-    for (int c0 = npad - 64; c0 >= 0; c0 -= 64) {
-        const cplx<T> zblk = znext;
-        const int rn = c0 - 64 + lane;
-        const cplx<T> ynx = yb[max(rn, 0)];
-        const cplx<T> dnx = Dv[max(rn, 0)];
-#pragma unroll
-        for (int k = 0; k < K; ++k) x[k] = csel(kb == k, cadd(x[k], csub(zblk, hk[k])), x[k]);
-        cplx<T> xr = zero;
+    cplx<T> y[KA], hk[KA];
+    // 64 steps applying the pivots of register vector pv (lane t: step t;
+    // down: steps in decreasing t)
+    auto apply = [&](const cplx<T> pv, bool down) {
 #pragma unroll
         for (int q = 0; q < 64; ++q) {
-            const int t = 63 - q;
+            const int t = down ? 63 - q : q;
             const int u = q % PD;
-            const cplx<T> piv = readlane(pick(x, kb), t);          // x_(c0+t)
+            const cplx<T> piv = readlane(pv, t);
 #pragma unroll
-            for (int k = 0; k < K; ++k) x[k] = cfms(x[k], f[u][k], piv);
-            xr = writelane(xr, piv, t);
+            for (int j = 0; j < KA; ++j) y[j] = cfms(y[j], f[u][j], piv);
 #pragma unroll
-            for (int k = 0; k < K; ++k) f[u][k] = nt_load(pf + 64 * k + lane);
+            for (int j = 0; j < KA; ++j) f[u][j] = nt_load(pf + off[j]);
             pf += W;
             __builtin_amdgcn_sched_barrier(0);
         }
-        znext = csel(rn >= 0, cmul(ynx, dnx), zero);
-        xo[c0 + lane] = xr;
+    };
+    // 64 serial steps with the pivots in local register jl; returns them
+    auto chain = [&](int jl, bool down) {
+        cplx<T> out = zero;
 #pragma unroll
-        for (int k = 0; k < K; ++k) hk[k] = csel(kb == k, xr, hk[k]);
-        kb = kb == 0 ? K - 1 : kb - 1;
-    }
+        for (int q = 0; q < 64; ++q) {
+            const int t = down ? 63 - q : q;
+            const int u = q % PD;
+            const cplx<T> piv = readlane(pick(y, jl), t);
+#pragma unroll
+            for (int j = 0; j < KA; ++j) y[j] = cfms(y[j], f[u][j], piv);
+            out = writelane(out, piv, t);
+#pragma unroll
+            for (int j = 0; j < KA; ++j) f[u][j] = nt_load(pf + off[j]);
+            pf += W;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return out;
+    };
+    // one sweep: blocks b0, b0 + db, ... (nb of them), right-hand side of
+    // block b from rhs(b), outputs to dst
+    auto sweep = [&](int b0, int db, bool down, auto rhs, cplx<T> *dst) {
+#pragma unroll
+        for (int j = 0; j < KA; ++j) y[j] = hk[j] = zero;
+        cplx<T> rnext = rhs(b0);
+        for (int i = 0; i < nb; ++i) {
+            const int b = b0 + i * db;
+            const int kb = b % K, kbp = (b - db) % K;
+            const cplx<T> rblk = rnext;
+            if (i + 1 < nb) rnext = rhs(b + db);
+            if (i > 0 && owner(kbp) != wv) apply(pbuf[(i - 1) & 1][lane], down);
+            if (owner(kb) == wv) {
+                const int jl = kb - g0;
+#pragma unroll
+                for (int j = 0; j < KA; ++j) y[j] = csel(j == jl, cadd(y[j], csub(rblk, hk[j])), y[j]);
+                const cplx<T> out = chain(jl, down);
+#pragma unroll
+                for (int j = 0; j < KA; ++j) hk[j] = csel(j == jl, out, hk[j]);
+                dst[64 * b + lane] = out;
+                pbuf[i & 1][lane] = out;
+            }
+            __syncthreads();
+        }
+    };
+
+    // forward L y = R_j v (columns of L, blocks in increasing order)
+    start(L);
+    sweep(0, 1, false, [&](int b) { return gather_rhs<T>(S, dof_off, n1, v, 64 * b + lane); }, yb);
+    // backward L^T x = D^{-1} y (rows of L, last first; the forward results
+    // of the other wave are visible after the sweep's last barrier)
+    start(L + NW);
+    sweep(nb - 1, -1, true, [&](int b) { return cmul(yb[64 * b + lane], Dv[64 * b + lane]); }, xo);
 }
 
-// One wave per wide subdomain (order[0 .. nsub)), the right-hand side as
+// Two waves per wide subdomain (order[0 .. nsub)), the right-hand side as
 // for k_band_solve.
 template <typename T, int PD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_band_solve_wide(
+__global__ __launch_bounds__(128) void k_band_solve_wide(
     const DevProb *__restrict__ probs, const DevSub *__restrict__ subs,
     const int *__restrict__ order, const int *__restrict__ active,
     const double2 *__restrict__ v, const KState *__restrict__ ks, long long vstride,
     const cplx<T> *__restrict__ F, cplx<T> *__restrict__ ybuf, cplx<T> *__restrict__ xout) {
+    __shared__ cplx<T> pbuf[2][64];            // the last two blocks' pivots
     const DevSub S = subs[order[blockIdx.x]];
     if (active != nullptr && active[S.prob] == 0) return;
     const double2 *vs = ks != nullptr ? v + static_cast<long long>(ks[S.prob].kp) * vstride : v;
     switch (S.W >> 6) {
-        case 3: solve_wide<T, 3, PD>(probs, S, vs, F, ybuf, xout); break;
-        case 4: solve_wide<T, 4, PD>(probs, S, vs, F, ybuf, xout); break;
-        case 5: solve_wide<T, 5, PD>(probs, S, vs, F, ybuf, xout); break;
-        case 6: solve_wide<T, 6, PD>(probs, S, vs, F, ybuf, xout); break;
-        default: solve_wide<T, 7, PD>(probs, S, vs, F, ybuf, xout); break;
+        case 3: solve_wide<T, 3, PD>(probs, S, vs, F, ybuf, xout, pbuf); break;
+        case 4: solve_wide<T, 4, PD>(probs, S, vs, F, ybuf, xout, pbuf); break;
+        case 5: solve_wide<T, 5, PD>(probs, S, vs, F, ybuf, xout, pbuf); break;
+        case 6: solve_wide<T, 6, PD>(probs, S, vs, F, ybuf, xout, pbuf); break;
+        default: solve_wide<T, 7, PD>(probs, S, vs, F, ybuf, xout, pbuf); break;
     }
 }
 
@@ -558,18 +578,18 @@ void launch_solve_cfg(const DevProb *probs, const DevSub *subs, const int *order
 // dispatch of one wave per subdomain, or a persistent grid of dsp.waves
 // waves taking subdomains from the counter dsp.queue (two words, zero
 // between launches) when fewer waves than subdomains are asked for.
-// The wide subdomains order[0 .. nsub) (W = 192, 256, 320, 384 or 448), one
-// wave each; prefetch 16 vectors in complex64, 8 in complex128.
+// The wide subdomains order[0 .. nsub) (W = 192, 256, 320, 384 or 448), two
+// waves each; prefetch 16 vectors in complex64, 8 in complex128.
 void launch_band_solve_wide(bool fp64, const DevProb *probs, const DevSub *subs, const int *order,
                             int nsub, const int *active, const SolveSrc &src, const void *F,
                             void *ybuf, void *xout, hipStream_t st) {
     if (fp64)
-        hipLaunchKernelGGL((k_band_solve_wide<double, 8>), dim3(nsub), dim3(64), 0, st, probs, subs,
+        hipLaunchKernelGGL((k_band_solve_wide<double, 8>), dim3(nsub), dim3(128), 0, st, probs, subs,
                            order, active, src.v, src.ks, src.stride,
                            static_cast<const cplx<double> *>(F), static_cast<cplx<double> *>(ybuf),
                            static_cast<cplx<double> *>(xout));
     else
-        hipLaunchKernelGGL((k_band_solve_wide<float, 16>), dim3(nsub), dim3(64), 0, st, probs, subs,
+        hipLaunchKernelGGL((k_band_solve_wide<float, 16>), dim3(nsub), dim3(128), 0, st, probs, subs,
                            order, active, src.v, src.ks, src.stride,
                            static_cast<const cplx<float> *>(F), static_cast<cplx<float> *>(ybuf),
                            static_cast<cplx<float> *>(xout));
