@@ -493,7 +493,7 @@ int build(ras_pml_handle *H, hipStream_t st) {
         H->lu_order = H->order;
         // window classes of the register kernel, widest first; then the wide
         // subdomains by W
-        auto tiles = [&](int j) { return wide(j) ? -H->hsubs[j].W : ldlt_mfma_tiles(H->hsubs[j].W); };
+        auto tiles = [&](int j) { return ldlt_mfma_tiles(H->hsubs[j].W); };
         std::stable_sort(H->lu_order.begin(), H->lu_order.begin() + H->nsub_reg,
                          [&](int a, int b) { return tiles(a) > tiles(b); });
         std::stable_sort(H->lu_order.begin() + H->nsub_reg, H->lu_order.end(),
