@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 import paper_2602_00735_amd as rp
 from paper_2602_00735_amd import inputs
 from oracle import fem, gmres, ras, richardson
-from oracle.geometry import Problem
+from oracle.geometry import BC_DRCH, Problem
 
 WIDE = {
     # four subdomains of 137 x 137 unknowns: W = 192 (three 64-slot registers)
@@ -26,6 +26,9 @@ WIDE = {
     # eight subdomains with W = 118 (register-ring kernels) beside the middle
     # one with W = 192 (wide kernels), in one handle
     "mixed_wide": Problem(k=60.0, n_int=288, G=6, Px=3, Py=3, delta=8, kappa=8, sigma=600.0),
+    # RAS-PML-Drch: Dirichlet instead of impedance on the subdomain boundaries
+    "wide_drch": Problem(k=30.0, n_int=230, G=6, Px=2, Py=2, delta=8, kappa=8, sigma=300.0,
+                         bc=BC_DRCH),
 }
 _oracles = {}
 
