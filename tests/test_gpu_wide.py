@@ -215,19 +215,21 @@ def test_wide_single_subdomain_is_the_direct_solve(n_int, precision):
         assert it <= 4
 
 
-@pytest.mark.parametrize("solver", ["richardson", "gmres"])
-def test_table4_covering_at_k300(solver):
+@pytest.mark.parametrize("solver,precision", [("richardson", rp.RAS_MIXED),
+                                              ("gmres", rp.RAS_MIXED),
+                                              ("richardson", rp.RAS_FP64)])
+def test_table4_covering_at_k300(solver, precision):
     """Section 4's own covering at k = 300: grid 600^2, 2 x 2 subdomains with
     300-cell cores, overlap 4 and PML 12 cells (the width rule), a global PML
     of three wavelengths, the smoothed point source, rtol 1e-10 (Table 4
-    reports 7 Richardson steps).  Mixed precision through the wide kernels
-    (W = 384), checked by the true residual under the oracle's assembled
-    operator (its band LU of four 124k-unknown subdomains would take
-    minutes)."""
+    reports 7 Richardson steps).  Through the wide kernels (W = 384), in
+    mixed precision and in FP64, checked by the true residual under the
+    oracle's assembled operator (its band LU of four 124k-unknown subdomains
+    would take minutes)."""
     pb = Problem(k=300.0, n_int=600, G=37, Px=2, Py=2, delta=4, kappa=12, sigma=3000.0)
     A, M1 = fem.assemble_global(pb)
     b = fem.rhs(M1, inputs.paper(pb.k, pb.n_int, pb.G))
-    H = setup_gpu(pb, rp.RAS_MIXED)
+    H = setup_gpu(pb, precision)
     assert all(d[2] == 384 for d in H.desc())
     x = torch.zeros(pb.ndof, dtype=torch.complex128, device="cuda")
     if solver == "richardson":
