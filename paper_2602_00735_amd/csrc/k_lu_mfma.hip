@@ -51,6 +51,10 @@ struct Prec<float> {
     static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    // c + (-a) b
+    static __device__ __forceinline__ v4 mfma_na(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
+    }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ int row0(int lane) { return 4 * (lane >> 4); }
     static constexpr int rs = 1;
@@ -61,6 +65,11 @@ struct Prec<double> {
     typedef double v4 __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // c + (-a) b: the f64 instruction's own negation of A (its last operand
+    // is the neg:[a, b, c] modifier), no vector instruction for the sign
+    static __device__ __forceinline__ v4 mfma_na(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
     }
     // v_rcp_f64 and two Newton steps r <- r + r (1 - x r): within an ulp or
     // two of 1/x (the division's scaling and fix-up steps, which make it
@@ -365,10 +374,10 @@ k_band_ldlt_mfma(const DevSub *__restrict__ subs, const int *__restrict__ order,
                         const int col = 4 * kk + (lane >> 4);
                         const cplx<T> l = LP[(16 * I + tj) * kLdsStride + col];
                         const cplx<T> w = WB[(16 * J + tj) * kLdsStride + col];
-                        cre[s] = Prec<T>::mfma(-l.re, w.re, cre[s]);
+                        cre[s] = Prec<T>::mfma_na(l.re, w.re, cre[s]);
                         cre[s] = Prec<T>::mfma(l.im, w.im, cre[s]);
-                        cim[s] = Prec<T>::mfma(-l.re, w.im, cim[s]);
-                        cim[s] = Prec<T>::mfma(-l.im, w.re, cim[s]);
+                        cim[s] = Prec<T>::mfma_na(l.re, w.im, cim[s]);
+                        cim[s] = Prec<T>::mfma_na(l.im, w.re, cim[s]);
                     }
                 } else {
                     // next window: row NT - 1, column NT - 1 - d, from the
@@ -665,10 +674,10 @@ __global__ __launch_bounds__(wide_threads<T>()) void k_band_ldlt_wide(
                 for (int h = 0; h < 2; ++h) {
                     const cplx<T> l = LP[(16 * I[h] + tj) * kLdsStride + col];
                     const cplx<T> w = cmul(LP[(16 * J[h] + tj) * kLdsStride + col], dv);
-                    cre[h] = Prec<T>::mfma(-l.re, w.re, cre[h]);
-                    cim[h] = Prec<T>::mfma(-l.re, w.im, cim[h]);
+                    cre[h] = Prec<T>::mfma_na(l.re, w.re, cre[h]);
+                    cim[h] = Prec<T>::mfma_na(l.re, w.im, cim[h]);
                     cre[h] = Prec<T>::mfma(l.im, w.im, cre[h]);
-                    cim[h] = Prec<T>::mfma(-l.im, w.re, cim[h]);
+                    cim[h] = Prec<T>::mfma_na(l.im, w.re, cim[h]);
                 }
             }
 #pragma unroll
