@@ -164,7 +164,8 @@ constexpr int panel_waves() { return M <= 64 ? 1 : 1 + (M - 64 + 47) / 48; }
 // which is what the later panel columns need (the values of rows j < 16,
 // broadcast with v_readlane) and what is stored in WB; L goes to LP, except
 // for the first 16 rows, whose L goes to LT (every part reads those rows of
-// LP first).  Zero on and above the diagonal.  dg: lane k < 16 holds
+// LP first).  Entries on and above the diagonal are not zeroed: no reader
+// uses them.  dg: lane k < 16 holds
 // |A_j(c0 + k, c0 + k)| for the pivot test.  The reciprocal of the pivot is
 // Prec<T>::rcp of |d|^2.
 template <typename T, int M>
@@ -196,9 +197,10 @@ __device__ __forceinline__ int factor_panel(cplx<T> *LP, cplx<T> *LT, cplx<T> *W
         const cplx<T> l = cmul(w, inv);
 #pragma unroll
         for (int j = k + 1; j < 16; ++j) x[j] = cfms(x[j], l, readlane(w, j));
-        const bool below = row > k;
-        dl[k] = csel(below, l, zero);
-        dw[k] = csel(below, w, zero);
+        // (rows k and above hold values no reader uses: the column and row
+        // copies read L strictly below the diagonal, the update rows >= 16)
+        dl[k] = l;
+        dw[k] = w;
     }
     if (part == 0 && lane < 16) Dinv[c0 + lane] = dinv;
     const T ad = sqrt(pa);
