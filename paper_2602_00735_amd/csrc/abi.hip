@@ -676,7 +676,7 @@ int plan_arnoldi(ras_pml_handle *H) {
         H->arn_nblocks = static_cast<int>(tab.size());
         RCHK(dalloc(H, &H->d_ablocks, sizeof(ArnoldiBlock) * tab.size()));
         RCHK(dalloc(H, &H->d_part2, sizeof(double2) * 2 * tab.size()));
-        const size_t bar_words = 32 * (tab.size() / 16 + 2);
+        const size_t bar_words = 32 * (tab.size() / 16 + 2);   // covers groups of 16 or more
         H->bar_words = bar_words;
         RCHK(dalloc(H, &H->d_bar, sizeof(unsigned long long) * bar_words));
         RCHK(dalloc(H, &H->d_epoch, sizeof(unsigned long long)));

@@ -348,7 +348,7 @@ __global__ void k_rich_update(RState *__restrict__ rs, int *__restrict__ active,
 
 // Barrier words, each on its own 256-byte line: [0] top arrivals,
 // [32 (g+1)] arrivals of group g, [32 (g+1) + 16] release epoch of group g.
-constexpr int kBarGroup = 16;           // blocks per group
+constexpr int kBarGroup = 32;           // blocks per group (13 groups of the 416 at k = 640)
 constexpr int kBarStride = 32;          // unsigned long long per line
 
 // Grid-wide barrier for a cooperative launch (every block co-resident).
